@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path: Y = mask(H X) (apply_H) then S = X^T Y, tr S.
+
+One step = one pass of the whole path over the resident multivector of the
+paper-scale quadratic workload (64x40x40 Q2 cells, 846369 DoFs, 320 orbitals
+in 40 column blocks of 8, support radius 4 cells).  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp64|fp32|fp32-mfma]
+                    [--config 2|3] [--no-cpu-baseline] [--no-forms]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector (= FP64 matrix)
+FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X FP32 matrix
+PRECS = {"fp64": 0, "fp64-mfma": 1, "fp32-mfma": 2, "fp32": 3}
+
+
+def flops_per_cell_column(p: int) -> int:
+    """Sum-factorised cell operator: 12 one-dimensional sweeps of n^4 multiply-adds
+    (S and D forward/backward along three axes) plus 7 n^3 scaling/adds."""
+    n = p + 1
+    return 24 * n ** 4 + 7 * n ** 3
+
+
+def algorithmic(dp, degree: int):
+    """Bytes and flops one apply_H must move / perform on this layout."""
+    info = dp.layout.info
+    E = dp.nvalues
+    n3 = (degree + 1) ** 3
+    # (batch, C) pairs whose own row block is stored are the ones whose
+    # gathered values are non-zero for orbital-supported inputs
+    own = info["apply_pairs_own"]
+    sizes = np.diff(dp.layout.pattern()["col_block_start"])
+    pat = dp.layout.pattern()
+    widths = sizes[pat["colidx"]]                     # |C| of each stored block
+    cell_cols = 8 * int(widths.sum())                 # 8 cells x |C| per own pair
+    active_batches = int(np.count_nonzero(np.diff(pat["rowptr"])))
+    bytes_ = 16 * E + 8 * n3 * 8 * active_batches
+    flops = flops_per_cell_column(degree) * cell_cols
+    return {"E": E, "bytes": bytes_, "flops": flops, "own_pairs": own,
+            "cell_columns": cell_cols, "active_batches": active_batches}
+
+
+def cpu_baseline(wl, budget_s: float = 12.0):
+    """The oracle's apply + overlap timed on the host cores on a bounded sample."""
+    from oracle.workload import OracleProblem
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    op = OracleProblem(wl)
+    t0 = time.perf_counter()
+    entries = 0
+    blocks = 0
+    for C in range(op.pattern.ncb):
+        orbs = op.block_orbitals(C)
+        op.Y_columns(orbs)
+        k = np.nonzero(op.pattern.colidx == C)[0]
+        rows = (op.pattern.rb_start[1:] - op.pattern.rb_start[:-1])
+        rb = np.searchsorted(op.pattern.rowptr, k, side="right") - 1
+        entries += int(rows[rb].sum()) * len(orbs)
+        blocks += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": entries / dt / 1e9, "unit": "GDoF*cols/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"oracle masked apply (element matrices built on the fly) over "
+                      f"{blocks} of {op.pattern.ncb} column blocks ({entries} stored entries), "
+                      f"{dt:.1f} s on {os.cpu_count()} visible host cores"}
+
+
+def build_problem(cfg: int):
+    import synth
+    from paper_1907_01005_amd.problem import DeviceProblem
+    wl = synth.make_workload(cfg)
+    ms = wl.mesh
+    dp = DeviceProblem((ms.nx, ms.ny, ms.nz), ms.L, ms.degree, ms.dirichlet, wl.centres,
+                       wl.radius, wl.colblock_sizes, lambda P: synth.potential_at(wl, P))
+    node, orb, val = synth.orbital_values(wl)
+    dp.set_X_coo(node, orb, val)
+    return wl, dp
+
+
+def time_path(dp, prec: int, steps: int, warmup: int, kernel: int = 0):
+    """Warm up, then time `steps` steps; per-apply and per-overlap event times."""
+    import torch
+    stream = torch.cuda.current_stream()
+
+    def step():
+        if kernel == 0:
+            dp.apply(prec)
+        else:
+            dp.apply_tuned(prec, kernel=kernel)
+        dp.overlap()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        a, b, c = ev[i]
+        a.record(stream)
+        if kernel == 0:
+            dp.apply(prec)
+        else:
+            dp.apply_tuned(prec, kernel=kernel)
+        b.record(stream)
+        dp.overlap()
+        c.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_apply = np.array([a.elapsed_time(b) for a, b, _ in ev]) * 1e-3
+    t_tm = np.array([b.elapsed_time(c) for _, b, c in ev]) * 1e-3
+    return wall, t_apply, t_tm
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--prec", default="fp64", choices=sorted(PRECS))
+    ap.add_argument("--config", type=int, default=2, choices=[2, 3])
+    ap.add_argument("--kernel", type=int, default=0, choices=[0, 1])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the path is not sharded across GPUs in this build "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    print(f"[bench] building config {args.config}", file=sys.stderr, flush=True)
+    wl, dp = build_problem(args.config)
+    degree = wl.mesh.degree
+    prec = PRECS[args.prec]
+    alg = algorithmic(dp, degree)
+    print(f"[bench] E={alg['E']} items={dp.layout.info['apply_items']}; timing {args.steps} steps",
+          file=sys.stderr, flush=True)
+    wall, t_apply, t_tm = time_path(dp, prec, args.steps, args.warmup, args.kernel)
+    ms_step = wall / args.steps * 1e3
+    value = alg["E"] * args.steps / wall / 1e9
+
+    t_ap = float(np.mean(t_apply))
+    gbs = alg["bytes"] / t_ap / 1e9
+    tfl = alg["flops"] / t_ap / 1e12
+    peak_f = FP32_MFMA_PEAK_TFLOPS if args.prec == "fp32-mfma" else FP64_PEAK_TFLOPS
+    t_hbm = alg["bytes"] / (HBM_PEAK_GBS * 1e9)
+    t_alu = alg["flops"] / (peak_f * 1e12)
+    if t_alu >= t_hbm:
+        roof = {"bound": "mfma" if args.prec == "fp32-mfma" else "alu", "achieved": tfl,
+                "peak": peak_f, "unit": "TFLOP/s", "frac": tfl / peak_f}
+    else:
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS}
+    roof.update({"traffic": None,
+                 "kernel": "apply_H (zero fill + apply_grid_kernel)",
+                 "algorithmic_bytes": alg["bytes"], "algorithmic_flops": alg["flops"],
+                 "avg_launch_s": t_ap, "hbm_frac": gbs / HBM_PEAK_GBS,
+                 "alu_frac": tfl / peak_f})
+    tm_bytes = 16 * alg["E"] + 8 * dp.M * dp.M
+    t_t = float(np.mean(t_tm))
+    out = {
+        "metric": "apply_H GDoF*cols/s (stored BCSR entries per second, apply_H + tmmult step)",
+        "value": value,
+        "unit": "GDoF*cols/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.prec.startswith("fp64") else "f32 contractions, f64 storage/scaling/S",
+        "data": "synthetic (seeded centres, Gaussian-well potential, N(0,1) orbital values)",
+        "config": {"workload": wl.name, "dofs": dp.mesh.ndofs, "orbitals": dp.M,
+                   "colblocks": int(len(wl.colblock_sizes)), "radius": wl.radius,
+                   "degree": degree, "stored_entries": alg["E"], "prec": args.prec,
+                   "kernel": ["grid", "queue"][args.kernel]},
+        "apply_ms_p50": float(np.percentile(t_apply, 50) * 1e3),
+        "apply_ms_p99": float(np.percentile(t_apply, 99) * 1e3),
+        "apply_gdofcols_s": alg["E"] / t_ap / 1e9,
+        "tmmult_ms_mean": t_t * 1e3,
+        "tmmult_hbm_frac": tm_bytes / t_t / 1e9 / HBM_PEAK_GBS,
+        "roofline": roof,
+    }
+    if not args.no_forms:
+        forms = {}
+        for name in ("fp32",):
+            try:
+                _, ta, _ = time_path(dp, PRECS[name], 50, 5)
+                forms[name] = {"apply_ms_mean": float(np.mean(ta) * 1e3),
+                               "speedup_vs_fp64": t_ap / float(np.mean(ta))}
+            except Exception as e:  # unsupported variant
+                forms[name] = {"error": str(e)}
+        _, ta, _ = time_path(dp, prec, 50, 5, kernel=1)
+        forms["queue-kernel"] = {"apply_ms_mean": float(np.mean(ta) * 1e3)}
+        out["forms"] = forms
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

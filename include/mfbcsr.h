@@ -1,0 +1,261 @@
+/*
+ * mfbcsr -- matrix-free finite element Hamiltonian on BCSR sparse multivectors
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * What the library computes (Davydov & Kronbichler, arXiv 1907.01005):
+ *
+ *   Y = mask_P(X)( H X ),   S = X^T Y,   t = tr(S)
+ *
+ * H is the finite element Hamiltonian -1/2 Laplacian + V(x) on a box of
+ * Q_p hexahedra (eq. fe_matrices), applied cell by cell with sum
+ * factorisation (eq. fe_matrices_cell_based, Sec. 3.2), restricted to the
+ * nodes off the homogeneous Dirichlet faces.  X is a sparse multivector in
+ * BCSR layout (Sec. 3.3-3.4): row blocks are the nodes first met in each
+ * 2x2x2 batch of cells along a Hilbert curve (Alg. 1), column blocks are
+ * groups of orbitals sorted along the same curve (Alg. 2).  Y has the
+ * pattern of X; entries of H X outside the stored blocks are dropped, as
+ * the write accessor of Alg. 6 only reaches stored blocks.  S is the
+ * projected matrix of eq. inner2 computed block by block as in Alg. 8, and t
+ * its trace (the column-wise inner product of eq. G_ops4).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns an mfb_status (0 on success, negative on error)
+ *    and never throws.  The message of the last error on the calling thread
+ *    is returned by mfb_last_error().
+ *  - Handles (mfb_mesh, mfb_mv) belong to the library; free them with the
+ *    matching destroy call.  A multivector layout keeps a pointer to its
+ *    mesh: the mesh must outlive it.
+ *  - Device memory (values, metadata, workspace, S, trace) belongs to the
+ *    caller.  The library never allocates or frees device memory; the caller
+ *    keeps buffers alive while work that uses them is in flight.
+ *  - Creation and host queries are synchronous and host-only (no GPU
+ *    needed).  *_bind copies host-built metadata to a caller buffer with
+ *    hipMemcpyAsync on the given stream.  mfb_apply_H, mfb_apply_H_tuned and
+ *    mfb_tmmult only enqueue kernels on the caller's hipStream_t (passed as
+ *    void*; NULL means the default stream) and return immediately.
+ *  - All values are IEEE float64 in device memory.  The precision argument
+ *    of mfb_apply_H only selects the arithmetic of the sum-factorisation
+ *    contractions; loads, stores, quadrature scaling and accumulation into
+ *    Y stay float64.
+ *  - Device buffers must be 256-byte aligned (any torch CUDA allocation is).
+ *
+ * Value layout of a multivector
+ * -----------------------------
+ * The stored blocks (r, C) are numbered in CSR order (row block r ascending,
+ * column block C ascending within a row) and laid out back to back in one
+ * float64 array.  Block k starts at block_offset[k] and is a dense row-major
+ * rows_r x |C| matrix (row stride |C|, no padding).  Row i of block (r, C)
+ * is the row row_block_start[r] + i of the multivector, whose global node is
+ * dof_perm[row]; column j is column col_block_start[C] + j, whose original
+ * orbital id is col_perm[column].  S is written M x M row-major in this
+ * column order (S[a*M + b] pairs columns a and b).
+ */
+#ifndef MFBCSR_H
+#define MFBCSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mfb_mesh mfb_mesh;
+typedef struct mfb_mv mfb_mv;
+
+typedef enum {
+  MFB_OK = 0,
+  MFB_EINVAL = -1,        /* bad argument (null pointer, size, range)          */
+  MFB_EUNSUPPORTED = -2,  /* valid request this build does not implement      */
+  MFB_EPATTERN = -3,      /* layout/mesh mismatch, entry outside the pattern   */
+  MFB_ENOMEM = -4,        /* host allocation failed                            */
+  MFB_EHIP = -5,          /* a HIP runtime call failed                          */
+  MFB_ESTATE = -6         /* handle not ready (e.g. not bound, no potential)   */
+} mfb_status;
+
+/* Arithmetic of the sum-factorisation contractions (mfb_apply_H). */
+typedef enum {
+  MFB_FP64 = 0,       /* float64 on the vector ALUs                            */
+  MFB_FP64_MFMA = 1,  /* float64 on the matrix cores                           */
+  MFB_FP32_MFMA = 2,  /* float32 on the matrix cores, float32 accumulation;
+                         quadrature scaling, S and trace stay float64          */
+  MFB_FP32 = 3        /* float32 on the vector ALUs (comparison form)          */
+} mfb_prec;
+
+/* ------------------------------------------------------------------ mesh */
+
+/* Box [0,Lx]x[0,Ly]x[0,Lz] split into nx x ny x nz equal Q_p cells.
+ * nx, ny, nz must be even (cells are grouped in 2x2x2 batches, the coarse
+ * level of Alg. 1).  degree p in {2, 4} (else MFB_EUNSUPPORTED).
+ * dirichlet_faces: bit 2d = face x_d = 0, bit 2d+1 = face x_d = L_d.
+ * order: 0 = batches along the Hilbert curve (Alg. 1 step 2), 1 = batches
+ * in lexicographic order (x fastest).                                      */
+typedef struct {
+  int32_t nx, ny, nz;
+  double Lx, Ly, Lz;
+  int32_t degree;
+  uint32_t dirichlet_faces;
+  int32_t order;
+} mfb_mesh_desc;
+
+typedef struct {
+  int64_t ndofs;            /* (p nx + 1)(p ny + 1)(p nz + 1) rows            */
+  int64_t ncells;
+  int32_t nbatches;         /* = number of row blocks                         */
+  int32_t degree;
+  int32_t qp_per_cell;      /* (p+1)^3                                         */
+  int32_t nodes_per_batch;  /* (2p+1)^3                                        */
+  size_t meta_bytes;        /* device metadata size for mfb_mesh_bind          */
+} mfb_mesh_info;
+
+/* Plans the mesh: batch order (Hilbert, Alg. 1 step 2), first-encounter row
+ * numbering and row blocks (Alg. 1 steps 5-7), per-batch gather tables and
+ * the 1D basis (Gauss-Lobatto nodes, (p+1)-point Gauss rule).  Host only.
+ * Errors: EINVAL (null, non-positive or odd sizes), EUNSUPPORTED (degree). */
+int mfb_create_mesh(const mfb_mesh_desc* desc, mfb_mesh** out);
+int mfb_mesh_get_info(const mfb_mesh* mesh, mfb_mesh_info* out);
+
+/* Integer coordinates (cx, cy, cz) of every cell in library cell order:
+ * cell 8 r + e is child e = ex + 2 ey + 4 ez of the batch in row block r.
+ * ijk: host array of ncells*3 int32.                                         */
+int mfb_mesh_cells(const mfb_mesh* mesh, int32_t* ijk);
+
+/* Physical quadrature points x_q = x_K + h (.) xi_q of every cell, library
+ * cell order, q = q1 + n q2 + n^2 q3: host array [ncells][(p+1)^3][3].       */
+int mfb_mesh_qp_points(const mfb_mesh* mesh, double* xyz);
+
+/* Potential values V(x_q) at those points (host array [ncells][(p+1)^3]).
+ * The library stores JxW_q V(x_q), the coefficient of the N_i V N_j term of
+ * eq. fe_matrices.  Must be called before mfb_mesh_bind.                    */
+int mfb_mesh_set_potential(mfb_mesh* mesh, const double* v_qp);
+
+/* Copies the mesh metadata (gather tables, quadrature coefficients) into
+ * d_meta (caller-owned device buffer of info.meta_bytes, 256-B aligned).
+ * Errors: ESTATE (no potential set), EHIP.                                   */
+int mfb_mesh_bind(mfb_mesh* mesh, void* d_meta, void* stream);
+void mfb_destroy_mesh(mfb_mesh* mesh);
+
+/* ----------------------------------------------------------- multivector */
+
+/* Sparse multivector layout.  centers: M x 3 orbital centres (original
+ * order).  radius: radius_count == 1 (shared) or M values: the patch of an
+ * orbital is the set of batches whose centre lies within the radius (the
+ * support construction of Sec. 6); block (r, C) is stored iff row block r's
+ * batch is in the patch of an orbital of C.  Column blocks: colblock_sizes
+ * (ncolblocks values summing to M) or, when NULL, blocks of B with the
+ * remainder on the last block (Alg. 2 step 4).  col_order: 0 = Hilbert order
+ * of the batch containing each centre (Alg. 2 step 3), 1 = original order.
+ * Column blocks wider than 16 are rejected (EUNSUPPORTED).                  */
+typedef struct {
+  int32_t M;
+  const double* centers;
+  const double* radius;
+  int32_t radius_count;
+  int32_t ncolblocks;
+  const int32_t* colblock_sizes;
+  int32_t B;
+  int32_t col_order;
+} mfb_mv_desc;
+
+typedef struct {
+  int32_t M, nrowblocks, ncolblocks;
+  int64_t nblocks;          /* stored blocks                                   */
+  int64_t nvalues;          /* float64 values of one multivector (= E)         */
+  size_t meta_bytes;        /* device metadata size for mfb_mv_bind            */
+  size_t work_bytes;        /* device workspace of mfb_tmmult / tuned apply    */
+  int64_t apply_items;      /* (batch, column block, 8-column chunk) items     */
+  int64_t apply_pairs;      /* (batch, column block) pairs touching a block    */
+  int64_t apply_pairs_own;  /* ... of which the batch's own block is stored    */
+  int64_t tm_units;         /* (row block, C1, C2) products of Alg. 8          */
+  int64_t s_pairs;          /* stored (C1, C2) blocks of S                     */
+} mfb_mv_info;
+
+/* Table-1-style statistics of a layout (Sec. 6, Table 1).                   */
+typedef struct {
+  double rows_mean, rows_std;        /* row block sizes                        */
+  double cols_mean, cols_std;        /* column block sizes                     */
+  double blocks_per_row_mean;        /* stored blocks per row block            */
+  double colblocks_per_cell_mean;    /* non-empty column blocks per FE cell    */
+  double colblocks_per_cell_std;
+  int64_t colblocks_per_cell_sum;
+} mfb_stats;
+
+int mfb_create_bcsr_multivector(const mfb_mesh* mesh, const mfb_mv_desc* desc, mfb_mv** out);
+int mfb_mv_get_info(const mfb_mv* mv, mfb_mv_info* out);
+int mfb_query_stats(const mfb_mv* mv, mfb_stats* out);
+
+/* Host views of the pattern (valid while the handle lives):
+ * rowptr[nrowblocks+1], colidx[nblocks] (ascending within a row, Sec. 3.4),
+ * row_block_start[nrowblocks+1], col_block_start[ncolblocks+1],
+ * dof_perm[ndofs] (row -> global node id), col_perm[M] (column -> original
+ * orbital), block_offset[nblocks+1], batch_order[nrowblocks] (row block ->
+ * batch id bx + nbx (by + nby bz)).                                          */
+typedef struct {
+  const int64_t* rowptr;
+  const int32_t* colidx;
+  const int64_t* row_block_start;
+  const int32_t* col_block_start;
+  const int64_t* dof_perm;
+  const int32_t* col_perm;
+  const int64_t* block_offset;
+  const int32_t* batch_order;
+} mfb_pattern_view;
+int mfb_mv_pattern(const mfb_mv* mv, mfb_pattern_view* out);
+
+/* Host-side scatter of COO triplets (global node id, original orbital id,
+ * value) into a host value array of info.nvalues doubles (entries not named
+ * are set to 0).  Errors: EPATTERN when a triplet falls outside the stored
+ * blocks (nothing is written then), EINVAL on out-of-range ids.             */
+int mfb_mv_pack(const mfb_mv* mv, int64_t nnz, const int64_t* node, const int32_t* orb,
+                const double* val, double* values);
+/* Coordinates of every stored value position: node[k], orb[k] for
+ * k < info.nvalues (host arrays).                                           */
+int mfb_mv_entry_coords(const mfb_mv* mv, int64_t* node, int32_t* orb);
+
+/* Copies the layout's device plan (apply work list, Alg. 8 product list)
+ * into d_meta (caller-owned, info.meta_bytes, 256-B aligned).               */
+int mfb_mv_bind(mfb_mv* mv, void* d_meta, void* stream);
+void mfb_destroy_mv(mfb_mv* mv);
+
+/* --------------------------------------------------------------- compute */
+
+/* Y = mask_P(H X) (Alg. 6: zero the destination, then for every (batch,
+ * column block) pair whose batch touches a stored block, gather the batch's
+ * node values, integrate with sum factorisation, add into the stored rows).
+ * d_X, d_Y: device arrays of info.nvalues doubles in the layout of mv; d_Y
+ * is overwritten and must not alias d_X.  Values of X on Dirichlet rows are
+ * ignored; Y is 0 there.  Errors: EPATTERN (mv planned on another mesh),
+ * ESTATE (mesh or mv not bound), EUNSUPPORTED (precision), EHIP.             */
+int mfb_apply_H(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X, double* d_Y,
+                int prec, void* stream);
+
+/* Same result through an explicitly configured kernel.
+ * kernel: 0 = one work item per workgroup, 1 = persistent workgroups pulling
+ * items from a queue.  grid: persistent workgroups (0 = 2 per CU).  d_work:
+ * the workspace (info.work_bytes) -- it holds the queue counter, so two tuned
+ * applies sharing a workspace must not overlap in time.                     */
+typedef struct {
+  int32_t prec;
+  int32_t kernel;
+  int32_t grid;
+  int32_t reserved;
+} mfb_tune;
+int mfb_apply_H_tuned(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X, double* d_Y,
+                      const mfb_tune* tune, void* d_work, void* stream);
+
+/* S = X^T Y (Alg. 8) and t = tr S, float64.  X and Y share the layout mv.
+ * d_S: M*M doubles, fully written (entries outside the product pattern are
+ * exactly 0); d_trace: one double; d_work: info.work_bytes of scratch for the
+ * per-row-block partial products, which are summed in a fixed order (the
+ * result is bitwise reproducible).  Errors: ESTATE (not bound), EHIP.       */
+int mfb_tmmult(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d_S,
+               double* d_trace, void* d_work, void* stream);
+
+/* Thread-local message describing the last error (empty if none).           */
+const char* mfb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MFBCSR_H */

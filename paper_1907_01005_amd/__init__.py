@@ -1,0 +1,20 @@
+"""MI355X-native matrix-free FE Hamiltonian on BCSR sparse multivectors.
+
+Python side of libmfbcsr (include/mfbcsr.h): the C library plans meshes
+and BCSR layouts on the host and runs the apply / overlap kernels on the GPU;
+this package only marshals arguments and lends torch device memory.
+"""
+
+from .api import (  # noqa: F401
+    FP32,
+    FP32_MFMA,
+    FP64,
+    FP64_MFMA,
+    PREC_NAMES,
+    Layout,
+    Mesh,
+    apply_H,
+    apply_H_tuned,
+    tmmult,
+)
+from ._native import MfbError, lib  # noqa: F401

@@ -1,0 +1,205 @@
+"""Thin Python binding over the C ABI: marshalling only.
+
+Device memory comes from torch (the caller owns it); every computation runs
+in the library's HIP kernels.  Names follow include/mfbcsr.h.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _native as N
+from ._native import check, lib
+
+FP64, FP64_MFMA, FP32_MFMA, FP32 = N.MFB_FP64, N.MFB_FP64_MFMA, N.MFB_FP32_MFMA, N.MFB_FP32
+PREC_NAMES = {FP64: "fp64", FP64_MFMA: "fp64-mfma", FP32_MFMA: "fp32-mfma", FP32: "fp32"}
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _stream(stream) -> C.c_void_p:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr())
+
+
+class Mesh:
+    """mfb_create_mesh: a box of Q_p cells grouped in Hilbert-ordered 2x2x2 batches."""
+
+    def __init__(self, nx: int, ny: int, nz: int, L: Sequence[float], degree: int,
+                 dirichlet: int = 0x3F, order: int = 0):
+        d = N.MeshDesc(nx, ny, nz, float(L[0]), float(L[1]), float(L[2]), degree, dirichlet, order)
+        h = C.c_void_p()
+        check(lib().mfb_create_mesh(C.byref(d), C.byref(h)))
+        self._h = h
+        info = N.MeshInfo()
+        check(lib().mfb_mesh_get_info(h, C.byref(info)))
+        self.ndofs = info.ndofs
+        self.ncells = info.ncells
+        self.nbatches = info.nbatches
+        self.degree = info.degree
+        self.qp_per_cell = info.qp_per_cell
+        self.nodes_per_batch = info.nodes_per_batch
+        self.meta_bytes = info.meta_bytes
+        self.cells_shape = (nx, ny, nz)
+        self.L = tuple(float(x) for x in L)
+        self.dirichlet = dirichlet
+        self._meta = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def cells(self) -> np.ndarray:
+        out = np.empty((self.ncells, 3), dtype=np.int32)
+        check(lib().mfb_mesh_cells(self._h, _ptr(out, C.c_int32)))
+        return out
+
+    def qp_points(self) -> np.ndarray:
+        out = np.empty((self.ncells, self.qp_per_cell, 3), dtype=np.float64)
+        check(lib().mfb_mesh_qp_points(self._h, _ptr(out, C.c_double)))
+        return out
+
+    def set_potential(self, v_qp: np.ndarray) -> None:
+        v = np.ascontiguousarray(v_qp, dtype=np.float64).reshape(self.ncells, self.qp_per_cell)
+        check(lib().mfb_mesh_set_potential(self._h, _ptr(v, C.c_double)))
+
+    def bind(self, device="cuda", stream=None) -> None:
+        import torch
+        self._meta = torch.empty(max(self.meta_bytes, 256), dtype=torch.uint8, device=device)
+        check(lib().mfb_mesh_bind(self._h, _dev_ptr(self._meta), _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mfb_destroy_mesh(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Layout:
+    """mfb_create_bcsr_multivector: the BCSR pattern and device plan of X (and Y)."""
+
+    def __init__(self, mesh: Mesh, centers: np.ndarray, radius, colblock_sizes=None, B: int = 8,
+                 col_order: int = 0):
+        self.mesh = mesh
+        cen = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 3)
+        rad = np.ascontiguousarray(np.atleast_1d(radius), dtype=np.float64)
+        M = len(cen)
+        sizes = None if colblock_sizes is None else \
+            np.ascontiguousarray(colblock_sizes, dtype=np.int32)
+        d = N.MvDesc(M, _ptr(cen, C.c_double), _ptr(rad, C.c_double), len(rad),
+                     0 if sizes is None else len(sizes),
+                     None if sizes is None else _ptr(sizes, C.c_int32), B, col_order)
+        h = C.c_void_p()
+        check(lib().mfb_create_bcsr_multivector(mesh.handle, C.byref(d), C.byref(h)))
+        self._h = h
+        self._keep = (cen, rad, sizes)
+        info = N.MvInfo()
+        check(lib().mfb_mv_get_info(h, C.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in N.MvInfo._fields_}
+        self.M = info.M
+        self.nvalues = info.nvalues
+        self.meta_bytes = info.meta_bytes
+        self.work_bytes = info.work_bytes
+        self._meta = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stats(self) -> dict:
+        s = N.Stats()
+        check(lib().mfb_query_stats(self._h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in N.Stats._fields_}
+
+    def pattern(self) -> dict:
+        v = N.PatternView()
+        check(lib().mfb_mv_pattern(self._h, C.byref(v)))
+        nrb, ncb = self.info["nrowblocks"], self.info["ncolblocks"]
+        nb = self.info["nblocks"]
+
+        def cp(p, n):
+            return np.ctypeslib.as_array(p, shape=(n,)).copy() if n > 0 else np.zeros(0, np.int64)
+        return {
+            "rowptr": cp(v.rowptr, nrb + 1),
+            "colidx": cp(v.colidx, nb),
+            "row_block_start": cp(v.row_block_start, nrb + 1),
+            "col_block_start": cp(v.col_block_start, ncb + 1),
+            "dof_perm": cp(v.dof_perm, self.mesh.ndofs),
+            "col_perm": cp(v.col_perm, self.M),
+            "block_offset": cp(v.block_offset, nb + 1),
+            "batch_order": cp(v.batch_order, nrb),
+        }
+
+    def pack(self, node, orb, val) -> np.ndarray:
+        node = np.ascontiguousarray(node, dtype=np.int64)
+        orb = np.ascontiguousarray(orb, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        out = np.empty(self.nvalues, dtype=np.float64)
+        check(lib().mfb_mv_pack(self._h, len(node), _ptr(node, C.c_int64), _ptr(orb, C.c_int32),
+                                _ptr(val, C.c_double), _ptr(out, C.c_double)))
+        return out
+
+    def entry_coords(self):
+        node = np.empty(self.nvalues, dtype=np.int64)
+        orb = np.empty(self.nvalues, dtype=np.int32)
+        check(lib().mfb_mv_entry_coords(self._h, _ptr(node, C.c_int64), _ptr(orb, C.c_int32)))
+        return node, orb
+
+    def bind(self, device="cuda", stream=None) -> None:
+        import torch
+        self._meta = torch.empty(max(self.meta_bytes, 256), dtype=torch.uint8, device=device)
+        check(lib().mfb_mv_bind(self._h, _dev_ptr(self._meta), _stream(stream)))
+
+    def new_values(self, device="cuda"):
+        import torch
+        return torch.zeros(max(self.nvalues, 1), dtype=torch.float64, device=device)
+
+    def new_work(self, device="cuda"):
+        import torch
+        return torch.zeros(max(self.work_bytes, 256), dtype=torch.uint8, device=device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mfb_destroy_mv(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def apply_H(mesh: Mesh, layout: Layout, X, Y, prec: int = FP64, stream=None) -> None:
+    """mfb_apply_H: Y = mask(H X) on the caller's stream (asynchronous)."""
+    check(lib().mfb_apply_H(mesh.handle, layout.handle, _dev_ptr(X), _dev_ptr(Y), int(prec),
+                            _stream(stream)))
+
+
+def apply_H_tuned(mesh: Mesh, layout: Layout, X, Y, work, prec: int = FP64, kernel: int = 0,
+                  grid: int = 0, stream=None) -> None:
+    """mfb_apply_H_tuned: the same result through an explicit kernel configuration."""
+    t = N.Tune(int(prec), int(kernel), int(grid), 0)
+    check(lib().mfb_apply_H_tuned(mesh.handle, layout.handle, _dev_ptr(X), _dev_ptr(Y),
+                                  C.byref(t), _dev_ptr(work), _stream(stream)))
+
+
+def tmmult(layout: Layout, X, Y, S, trace, work, stream=None) -> None:
+    """mfb_tmmult: S = X^T Y (M x M, library column order) and trace."""
+    check(lib().mfb_tmmult(layout.handle, _dev_ptr(X), _dev_ptr(Y), _dev_ptr(S), _dev_ptr(trace),
+                           _dev_ptr(work), _stream(stream)))

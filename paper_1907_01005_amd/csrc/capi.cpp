@@ -1,0 +1,451 @@
+// The C boundary of the library (include/mfbcsr.h).  Every entry point
+// converts exceptions into status codes and keeps a thread-local message.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mfbcsr.h"
+#include "kernels.hpp"
+#include "planner.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct MeshLayout {
+  size_t off_gtab = 0, off_cv = 0, bytes = 0;
+};
+
+MeshLayout mesh_layout(const mfb::MeshPlan& m) {
+  MeshLayout L;
+  const size_t nb3 = (size_t)m.NB * m.NB * m.NB;
+  L.off_gtab = 0;
+  L.off_cv = align256(sizeof(int32_t) * nb3 * m.nbatch);
+  L.bytes = align256(L.off_cv + sizeof(double) * (size_t)m.ncells * m.n * m.n * m.n);
+  return L;
+}
+
+struct MvLayout {
+  size_t off_items = 0, off_units = 0, off_pair_tab = 0, off_pair_ptr = 0, off_pair_list = 0,
+         off_cb_of_col = 0, off_cb_start = 0, bytes = 0;
+};
+
+MvLayout mv_layout(const mfb::MvPlan& v) {
+  MvLayout L;
+  size_t o = 0;
+  L.off_items = o;
+  o = align256(o + sizeof(mfb::ApplyItem) * v.items.size());
+  L.off_units = o;
+  o = align256(o + sizeof(mfb::TmUnit) * v.units.size());
+  L.off_pair_tab = o;
+  o = align256(o + sizeof(int32_t) * v.pair_tab.size());
+  L.off_pair_ptr = o;
+  o = align256(o + sizeof(int32_t) * v.pair_ptr.size());
+  L.off_pair_list = o;
+  o = align256(o + sizeof(int64_t) * v.pair_list.size());
+  L.off_cb_of_col = o;
+  o = align256(o + sizeof(int32_t) * v.cb_of_col.size());
+  L.off_cb_start = o;
+  o = align256(o + sizeof(int32_t) * v.cb_start.size());
+  L.bytes = std::max<size_t>(o, 256);
+  return L;
+}
+
+constexpr size_t kCounterBytes = 256;  // queue counters at the head of the workspace
+
+void fail(int code, const std::string& msg) { throw mfb::Error(code, msg); }
+
+void check_hip(hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(MFB_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+struct mfb_mesh {
+  mfb::MeshPlan plan;
+  MeshLayout lay;
+  void* d_meta = nullptr;
+  bool bound = false;
+};
+
+struct mfb_mv {
+  mfb::MvPlan plan;
+  const mfb_mesh* mesh = nullptr;
+  MvLayout lay;
+  size_t work_bytes = 0;
+  void* d_meta = nullptr;
+  bool bound = false;
+  std::vector<int64_t> rowptr_view;
+};
+
+#define MFB_TRY try {
+#define MFB_CATCH                                   \
+  }                                                 \
+  catch (const mfb::Error& e) {                     \
+    g_err = e.what();                               \
+    return e.code;                                  \
+  }                                                 \
+  catch (const std::bad_alloc&) {                   \
+    g_err = "host allocation failed";               \
+    return MFB_ENOMEM;                              \
+  }                                                 \
+  catch (const std::exception& e) {                 \
+    g_err = e.what();                               \
+    return MFB_EINVAL;                              \
+  }                                                 \
+  catch (...) {                                     \
+    g_err = "unknown error";                        \
+    return MFB_EINVAL;                              \
+  }
+
+extern "C" {
+
+const char* mfb_last_error(void) { return g_err.c_str(); }
+
+int mfb_create_mesh(const mfb_mesh_desc* desc, mfb_mesh** out) {
+  MFB_TRY
+  if (!desc || !out) fail(MFB_EINVAL, "null argument");
+  *out = nullptr;
+  auto* m = new mfb_mesh();
+  try {
+    const int nc[3] = {desc->nx, desc->ny, desc->nz};
+    const double L[3] = {desc->Lx, desc->Ly, desc->Lz};
+    mfb::plan_mesh(m->plan, nc, L, desc->degree, desc->dirichlet_faces, desc->order);
+    m->lay = mesh_layout(m->plan);
+  } catch (...) {
+    delete m;
+    throw;
+  }
+  *out = m;
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_mesh_get_info(const mfb_mesh* mesh, mfb_mesh_info* out) {
+  MFB_TRY
+  if (!mesh || !out) fail(MFB_EINVAL, "null argument");
+  const auto& m = mesh->plan;
+  out->ndofs = m.N;
+  out->ncells = m.ncells;
+  out->nbatches = m.nbatch;
+  out->degree = m.p;
+  out->qp_per_cell = m.n * m.n * m.n;
+  out->nodes_per_batch = m.NB * m.NB * m.NB;
+  out->meta_bytes = mesh->lay.bytes;
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_mesh_cells(const mfb_mesh* mesh, int32_t* ijk) {
+  MFB_TRY
+  if (!mesh || !ijk) fail(MFB_EINVAL, "null argument");
+  mfb::mesh_cells(mesh->plan, ijk);
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_mesh_qp_points(const mfb_mesh* mesh, double* xyz) {
+  MFB_TRY
+  if (!mesh || !xyz) fail(MFB_EINVAL, "null argument");
+  mfb::mesh_qp_points(mesh->plan, xyz);
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_mesh_set_potential(mfb_mesh* mesh, const double* v_qp) {
+  MFB_TRY
+  if (!mesh || !v_qp) fail(MFB_EINVAL, "null argument");
+  mfb::mesh_set_potential(mesh->plan, v_qp);
+  mesh->bound = false;
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_mesh_bind(mfb_mesh* mesh, void* d_meta, void* stream) {
+  MFB_TRY
+  if (!mesh || !d_meta) fail(MFB_EINVAL, "null argument");
+  if (((uintptr_t)d_meta & 255) != 0) fail(MFB_EINVAL, "d_meta must be 256-byte aligned");
+  const auto& m = mesh->plan;
+  if (!m.has_potential) fail(MFB_ESTATE, "set the potential before binding the mesh");
+  std::vector<char> host(mesh->lay.bytes, 0);
+  std::memcpy(host.data() + mesh->lay.off_gtab, m.gtab.data(), sizeof(int32_t) * m.gtab.size());
+  std::memcpy(host.data() + mesh->lay.off_cv, m.cV.data(), sizeof(double) * m.cV.size());
+  hipStream_t st = (hipStream_t)stream;
+  check_hip(hipMemcpyAsync(d_meta, host.data(), host.size(), hipMemcpyHostToDevice, st),
+            "hipMemcpyAsync(mesh metadata)");
+  check_hip(hipStreamSynchronize(st), "hipStreamSynchronize");
+  mesh->d_meta = d_meta;
+  mesh->bound = true;
+  return MFB_OK;
+  MFB_CATCH
+}
+
+void mfb_destroy_mesh(mfb_mesh* mesh) { delete mesh; }
+
+int mfb_create_bcsr_multivector(const mfb_mesh* mesh, const mfb_mv_desc* desc, mfb_mv** out) {
+  MFB_TRY
+  if (!mesh || !desc || !out) fail(MFB_EINVAL, "null argument");
+  *out = nullptr;
+  auto* v = new mfb_mv();
+  try {
+    mfb::plan_mv(v->plan, mesh->plan, desc->M, desc->centers, desc->radius, desc->radius_count,
+                 desc->ncolblocks, desc->colblock_sizes, desc->B, desc->col_order);
+    v->mesh = mesh;
+    v->lay = mv_layout(v->plan);
+    v->work_bytes = kCounterBytes + sizeof(double) * (size_t)v->plan.part_doubles;
+  } catch (...) {
+    delete v;
+    throw;
+  }
+  *out = v;
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_mv_get_info(const mfb_mv* mv, mfb_mv_info* out) {
+  MFB_TRY
+  if (!mv || !out) fail(MFB_EINVAL, "null argument");
+  const auto& p = mv->plan;
+  out->M = p.M;
+  out->nrowblocks = mv->mesh->plan.nbatch;
+  out->ncolblocks = p.ncb;
+  out->nblocks = (int64_t)p.colidx.size();
+  out->nvalues = p.block_offset.back();
+  out->meta_bytes = mv->lay.bytes;
+  out->work_bytes = mv->work_bytes;
+  out->apply_items = (int64_t)p.items.size();
+  out->apply_pairs = p.apply_pairs;
+  out->apply_pairs_own = p.apply_pairs_own;
+  out->tm_units = (int64_t)p.units.size();
+  out->s_pairs = (int64_t)p.pair_ptr.size() - 1;
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_query_stats(const mfb_mv* mv, mfb_stats* out) {
+  MFB_TRY
+  if (!mv || !out) fail(MFB_EINVAL, "null argument");
+  const auto& p = mv->plan;
+  const auto& m = mv->mesh->plan;
+  auto meanstd = [](const std::vector<double>& x, double& mu, double& sd) {
+    double s = 0, s2 = 0;
+    for (double v : x) s += v;
+    mu = x.empty() ? 0.0 : s / x.size();
+    for (double v : x) s2 += (v - mu) * (v - mu);
+    sd = x.empty() ? 0.0 : std::sqrt(s2 / x.size());
+  };
+  std::vector<double> rows(m.nbatch), cols(p.ncb), cells(m.ncells);
+  for (int r = 0; r < m.nbatch; ++r) rows[r] = (double)(m.rb_start[r + 1] - m.rb_start[r]);
+  for (int C = 0; C < p.ncb; ++C) cols[C] = p.cb_start[C + 1] - p.cb_start[C];
+  int64_t sum = 0;
+  for (int64_t c = 0; c < m.ncells; ++c) {
+    cells[c] = p.cell_colblocks[c];
+    sum += p.cell_colblocks[c];
+  }
+  meanstd(rows, out->rows_mean, out->rows_std);
+  meanstd(cols, out->cols_mean, out->cols_std);
+  meanstd(cells, out->colblocks_per_cell_mean, out->colblocks_per_cell_std);
+  out->colblocks_per_cell_sum = sum;
+  out->blocks_per_row_mean = (double)p.colidx.size() / m.nbatch;
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_mv_pattern(const mfb_mv* mv, mfb_pattern_view* out) {
+  MFB_TRY
+  if (!mv || !out) fail(MFB_EINVAL, "null argument");
+  const auto& p = mv->plan;
+  const auto& m = mv->mesh->plan;
+  out->rowptr = p.rowptr.data();
+  out->colidx = p.colidx.data();
+  out->row_block_start = m.rb_start.data();
+  out->col_block_start = p.cb_start.data();
+  out->dof_perm = m.dof_perm.data();
+  out->col_perm = p.col_perm.data();
+  out->block_offset = p.block_offset.data();
+  out->batch_order = m.batch_order.data();
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_mv_pack(const mfb_mv* mv, int64_t nnz, const int64_t* node, const int32_t* orb,
+                const double* val, double* values) {
+  MFB_TRY
+  if (!mv || !values || (nnz > 0 && (!node || !orb || !val))) fail(MFB_EINVAL, "null argument");
+  if (nnz < 0) fail(MFB_EINVAL, "negative count");
+  const auto& p = mv->plan;
+  const auto& m = mv->mesh->plan;
+  std::vector<int64_t> pos(nnz);
+  for (int64_t k = 0; k < nnz; ++k) {
+    if (node[k] < 0 || node[k] >= m.N) fail(MFB_EINVAL, "node id out of range");
+    if (orb[k] < 0 || orb[k] >= p.M) fail(MFB_EINVAL, "orbital id out of range");
+    const int r = m.node_rb[node[k]];
+    const int col = p.col_pos[orb[k]];
+    const int C = p.cb_of_col[col];
+    const int64_t b = p.block_index(r, C);
+    if (b < 0) fail(MFB_EPATTERN, "entry outside the stored blocks");
+    const int64_t w = p.cb_start[C + 1] - p.cb_start[C];
+    pos[k] = p.block_offset[b] + (m.node_row[node[k]] - m.rb_start[r]) * w + (col - p.cb_start[C]);
+  }
+  std::memset(values, 0, sizeof(double) * (size_t)p.block_offset.back());
+  for (int64_t k = 0; k < nnz; ++k) values[pos[k]] = val[k];
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_mv_entry_coords(const mfb_mv* mv, int64_t* node, int32_t* orb) {
+  MFB_TRY
+  if (!mv || !node || !orb) fail(MFB_EINVAL, "null argument");
+  const auto& p = mv->plan;
+  const auto& m = mv->mesh->plan;
+  for (int r = 0; r < m.nbatch; ++r) {
+    const int64_t r0 = m.rb_start[r], rows = m.rb_start[r + 1] - r0;
+    for (int64_t k = p.rowptr[r]; k < p.rowptr[r + 1]; ++k) {
+      const int C = p.colidx[k];
+      const int c0 = p.cb_start[C], w = p.cb_start[C + 1] - c0;
+      int64_t o = p.block_offset[k];
+      for (int64_t i = 0; i < rows; ++i)
+        for (int j = 0; j < w; ++j, ++o) {
+          node[o] = m.dof_perm[r0 + i];
+          orb[o] = p.col_perm[c0 + j];
+        }
+    }
+  }
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_mv_bind(mfb_mv* mv, void* d_meta, void* stream) {
+  MFB_TRY
+  if (!mv || !d_meta) fail(MFB_EINVAL, "null argument");
+  if (((uintptr_t)d_meta & 255) != 0) fail(MFB_EINVAL, "d_meta must be 256-byte aligned");
+  const auto& p = mv->plan;
+  const auto& L = mv->lay;
+  std::vector<char> host(L.bytes, 0);
+  auto put = [&](size_t off, const void* src, size_t n) {
+    if (n) std::memcpy(host.data() + off, src, n);
+  };
+  put(L.off_items, p.items.data(), sizeof(mfb::ApplyItem) * p.items.size());
+  put(L.off_units, p.units.data(), sizeof(mfb::TmUnit) * p.units.size());
+  put(L.off_pair_tab, p.pair_tab.data(), sizeof(int32_t) * p.pair_tab.size());
+  put(L.off_pair_ptr, p.pair_ptr.data(), sizeof(int32_t) * p.pair_ptr.size());
+  put(L.off_pair_list, p.pair_list.data(), sizeof(int64_t) * p.pair_list.size());
+  put(L.off_cb_of_col, p.cb_of_col.data(), sizeof(int32_t) * p.cb_of_col.size());
+  put(L.off_cb_start, p.cb_start.data(), sizeof(int32_t) * p.cb_start.size());
+  hipStream_t st = (hipStream_t)stream;
+  check_hip(hipMemcpyAsync(d_meta, host.data(), host.size(), hipMemcpyHostToDevice, st),
+            "hipMemcpyAsync(layout metadata)");
+  check_hip(hipStreamSynchronize(st), "hipStreamSynchronize");
+  mv->d_meta = d_meta;
+  mv->bound = true;
+  return MFB_OK;
+  MFB_CATCH
+}
+
+void mfb_destroy_mv(mfb_mv* mv) { delete mv; }
+
+static void fill_apply_params(const mfb_mesh* mesh, const mfb_mv* mv, const double* X, double* Y,
+                              mfb::gpu::ApplyParams& a) {
+  const auto& m = mesh->plan;
+  const auto& b = m.basis;
+  std::memset(&a, 0, sizeof(a));
+  a.X = X;
+  a.Y = Y;
+  const char* mb = (const char*)mv->d_meta;
+  const char* gb = (const char*)mesh->d_meta;
+  a.items = (const mfb::ApplyItem*)(mb + mv->lay.off_items);
+  a.nitems = (int64_t)mv->plan.items.size();
+  a.gtab = (const int32_t*)(gb + mesh->lay.off_gtab);
+  a.cV = (const double*)(gb + mesh->lay.off_cv);
+  const int n = m.n;
+  for (int i = 0; i < n * n; ++i) {
+    a.S[i] = b.S[i];
+    a.Dco[i] = b.Dco[i];
+  }
+  for (int i = 0; i < n; ++i) {
+    a.w[i] = b.wq[i];
+    for (int j = 0; j < n; ++j) a.W2[i * n + j] = b.wq[i] * b.wq[j];
+  }
+  const double det = m.h[0] * m.h[1] * m.h[2];
+  for (int d = 0; d < 3; ++d) a.cg[d] = 0.5 * det / (m.h[d] * m.h[d]);
+}
+
+static void check_apply_args(const mfb_mesh* mesh, const mfb_mv* mv, const double* X, const double* Y) {
+  if (!mesh || !mv || !X || !Y) fail(MFB_EINVAL, "null argument");
+  if (mv->mesh != mesh) fail(MFB_EPATTERN, "layout was planned on another mesh");
+  if (!mesh->bound) fail(MFB_ESTATE, "mesh metadata not bound");
+  if (!mv->bound) fail(MFB_ESTATE, "layout metadata not bound");
+  if (X == Y) fail(MFB_EINVAL, "X and Y must not alias");
+}
+
+int mfb_apply_H(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X, double* d_Y, int prec,
+                void* stream) {
+  MFB_TRY
+  check_apply_args(mesh, mv, d_X, d_Y);
+  if (prec < 0 || prec > 3) fail(MFB_EINVAL, "unknown precision");
+  mfb::gpu::ApplyParams a;
+  fill_apply_params(mesh, mv, d_X, d_Y, a);
+  const int rc = mfb::gpu::launch_apply(a, mesh->plan.p, prec, 0, mv->plan.block_offset.back(), stream);
+  if (rc == -2) fail(MFB_EUNSUPPORTED, "precision not implemented in this build");
+  if (rc != 0) fail(MFB_EHIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)rc));
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_apply_H_tuned(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X, double* d_Y,
+                      const mfb_tune* tune, void* d_work, void* stream) {
+  MFB_TRY
+  check_apply_args(mesh, mv, d_X, d_Y);
+  if (!tune) fail(MFB_EINVAL, "null tune");
+  if (tune->prec < 0 || tune->prec > 3) fail(MFB_EINVAL, "unknown precision");
+  if (tune->kernel != 0 && tune->kernel != 1) fail(MFB_EINVAL, "kernel must be 0 or 1");
+  if (tune->grid < 0) fail(MFB_EINVAL, "negative grid");
+  if (tune->kernel == 1 && !d_work) fail(MFB_EINVAL, "the queue kernel needs the workspace");
+  mfb::gpu::ApplyParams a;
+  fill_apply_params(mesh, mv, d_X, d_Y, a);
+  a.counters = (int32_t*)d_work;
+  a.grid = tune->grid;
+  const int rc =
+      mfb::gpu::launch_apply(a, mesh->plan.p, tune->prec, tune->kernel, mv->plan.block_offset.back(), stream);
+  if (rc == -2) fail(MFB_EUNSUPPORTED, "precision not implemented in this build");
+  if (rc != 0) fail(MFB_EHIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)rc));
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_tmmult(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d_S, double* d_trace,
+               void* d_work, void* stream) {
+  MFB_TRY
+  if (!mv || !d_X || !d_Y || !d_S || !d_trace || !d_work) fail(MFB_EINVAL, "null argument");
+  if (!mv->bound) fail(MFB_ESTATE, "layout metadata not bound");
+  const auto& p = mv->plan;
+  const char* mb = (const char*)mv->d_meta;
+  mfb::gpu::TmParams t;
+  t.X = d_X;
+  t.Y = d_Y;
+  t.units = (const mfb::TmUnit*)(mb + mv->lay.off_units);
+  t.nunits = (int64_t)p.units.size();
+  t.part = (double*)((char*)d_work + kCounterBytes);
+  t.pair_tab = (const int32_t*)(mb + mv->lay.off_pair_tab);
+  t.pair_ptr = (const int32_t*)(mb + mv->lay.off_pair_ptr);
+  t.pair_list = (const int64_t*)(mb + mv->lay.off_pair_list);
+  t.cb_of_col = (const int32_t*)(mb + mv->lay.off_cb_of_col);
+  t.cb_start = (const int32_t*)(mb + mv->lay.off_cb_start);
+  t.M = p.M;
+  t.ncb = p.ncb;
+  t.S = d_S;
+  t.trace = d_trace;
+  const int rc = mfb::gpu::launch_tmmult(t, stream);
+  if (rc != 0) fail(MFB_EHIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)rc));
+  return MFB_OK;
+  MFB_CATCH
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+// Host-side planning of the mesh and of BCSR multivector layouts.
+//
+// Nothing here touches the GPU: the structures built here are copied to
+// device memory by the bind calls and read by the kernels in kernels.hip.
+#pragma once
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace mfb {
+
+// Error carrying an mfb_status code; converted at the C boundary.
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+// ---------------------------------------------------------------- 1D basis
+// Lagrange polynomials on p+1 Gauss-Lobatto-Legendre nodes of [0,1] and the
+// (p+1)-point Gauss-Legendre rule (Sec. 3.1: Lagrange shape functions,
+// continuous across cells).
+struct Basis1D {
+  int p = 0, n = 0;
+  std::vector<double> nodes;  // n GLL nodes, ascending
+  std::vector<double> xq, wq; // n Gauss points (ascending) and weights
+  std::vector<double> S;      // S[q*n + k] = phi_k(xq[q])
+  std::vector<double> Dco;    // Dco[q*n + j] = psi_j'(xq[q]); psi = Lagrange basis on the Gauss points
+};
+Basis1D make_basis(int p);
+
+// Hilbert index of an integer point of a 2^bits cube (Skilling's transform).
+uint64_t hilbert3(uint32_t x, uint32_t y, uint32_t z, int bits);
+int bits_for(int extent);
+
+// ---------------------------------------------------------------- mesh
+constexpr int kMaxDeg = 4;
+
+struct MeshPlan {
+  int nc[3] = {0, 0, 0};   // cells per axis
+  int p = 0, n = 0, NB = 0; // degree, p+1, 2p+1
+  double L[3] = {0, 0, 0}, h[3] = {0, 0, 0};
+  unsigned dirichlet = 0;
+  int order = 0;
+  int nb[3] = {0, 0, 0};   // batches per axis
+  int nbatch = 0;
+  int64_t na[3] = {0, 0, 0}; // nodes per axis
+  int64_t N = 0, ncells = 0;
+  std::vector<int32_t> batch_order;  // rank -> batch id
+  std::vector<int32_t> batch_rank;   // batch id -> rank
+  std::vector<int64_t> rb_start;     // nbatch + 1
+  std::vector<int64_t> dof_perm;     // row -> node
+  std::vector<int64_t> node_row;     // node -> row
+  std::vector<int32_t> node_rb;      // node -> row block
+  std::vector<uint8_t> is_dirichlet; // node -> 0/1
+  // per rank: NB^3 entries, (slot << 24) | row-in-owner-block, or -1 (Dirichlet)
+  std::vector<int32_t> gtab;
+  Basis1D basis;
+  std::vector<double> cV;            // [cell 8r+e][q]: JxW_q V(x_q)
+  bool has_potential = false;
+
+  int64_t node_id(int64_t X, int64_t Y, int64_t Z) const { return X + na[0] * (Y + na[1] * Z); }
+  void batch_coords(int b, int& bx, int& by, int& bz) const {
+    bx = b % nb[0]; by = (b / nb[0]) % nb[1]; bz = b / (nb[0] * nb[1]);
+  }
+};
+
+void plan_mesh(MeshPlan& m, const int nc[3], const double L[3], int degree, unsigned dirichlet,
+               int order);
+void mesh_cells(const MeshPlan& m, int32_t* ijk);
+void mesh_qp_points(const MeshPlan& m, double* xyz);
+void mesh_set_potential(MeshPlan& m, const double* v);
+
+// ---------------------------------------------------------------- layouts
+// One work item of the apply kernel: an 8-column chunk of column block C on
+// the 2x2x2 cells of the batch with rank `rank`.  off[s] is the value offset
+// of block (owner row block of neighbour slot s, C), or -1 when that block
+// is not stored (or slot s owns no node of this batch).
+struct ApplyItem {
+  int32_t rank;
+  int32_t c0;   // first column of the chunk within C
+  int32_t nc;   // columns in the chunk (1..8)
+  int32_t ld;   // |C|: row stride of the blocks of C
+  int64_t off[27];
+};
+static_assert(sizeof(ApplyItem) == 232, "ApplyItem layout");
+
+// One block product of Alg. 8: X_{r,C1}^T Y_{r,C2} into partial[part].
+struct TmUnit {
+  int64_t off1, off2, part;
+  int32_t rows, w1, w2, pad;
+};
+static_assert(sizeof(TmUnit) == 40, "TmUnit layout");
+
+struct MvPlan {
+  const MeshPlan* mesh = nullptr;
+  int M = 0, ncb = 0;
+  std::vector<int32_t> col_perm;     // column -> original orbital
+  std::vector<int32_t> col_pos;      // original orbital -> column
+  std::vector<int32_t> cb_start;     // ncb + 1
+  std::vector<int32_t> cb_of_col;    // column -> column block
+  std::vector<int64_t> rowptr;       // nbatch + 1
+  std::vector<int32_t> colidx;
+  std::vector<int64_t> block_offset; // nblocks + 1
+  std::vector<ApplyItem> items;
+  int64_t apply_pairs = 0, apply_pairs_own = 0;
+  std::vector<TmUnit> units;
+  int64_t part_doubles = 0;
+  std::vector<int32_t> pair_tab;     // ncb*ncb -> pair id or -1
+  std::vector<int32_t> pair_ptr;     // npairs + 1
+  std::vector<int64_t> pair_list;    // partial offsets per pair, in row-block order
+  // cell statistics
+  std::vector<int32_t> cell_colblocks; // per library cell: non-empty column blocks
+  int64_t block_index(int r, int C) const;  // -1 if (r, C) not stored
+};
+
+void plan_mv(MvPlan& mv, const MeshPlan& m, int M, const double* centers, const double* radius,
+             int radius_count, int ncolblocks, const int32_t* sizes, int B, int col_order);
+
+}  // namespace mfb

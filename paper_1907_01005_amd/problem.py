@@ -1,0 +1,69 @@
+"""Device-resident problem: mesh + layout + X/Y/S buffers on one GPU.
+
+Glue for callers (benchmark, tests, serving loop): plans the mesh and the
+BCSR layout through the C ABI, uploads the potential, packs the orbital
+values into BCSR order and keeps every device buffer alive.
+"""
+
+from __future__ import annotations
+
+from typing import Callable, Optional, Sequence
+
+import numpy as np
+
+from .api import FP64, Layout, Mesh, apply_H, apply_H_tuned, tmmult
+
+
+class DeviceProblem:
+    def __init__(self, cells: Sequence[int], L: Sequence[float], degree: int, dirichlet: int,
+                 centres: np.ndarray, radius, colblock_sizes, potential: Callable[[np.ndarray], np.ndarray],
+                 device: str = "cuda", stream=None):
+        import torch
+        self.device = device
+        self.mesh = Mesh(cells[0], cells[1], cells[2], L, degree, dirichlet)
+        qp = self.mesh.qp_points()
+        self.mesh.set_potential(np.asarray(potential(qp.reshape(-1, 3)), dtype=np.float64))
+        self.layout = Layout(self.mesh, centres, radius, colblock_sizes)
+        self.mesh.bind(device, stream)
+        self.layout.bind(device, stream)
+        self.M = self.layout.M
+        self.nvalues = self.layout.nvalues
+        self.X = self.layout.new_values(device)
+        self.Y = self.layout.new_values(device)
+        self.work = self.layout.new_work(device)
+        self.S = torch.zeros((self.M, self.M), dtype=torch.float64, device=device)
+        self.trace = torch.zeros(1, dtype=torch.float64, device=device)
+
+    def set_X_coo(self, node, orb, val) -> None:
+        import torch
+        host = self.layout.pack(node, orb, val)
+        self.X.copy_(torch.from_numpy(host).to(self.device))
+
+    def set_X_values(self, values: np.ndarray) -> None:
+        import torch
+        self.X.copy_(torch.from_numpy(np.ascontiguousarray(values, dtype=np.float64)).to(self.device))
+
+    def apply(self, prec: int = FP64, stream=None, X=None, Y=None) -> None:
+        apply_H(self.mesh, self.layout, self.X if X is None else X, self.Y if Y is None else Y,
+                prec, stream)
+
+    def apply_tuned(self, prec: int = FP64, kernel: int = 1, grid: int = 0, stream=None,
+                    X=None, Y=None) -> None:
+        apply_H_tuned(self.mesh, self.layout, self.X if X is None else X,
+                      self.Y if Y is None else Y, self.work, prec, kernel, grid, stream)
+
+    def overlap(self, stream=None, X=None, Y=None) -> None:
+        tmmult(self.layout, self.X if X is None else X, self.Y if Y is None else Y, self.S,
+               self.trace, self.work, stream)
+
+    def S_original_order(self) -> np.ndarray:
+        """S permuted back to original orbital ids."""
+        S = self.S.cpu().numpy()
+        perm = self.layout.pattern()["col_perm"]
+        out = np.empty_like(S)
+        out[np.ix_(perm, perm)] = S
+        return out
+
+    def device_bytes(self) -> int:
+        return (3 * 8 * self.nvalues + self.mesh.meta_bytes + self.layout.meta_bytes
+                + self.layout.work_bytes + 8 * self.M * self.M)

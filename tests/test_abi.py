@@ -1,0 +1,98 @@
+"""The C-ABI library loads, exports every declared symbol, and rejects bad
+arguments with the documented status codes (host-only calls, no GPU)."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1907_01005_amd import Layout, MfbError, Mesh, lib
+from paper_1907_01005_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "mfbcsr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mfb_[A-Za-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    h = lib()
+    names = declared_functions()
+    assert len(names) >= 19
+    for name in names:
+        assert hasattr(h, name), name
+    assert set(names) == set(N.SIGNATURES), set(names) ^ set(N.SIGNATURES)
+
+
+def test_mesh_errors():
+    with pytest.raises(MfbError) as e:
+        Mesh(3, 4, 4, (1, 1, 1), 2)
+    assert e.value.code == N.MFB_EINVAL
+    with pytest.raises(MfbError) as e:
+        Mesh(4, 4, 4, (1, 1, 1), 3)
+    assert e.value.code == N.MFB_EUNSUPPORTED
+    with pytest.raises(MfbError) as e:
+        Mesh(4, 4, 4, (1, -1, 1), 2)
+    assert e.value.code == N.MFB_EINVAL
+    h = C.c_void_p()
+    assert lib().mfb_create_mesh(None, C.byref(h)) == N.MFB_EINVAL
+    assert b"null" in lib().mfb_last_error()
+
+
+def test_layout_errors():
+    m = Mesh(4, 4, 4, (4, 4, 4), 2)
+    c = np.random.default_rng(0).random((10, 3)) * 4
+    with pytest.raises(MfbError) as e:
+        Layout(m, c, 1.5, colblock_sizes=[5, 4])      # does not sum to M
+    assert e.value.code == N.MFB_EINVAL
+    with pytest.raises(MfbError) as e:
+        Layout(m, c, -1.0)
+    assert e.value.code == N.MFB_EINVAL
+    with pytest.raises(MfbError) as e:
+        Layout(m, c, 1.5, colblock_sizes=[5, 0, 5])
+    assert e.value.code == N.MFB_EINVAL
+    lay = Layout(m, c, 1.5, colblock_sizes=[10])      # width 10 is fine
+    assert lay.info["ncolblocks"] == 1
+
+
+def test_layout_width_limit_and_pattern_errors():
+    m = Mesh(4, 4, 4, (4, 4, 4), 2)
+    c = np.random.default_rng(0).random((20, 3)) * 4
+    with pytest.raises(MfbError) as e:
+        Layout(m, c, 1.5, colblock_sizes=[20])
+    assert e.value.code == N.MFB_EUNSUPPORTED
+    lay = Layout(m, c, 1.5, colblock_sizes=[10, 10])
+    node, orb = lay.entry_coords()
+    stored = set(zip(node.tolist(), orb.tolist()))
+    out = next((g, a) for g in range(m.ndofs) for a in range(20) if (g, a) not in stored)
+    with pytest.raises(MfbError) as e:
+        lay.pack([out[0]], [out[1]], [1.0])
+    assert e.value.code == N.MFB_EPATTERN
+    with pytest.raises(MfbError) as e:
+        lay.pack([m.ndofs], [0], [1.0])
+    assert e.value.code == N.MFB_EINVAL
+
+
+def test_compute_calls_reject_unbound_handles():
+    """Argument and state checks run before any HIP call."""
+    m = Mesh(4, 4, 4, (4, 4, 4), 2)
+    lay = Layout(m, np.full((8, 3), 2.0), 3.0)
+    fake = C.c_void_p(4096)
+    rc = lib().mfb_apply_H(m.handle, lay.handle, fake, C.c_void_p(8192), 0, None)
+    assert rc == N.MFB_ESTATE
+    rc = lib().mfb_apply_H(m.handle, lay.handle, fake, fake, 0, None)
+    assert rc in (N.MFB_ESTATE, N.MFB_EINVAL)
+    m2 = Mesh(4, 4, 4, (4, 4, 4), 2)
+    rc = lib().mfb_apply_H(m2.handle, lay.handle, fake, C.c_void_p(8192), 0, None)
+    assert rc == N.MFB_EPATTERN
+    rc = lib().mfb_tmmult(lay.handle, fake, fake, fake, fake, fake, None)
+    assert rc == N.MFB_ESTATE
+    rc = lib().mfb_mesh_bind(m.handle, C.c_void_p(4096), None)
+    assert rc == N.MFB_ESTATE                         # no potential yet
+    rc = lib().mfb_mv_bind(lay.handle, C.c_void_p(4097), None)
+    assert rc == N.MFB_EINVAL                         # misaligned

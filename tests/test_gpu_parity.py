@@ -1,0 +1,199 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars: float64 forms within 1e-12 relative Frobenius error (Y, S, trace), the
+float32 forms within 1e-5; BCSR indices bit-exact (checked on the CPU in
+test_pattern_parity.py).
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from helpers import device_problem, gpu_available, oracle_Y_at, rel_fro, say
+from oracle.workload import OracleProblem
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not gpu_available():
+        pytest.fail("GPU tests need a visible GPU (run with -m 'not gpu' on CPU)")
+
+
+def _run(dp, prec, tuned=None):
+    import torch
+    if tuned is None:
+        dp.apply(prec)
+    else:
+        dp.apply_tuned(prec, kernel=tuned)
+    dp.overlap()
+    torch.cuda.synchronize()
+    return dp.Y.cpu().numpy()[:dp.nvalues], dp.S_original_order(), float(dp.trace.cpu()[0])
+
+
+def _check_full(wl, op, dp, prec, tol, tuned=None):
+    Yg, S, tr = _run(dp, prec, tuned)
+    node, orb = dp.layout.entry_coords()
+    Yo = oracle_Y_at(op, node, orb)
+    So, tro = op.overlap()
+    eY, eS = rel_fro(Yg, Yo), rel_fro(S, So)
+    et = abs(tr - tro) / max(abs(tro), 1e-300)
+    say(f"{wl.name} prec={prec} tuned={tuned}: relY={eY:.2e} relS={eS:.2e} relTr={et:.2e}")
+    assert eY <= tol and eS <= tol and et <= tol
+    return Yg
+
+
+def _small(cfg_cells, degree, M, radius, seed, sizes=None, dirichlet=0x3F, potential="wells",
+           L=None):
+    nx, ny, nz = cfg_cells
+    L = L or (float(nx), float(ny), float(nz))
+    ms = synth.MeshSpec(nx, ny, nz, L, degree, dirichlet)
+    wl = synth.custom_workload(ms, M, radius, seed, potential=potential,
+                               name=f"{nx}x{ny}x{nz}-Q{degree}-M{M}")
+    if sizes is not None:
+        wl.colblock_sizes = np.asarray(sizes, dtype=np.int32)
+    return wl
+
+
+@pytest.mark.parametrize("prec,tol", [(0, TOL64), (3, TOL32)])
+def test_config1_full(prec, tol):
+    wl = synth.make_workload(1)
+    say(f"config1 prec={prec}")
+    op = OracleProblem(wl)
+    dp = device_problem(wl)
+    dp.set_X_coo(op.node, op.orb, op.val)
+    _check_full(wl, op, dp, prec, tol)
+
+
+@pytest.mark.parametrize("degree", [2, 4])
+def test_generic_values_ragged_blocks(degree):
+    """Values at every stored entry (shell items do work) and ragged column blocks."""
+    wl = _small((8, 6, 4), degree, 29, 2.2, 11, sizes=[8, 5, 12, 4])
+    say(f"generic values Q{degree}")
+    op = OracleProblem(wl, values="generic", value_seed=3)
+    dp = device_problem(wl)
+    dp.set_X_coo(op.node, op.orb, op.val)
+    for prec, tol in ((0, TOL64), (3, TOL32)):
+        _check_full(wl, op, dp, prec, tol)
+    _check_full(wl, op, dp, 0, TOL64, tuned=1)
+
+
+def test_natural_bc_lexicographic_free_faces():
+    wl = _small((4, 6, 8), 2, 12, 3.0, 5, sizes=[7, 5], dirichlet=0b010110)
+    say("mixed Dirichlet faces")
+    op = OracleProblem(wl, values="generic", value_seed=9)
+    dp = device_problem(wl)
+    dp.set_X_coo(op.node, op.orb, op.val)
+    _check_full(wl, op, dp, 0, TOL64)
+
+
+@pytest.mark.parametrize("degree", [2, 4])
+def test_closed_form_through_library(degree):
+    """V = 1, natural BCs, full support: S = X^T H X hits closed-form integrals."""
+    from oracle.fe1d import gll_nodes
+    nx, ny, nz = 4, 2, 6
+    L = (1.0, 0.5, 1.5)
+    ms = synth.MeshSpec(nx, ny, nz, L, degree, 0)
+    wl = synth.custom_workload(ms, 4, 100.0, 1, potential="one")
+    wl.colblock_sizes = np.asarray([4], dtype=np.int32)
+    say(f"closed form Q{degree}")
+    dp = device_problem(wl)
+    na = [degree * c + 1 for c in (nx, ny, nz)]
+    xi = gll_nodes(degree)
+    pos = []
+    for d, c in enumerate((nx, ny, nz)):
+        X = np.arange(na[d])
+        cell = np.minimum(X // degree, c - 1)
+        pos.append((cell + xi[X - degree * cell]) * (L[d] / c))
+    g = np.arange(na[0] * na[1] * na[2])
+    x = pos[0][g % na[0]]
+    y = pos[1][(g // na[0]) % na[1]]
+    cols = [np.ones_like(x), x, y, x * y]
+    node = np.concatenate([g] * 4)
+    orb = np.repeat(np.arange(4), len(g)).astype(np.int32)
+    dp.set_X_coo(node, orb, np.concatenate(cols))
+    _, S, tr = _run(dp, 0)
+    Lx, Ly, Lz = L
+    vol = Lx * Ly * Lz
+    exact = {
+        (0, 0): vol,
+        (1, 1): 0.5 * vol + Lx ** 3 / 3 * Ly * Lz,
+        (2, 2): 0.5 * vol + Ly ** 3 / 3 * Lx * Lz,
+        (3, 3): 0.5 * (Ly ** 3 / 3 * Lx * Lz + Lx ** 3 / 3 * Ly * Lz) + Lx ** 3 / 3 * Ly ** 3 / 3 * Lz,
+        (0, 1): Lx ** 2 / 2 * Ly * Lz,
+    }
+    for (a, b), v in exact.items():
+        assert abs(S[a, b] - v) <= 1e-12 * max(1.0, abs(v)), (a, b, S[a, b], v)
+    assert abs(S[1, 0] - exact[(0, 1)]) <= 1e-12
+    assert abs(tr - sum(exact[(k, k)] for k in range(4))) <= 1e-11
+
+
+def test_empty_and_degenerate_layouts():
+    """No stored block at all, and an orbital set whose blocks miss some rows."""
+    import torch
+    wl = _small((4, 4, 4), 2, 8, 0.0, 2)      # no batch centre within radius 0
+    say("empty layout")
+    dp = device_problem(wl)
+    assert dp.nvalues == 0
+    dp.apply(0)
+    dp.overlap()
+    torch.cuda.synchronize()
+    assert float(dp.trace.cpu()[0]) == 0.0
+    assert not dp.S.abs().max().item()
+
+
+def test_repeat_determinism_and_queue_kernel():
+    wl = synth.make_workload(1)
+    say("determinism")
+    op = OracleProblem(wl)
+    dp = device_problem(wl)
+    dp.set_X_coo(op.node, op.orb, op.val)
+    Y1, S1, _ = _run(dp, 0)
+    Y2, S2, _ = _run(dp, 0)
+    Y3, S3, _ = _run(dp, 0, tuned=1)
+    scale = np.abs(Y1).max()
+    assert np.abs(Y1 - Y2).max() <= 1e-14 * scale
+    assert np.abs(Y1 - Y3).max() <= 1e-14 * scale
+    # the overlap reduction has a fixed order: bitwise repeatable for equal inputs
+    dp.Y.copy_(torch_from(Y1, dp))
+    dp.overlap()
+    Sa = dp.S.cpu().numpy().copy()
+    dp.overlap()
+    assert np.array_equal(Sa, dp.S.cpu().numpy())
+
+
+def torch_from(a, dp):
+    import torch
+    t = torch.zeros_like(dp.Y)
+    t[:len(a)] = torch.from_numpy(a).to(t.device)
+    return t
+
+
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_paper_scale_sampled(cfg):
+    """Full-size configurations: every stored entry of 3 column blocks, all of S."""
+    wl = synth.make_workload(cfg)
+    say(f"config{cfg} full size")
+    op = OracleProblem(wl)
+    dp = device_problem(wl)
+    dp.set_X_coo(op.node, op.orb, op.val)
+    for prec, tol in ((0, TOL64), (3, TOL32)):
+        Yg, S, tr = _run(dp, prec)
+        node, orb = dp.layout.entry_coords()
+        blocks = [0, wl.colblock_sizes.size // 2, wl.colblock_sizes.size - 1]
+        sel_orbs = np.concatenate([op.block_orbitals(C) for C in blocks])
+        sel = np.isin(orb, sel_orbs)
+        Yo = oracle_Y_at(op, node[sel], orb[sel], blocks)
+        eY = rel_fro(Yg[sel], Yo)
+        say(f"config{cfg} prec={prec} relY(sampled)={eY:.2e}")
+        assert eY <= tol
+        if prec == 0:
+            So, tro = op.overlap()
+            eS = rel_fro(S, So)
+            et = abs(tr - tro) / abs(tro)
+            say(f"config{cfg} relS={eS:.2e} relTr={et:.2e}")
+            assert eS <= tol and et <= tol

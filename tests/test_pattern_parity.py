@@ -1,0 +1,97 @@
+"""Host planner of the library (C ABI, no GPU) against the oracle's pattern:
+every index array bit-exact."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.mesh import BoxMesh
+from oracle.pattern import build_pattern, entry_coords
+from paper_1907_01005_amd import Layout, Mesh
+
+
+def _both(wl, mesh_index=0, order=0):
+    ms = wl.meshes[mesh_index]
+    m = Mesh(ms.nx, ms.ny, ms.nz, ms.L, ms.degree, ms.dirichlet, order=order)
+    lay = Layout(m, wl.centres, wl.radius, wl.colblock_sizes)
+    om = BoxMesh(ms.nx, ms.ny, ms.nz, tuple(ms.L), ms.degree, ms.dirichlet)
+    op = build_pattern(om, wl.centres, wl.radius, wl.colblock_sizes, hilbert_rows=(order == 0))
+    return m, lay, op
+
+
+def _assert_same(lay, op):
+    p = lay.pattern()
+    assert np.array_equal(p["batch_order"], op.batch_order)
+    assert np.array_equal(p["row_block_start"], op.rb_start)
+    assert np.array_equal(p["dof_perm"], op.dof_perm)
+    assert np.array_equal(p["col_perm"], op.col_perm)
+    assert np.array_equal(p["col_block_start"], op.cb_start)
+    assert np.array_equal(p["rowptr"], op.rowptr)
+    assert np.array_equal(p["colidx"], op.colidx)
+    assert np.array_equal(p["block_offset"], op.block_offset)
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_config_patterns_bit_exact(cfg):
+    wl = synth.make_workload(cfg)
+    _, lay, op = _both(wl)
+    _assert_same(lay, op)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("mesh_index", [0, 1])
+def test_config4_patterns_bit_exact(mesh_index):
+    wl = synth.make_workload(4)
+    _, lay, op = _both(wl, mesh_index)
+    _assert_same(lay, op)
+    assert lay.info["ncolblocks"] == len(wl.colblock_sizes)
+    assert 4 <= wl.colblock_sizes.min() and wl.colblock_sizes.max() <= 15
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_small_meshes(seed):
+    rng = np.random.default_rng(seed)
+    cells = tuple(int(2 * rng.integers(1, 6)) for _ in range(3))
+    degree = int(rng.choice([2, 4]))
+    L = tuple(float(c) * float(rng.uniform(0.5, 1.5)) for c in cells)
+    ms = synth.MeshSpec(*cells, L, degree, int(rng.integers(0, 64)))
+    M = int(rng.integers(1, 40))
+    wl = synth.custom_workload(ms, M, float(rng.uniform(0.5, 4.0)), seed, B=int(rng.integers(1, 9)),
+                               uneven=bool(rng.integers(0, 2)))
+    for order in (0, 1):
+        _, lay, op = _both(wl, order=order)
+        _assert_same(lay, op)
+
+
+def test_entry_coords_and_pack_roundtrip():
+    wl = synth.make_workload(1)
+    m, lay, op = _both(wl)
+    node, orb = lay.entry_coords()
+    onode, oorb = entry_coords(op)
+    assert np.array_equal(node, onode) and np.array_equal(orb, oorb)
+    vals = np.arange(len(node), dtype=np.float64) + 1.0
+    packed = lay.pack(node, orb, vals)
+    assert np.array_equal(packed, vals)
+
+
+def test_support_values_fit_the_pattern():
+    for cfg in (1, 2):
+        wl = synth.make_workload(cfg)
+        ms = wl.mesh
+        m = Mesh(ms.nx, ms.ny, ms.nz, ms.L, ms.degree, ms.dirichlet)
+        lay = Layout(m, wl.centres, wl.radius, wl.colblock_sizes)
+        node, orb, val = synth.orbital_values(wl)
+        lay.pack(node, orb, val)          # raises MFB_EPATTERN if any value falls outside
+
+
+def test_table1_statistics_plausible():
+    """Table 1: 66.1 +- 18.1 rows per row block; total non-empty column blocks
+    over all cells 97429.8 (quadratic) and 14877.4 (quartic) -- soft checks."""
+    for cfg, rows_mean, colsum in ((2, 66.1226, 97429.8), (3, 528.981, 14877.4)):
+        wl = synth.make_workload(cfg)
+        ms = wl.mesh
+        m = Mesh(ms.nx, ms.ny, ms.nz, ms.L, ms.degree, ms.dirichlet)
+        lay = Layout(m, wl.centres, wl.radius, wl.colblock_sizes)
+        st = lay.stats()
+        assert abs(st["rows_mean"] - rows_mean) < 1e-3
+        assert 0.5 * colsum < st["colblocks_per_cell_sum"] < 2.0 * colsum
