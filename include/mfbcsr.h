@@ -230,11 +230,16 @@ void mfb_destroy_mv(mfb_mv* mv);
 int mfb_apply_H(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X, double* d_Y,
                 int prec, void* stream);
 
-/* Same result through an explicitly configured kernel.
- * kernel: 0 = one work item per workgroup, 1 = persistent workgroups pulling
- * items from a queue.  grid: persistent workgroups (0 = 2 per CU).  d_work:
- * the workspace (info.work_bytes) -- it holds the queue counter, so two tuned
- * applies sharing a workspace must not overlap in time.                     */
+/* Same result through an explicitly configured kernel (used by the
+ * autotuner).  kernel: even values launch one work unit per workgroup, odd
+ * values launch persistent workgroups that pull units from a queue; kernel/2
+ * selects how a unit maps onto threads: 0 = the default for the degree,
+ * 1 = a workgroup of 64(p+1) threads per (batch, 8-column chunk) with LDS
+ * layout switches, 2 = one wave per unit (p = 2: the whole cell tensor in
+ * registers; p = 4: one wave per cell).  grid: persistent workgroups (0 =
+ * as many as fit on the device).  d_work: the workspace (info.work_bytes);
+ * it holds the queue counters, so two tuned applies sharing a workspace must
+ * not overlap in time.                                                      */
 typedef struct {
   int32_t prec;
   int32_t kernel;

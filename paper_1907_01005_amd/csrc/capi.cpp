@@ -9,7 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/mfbcsr.h"
+#include "mfbcsr.h"
 #include "kernels.hpp"
 #include "planner.hpp"
 
@@ -20,16 +20,33 @@ thread_local std::string g_err;
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct MeshLayout {
-  size_t off_gtab = 0, off_cv = 0, bytes = 0;
+  size_t off_gtab = 0, off_cv = 0, off_wg = 0, bytes = 0;
 };
 
 MeshLayout mesh_layout(const mfb::MeshPlan& m) {
   MeshLayout L;
-  const size_t nb3 = (size_t)m.NB * m.NB * m.NB;
+  const size_t nb3 = (size_t)m.NB * m.NB * m.NB, n3 = (size_t)m.n * m.n * m.n;
   L.off_gtab = 0;
   L.off_cv = align256(sizeof(int32_t) * nb3 * m.nbatch);
-  L.bytes = align256(L.off_cv + sizeof(double) * (size_t)m.ncells * m.n * m.n * m.n);
+  L.off_wg = align256(L.off_cv + sizeof(double) * (size_t)m.ncells * n3);
+  L.bytes = align256(L.off_wg + sizeof(double) * 3 * n3);
   return L;
+}
+
+// Per-direction quadrature scaling of the gradient term of eq. fe_matrices on
+// a box cell: 1/2 JxW_q / h_d^2 with JxW_q = w_q1 w_q2 w_q3 hx hy hz.
+std::vector<double> grad_scales(const mfb::MeshPlan& m) {
+  const int n = m.n, n3 = n * n * n;
+  const double det = m.h[0] * m.h[1] * m.h[2];
+  std::vector<double> wg(3 * n3);
+  for (int d = 0; d < 3; ++d)
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          const double jxw = m.basis.wq[i] * m.basis.wq[j] * m.basis.wq[k] * det;
+          wg[d * n3 + i + n * (j + n * k)] = 0.5 * jxw / (m.h[d] * m.h[d]);
+        }
+  return wg;
 }
 
 struct MvLayout {
@@ -177,6 +194,8 @@ int mfb_mesh_bind(mfb_mesh* mesh, void* d_meta, void* stream) {
   std::vector<char> host(mesh->lay.bytes, 0);
   std::memcpy(host.data() + mesh->lay.off_gtab, m.gtab.data(), sizeof(int32_t) * m.gtab.size());
   std::memcpy(host.data() + mesh->lay.off_cv, m.cV.data(), sizeof(double) * m.cV.size());
+  const std::vector<double> wg = grad_scales(m);
+  std::memcpy(host.data() + mesh->lay.off_wg, wg.data(), sizeof(double) * wg.size());
   hipStream_t st = (hipStream_t)stream;
   check_hip(hipMemcpyAsync(d_meta, host.data(), host.size(), hipMemcpyHostToDevice, st),
             "hipMemcpyAsync(mesh metadata)");
@@ -361,20 +380,17 @@ static void fill_apply_params(const mfb_mesh* mesh, const mfb_mv* mv, const doub
   const char* mb = (const char*)mv->d_meta;
   const char* gb = (const char*)mesh->d_meta;
   a.items = (const mfb::ApplyItem*)(mb + mv->lay.off_items);
-  a.nitems = (int64_t)mv->plan.items.size();
+  a.nitems = mv->plan.n_own_items;
+  a.shell = a.items + mv->plan.n_own_items;
+  a.nshell = (int64_t)mv->plan.items.size() - mv->plan.n_own_items;
   a.gtab = (const int32_t*)(gb + mesh->lay.off_gtab);
   a.cV = (const double*)(gb + mesh->lay.off_cv);
+  a.Wg = (const double*)(gb + mesh->lay.off_wg);
   const int n = m.n;
   for (int i = 0; i < n * n; ++i) {
     a.S[i] = b.S[i];
     a.Dco[i] = b.Dco[i];
   }
-  for (int i = 0; i < n; ++i) {
-    a.w[i] = b.wq[i];
-    for (int j = 0; j < n; ++j) a.W2[i * n + j] = b.wq[i] * b.wq[j];
-  }
-  const double det = m.h[0] * m.h[1] * m.h[2];
-  for (int d = 0; d < 3; ++d) a.cg[d] = 0.5 * det / (m.h[d] * m.h[d]);
 }
 
 static void check_apply_args(const mfb_mesh* mesh, const mfb_mv* mv, const double* X, const double* Y) {
@@ -405,9 +421,9 @@ int mfb_apply_H_tuned(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X,
   check_apply_args(mesh, mv, d_X, d_Y);
   if (!tune) fail(MFB_EINVAL, "null tune");
   if (tune->prec < 0 || tune->prec > 3) fail(MFB_EINVAL, "unknown precision");
-  if (tune->kernel != 0 && tune->kernel != 1) fail(MFB_EINVAL, "kernel must be 0 or 1");
+  if (tune->kernel < 0 || tune->kernel > 5) fail(MFB_EINVAL, "kernel must be in 0..5");
   if (tune->grid < 0) fail(MFB_EINVAL, "negative grid");
-  if (tune->kernel == 1 && !d_work) fail(MFB_EINVAL, "the queue kernel needs the workspace");
+  if ((tune->kernel & 1) && !d_work) fail(MFB_EINVAL, "the queue kernels need the workspace");
   mfb::gpu::ApplyParams a;
   fill_apply_params(mesh, mv, d_X, d_Y, a);
   a.counters = (int32_t*)d_work;
@@ -425,6 +441,7 @@ int mfb_tmmult(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d
   MFB_TRY
   if (!mv || !d_X || !d_Y || !d_S || !d_trace || !d_work) fail(MFB_EINVAL, "null argument");
   if (!mv->bound) fail(MFB_ESTATE, "layout metadata not bound");
+  if (((uintptr_t)d_work & 255) != 0) fail(MFB_EINVAL, "d_work must be 256-byte aligned");
   const auto& p = mv->plan;
   const char* mb = (const char*)mv->d_meta;
   mfb::gpu::TmParams t;

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -77,155 +78,195 @@ __device__ __forceinline__ int64_t xcd_item(int64_t wg, int64_t nwg) {
 }
 
 // -------------------------------------------------------------- apply
-template <typename R, int P>
-struct Shape {
+// Three ways to map a work item onto threads (selected per launch):
+//  * BatchProc: 64 (p+1) threads per (batch, 8-column chunk); thread
+//    (column, cell, plane) holds one plane of its cell-column and the layout
+//    switches go through an LDS tile per cell-column (8 cells x 8 columns).
+//  * RegProc: one wave per (batch, chunk); lane (cell, column) holds the
+//    whole cell-column tensor in registers, so every 1D contraction is
+//    in-lane and no LDS transpose is needed (used for p = 2).
+//  * CellProc: one wave per (batch, chunk, cell); lane (plane, column) as
+//    in BatchProc but for one cell, so the LDS tile is 8x smaller (p = 4).
+// All three end with the node sums of the cell results and float64 atomic
+// adds into the stored rows of Y.
+
+template <int P>
+struct Dims {
   static constexpr int n = P + 1, n2 = n * n, n3 = n2 * n;
   static constexpr int NB = 2 * P + 1, NB3 = NB * NB * NB;
-  static constexpr int NT = 64 * n;  // threads per workgroup
 };
 
+// Gather the z = pl plane of cell e of the item into u[i][j] (layout A).
+// Returns whether any gathered value is non-zero.
 template <typename R, int P>
-__device__ __forceinline__ void apply_item(const ApplyParams& a, const ApplyItem* __restrict__ it,
-                                           R* __restrict__ T, int64_t* __restrict__ s_off) {
-  using Sh = Shape<R, P>;
-  constexpr int n = Sh::n, n2 = Sh::n2, n3 = Sh::n3, NB = Sh::NB, NB3 = Sh::NB3, NT = Sh::NT;
-  const int t = threadIdx.x;
-  const int c = t & 7, e = (t >> 3) & 7, pl = t >> 6;
+__device__ __forceinline__ bool gather_plane(const ApplyParams& a, const int32_t* __restrict__ g,
+                                             const int64_t* __restrict__ off, int e, int pl, int c,
+                                             int c0, int nc, int ld, bool act,
+                                             R (&u)[P + 1][P + 1]) {
+  using D = Dims<P>;
+  constexpr int n = D::n, NB = D::NB;
   const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
-  const int cc = t & 63;  // cell-column slot of this thread
+  bool any = false;
+#pragma unroll
+  for (int j = 0; j < n; ++j)
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      double x = 0.0;
+      if (act && c < nc) {
+        const int v = (ex * P + i) + NB * ((ey * P + j) + NB * (ez * P + pl));
+        const int32_t ent = g[v];
+        if (ent >= 0) {
+          const int64_t o = off[ent >> 24];
+          if (o >= 0) x = a.X[o + (int64_t)(ent & 0xFFFFFF) * ld + c0 + c];
+        }
+      }
+      u[i][j] = (R)x;
+      any |= (x != 0.0);
+    }
+  return any;
+}
 
-  if (t < 27) s_off[t] = it->off[t];
-  const int rank = it->rank, c0 = it->c0, nc = it->nc, ld = it->ld;
-  __syncthreads();
-
+// Sum-factorised cell operator on planes.  On entry u holds the z = pl plane
+// of the nodal values (layout A); on exit Tc holds the cell's output values
+// (index i + n j + n^2 k).  Threads with act == false only join the barriers.
+template <typename R, int P>
+__device__ __forceinline__ void plane_operator(const ApplyParams& a, R* __restrict__ Tc, int pl,
+                                               const double* __restrict__ cv, bool act,
+                                               const R (&u)[P + 1][P + 1]) {
+  using D = Dims<P>;
+  constexpr int n = D::n, n2 = D::n2, n3 = D::n3;
   R Sm[n * n], Dm[n * n];
 #pragma unroll
   for (int i = 0; i < n * n; ++i) {
     Sm[i] = (R)a.S[i];
     Dm[i] = (R)a.Dco[i];
   }
-  const int32_t* __restrict__ g = a.gtab + (int64_t)rank * NB3;
-
-  // gather the z = pl plane of this cell-column (layout A)
-  R u[n][n];
-  bool any = false;
-#pragma unroll
-  for (int j = 0; j < n; ++j)
-#pragma unroll
-    for (int i = 0; i < n; ++i) {
-      const int v = (ex * P + i) + NB * ((ey * P + j) + NB * (ez * P + pl));
-      const int32_t ent = g[v];
-      double x = 0.0;
-      if (c < nc && ent >= 0) {
-        const int64_t off = s_off[ent >> 24];
-        if (off >= 0) x = a.X[off + (int64_t)(ent & 0xFFFFFF) * ld + c0 + c];
-      }
-      u[i][j] = (R)x;
-      any |= (x != 0.0);
-    }
-  // an item whose gathered values are all zero contributes exactly zero
-  if (!__syncthreads_or(any)) return;
-
-  R* __restrict__ Tc = T + cc * n3;
+  const double* __restrict__ wg = a.Wg;
   R A[n][n], B[n][n];
-  // forward interpolation along x and y (layout A)
   contract<n, 0, false>(Sm, u, A);
   contract<n, 1, false>(Sm, A, B);
+  if (act) {
 #pragma unroll
-  for (int j = 0; j < n; ++j)
+    for (int j = 0; j < n; ++j)
 #pragma unroll
-    for (int i = 0; i < n; ++i) Tc[i + n * j + n2 * pl] = B[i][j];
+      for (int i = 0; i < n; ++i) Tc[i + n * j + n2 * pl] = B[i][j];
+  }
   __syncthreads();
-  // layout B: plane y = pl (already at its Gauss point)
+  // layout B: plane y = pl
+  if (act) {
 #pragma unroll
-  for (int k = 0; k < n; ++k)
+    for (int k = 0; k < n; ++k)
 #pragma unroll
-    for (int i = 0; i < n; ++i) A[i][k] = Tc[i + n * pl + n2 * k];
-  R uq[n][n];
-  contract<n, 1, false>(Sm, A, uq);  // along z: uq[x][z] at y = pl
-  const double wpl = a.w[pl];
-  const double sx = a.cg[0] * wpl, sy = a.cg[1] * wpl, sz = a.cg[2] * wpl;
-  R wB[n][n];
-  // x-gradient
+      for (int i = 0; i < n; ++i) A[i][k] = Tc[i + n * pl + n2 * k];
+  }
+  R uq[n][n], wB[n][n];
+  contract<n, 1, false>(Sm, A, uq);
   contract<n, 0, false>(Dm, uq, A);
 #pragma unroll
   for (int i = 0; i < n; ++i)
 #pragma unroll
-    for (int k = 0; k < n; ++k) A[i][k] = (R)((double)A[i][k] * (sx * a.W2[i * n + k]));
+    for (int k = 0; k < n; ++k) A[i][k] = (R)((double)A[i][k] * wg[i + n * pl + n2 * k]);
   contract<n, 0, true>(Dm, A, wB);
-  // z-gradient
   contract<n, 1, false>(Dm, uq, A);
 #pragma unroll
   for (int i = 0; i < n; ++i)
 #pragma unroll
-    for (int k = 0; k < n; ++k) A[i][k] = (R)((double)A[i][k] * (sz * a.W2[i * n + k]));
+    for (int k = 0; k < n; ++k) A[i][k] = (R)((double)A[i][k] * wg[2 * n3 + i + n * pl + n2 * k]);
   contract_add<n, 1, true>(Dm, A, wB);
-  // potential term, float64: c_V = JxW V
-  {
-    const double* __restrict__ cv = a.cV + ((int64_t)rank * 8 + e) * n3 + n * pl;
+  if (act) {
 #pragma unroll
     for (int i = 0; i < n; ++i)
 #pragma unroll
       for (int k = 0; k < n; ++k)
-        wB[i][k] = (R)((double)wB[i][k] + cv[i + n2 * k] * (double)uq[i][k]);
+        wB[i][k] = (R)((double)wB[i][k] + cv[i + n * pl + n2 * k] * (double)uq[i][k]);
   }
   __syncthreads();
+  if (act) {
 #pragma unroll
-  for (int k = 0; k < n; ++k)
+    for (int k = 0; k < n; ++k)
 #pragma unroll
-    for (int i = 0; i < n; ++i) Tc[i + n * pl + n2 * k] = uq[i][k];
+      for (int i = 0; i < n; ++i) Tc[i + n * pl + n2 * k] = uq[i][k];
+  }
   __syncthreads();
-  // layout A again (plane z = pl): y-gradient
+  // layout A: y-gradient
+  if (act) {
 #pragma unroll
-  for (int j = 0; j < n; ++j)
+    for (int j = 0; j < n; ++j)
 #pragma unroll
-    for (int i = 0; i < n; ++i) A[i][j] = Tc[i + n * j + n2 * pl];
+      for (int i = 0; i < n; ++i) A[i][j] = Tc[i + n * j + n2 * pl];
+  }
   contract<n, 1, false>(Dm, A, B);
 #pragma unroll
   for (int i = 0; i < n; ++i)
 #pragma unroll
-    for (int j = 0; j < n; ++j) B[i][j] = (R)((double)B[i][j] * (sy * a.W2[i * n + j]));
-  contract<n, 1, true>(Dm, B, A);  // A = D_y^T g_y   (layout A)
+    for (int j = 0; j < n; ++j) B[i][j] = (R)((double)B[i][j] * wg[n3 + i + n * j + n2 * pl]);
+  contract<n, 1, true>(Dm, B, A);
   __syncthreads();
+  if (act) {
 #pragma unroll
-  for (int j = 0; j < n; ++j)
+    for (int j = 0; j < n; ++j)
 #pragma unroll
-    for (int i = 0; i < n; ++i) Tc[i + n * j + n2 * pl] = A[i][j];
+      for (int i = 0; i < n; ++i) Tc[i + n * j + n2 * pl] = A[i][j];
+  }
   __syncthreads();
-  // layout B: add the y part, then integrate back along z
+  // layout B: add the y part and integrate back along z
+  if (act) {
 #pragma unroll
-  for (int k = 0; k < n; ++k)
+    for (int k = 0; k < n; ++k)
 #pragma unroll
-    for (int i = 0; i < n; ++i) wB[i][k] += Tc[i + n * pl + n2 * k];
-  contract<n, 1, true>(Sm, wB, A);  // A[x][z nodal] at y = pl (Gauss)
+      for (int i = 0; i < n; ++i) wB[i][k] += Tc[i + n * pl + n2 * k];
+  }
+  contract<n, 1, true>(Sm, wB, A);
   __syncthreads();
+  if (act) {
 #pragma unroll
-  for (int k = 0; k < n; ++k)
+    for (int k = 0; k < n; ++k)
 #pragma unroll
-    for (int i = 0; i < n; ++i) Tc[i + n * pl + n2 * k] = A[i][k];
+      for (int i = 0; i < n; ++i) Tc[i + n * pl + n2 * k] = A[i][k];
+  }
   __syncthreads();
   // layout A: integrate back along y and x
+  if (act) {
 #pragma unroll
-  for (int j = 0; j < n; ++j)
+    for (int j = 0; j < n; ++j)
 #pragma unroll
-    for (int i = 0; i < n; ++i) A[i][j] = Tc[i + n * j + n2 * pl];
+      for (int i = 0; i < n; ++i) A[i][j] = Tc[i + n * j + n2 * pl];
+  }
   contract<n, 1, true>(Sm, A, B);
   contract<n, 0, true>(Sm, B, A);
   __syncthreads();
+  if (act) {
 #pragma unroll
-  for (int j = 0; j < n; ++j)
+    for (int j = 0; j < n; ++j)
 #pragma unroll
-    for (int i = 0; i < n; ++i) Tc[i + n * j + n2 * pl] = A[i][j];
+      for (int i = 0; i < n; ++i) Tc[i + n * j + n2 * pl] = A[i][j];
+  }
   __syncthreads();
+}
 
-  // sum the cell results per batch node and add into the stored rows of Y
-  for (int idx = t; idx < NB3 * 8; idx += NT) {
+// Sum the 8 cell results of a batch per batch node (T holds cell-column
+// tensors at T[(e*8 + col)*n^3 + local]) and add them into stored rows of Y.
+template <typename R, int P, int NT>
+__device__ __forceinline__ void batch_scatter(const ApplyParams& a, const R* __restrict__ T,
+                                              const int32_t* __restrict__ g,
+                                              const int64_t* __restrict__ off, int c0, int nc,
+                                              int ld, int t) {
+  using D = Dims<P>;
+  constexpr int n = D::n, n2 = D::n2, n3 = D::n3, NB = D::NB, NB3 = D::NB3;
+  constexpr int TOT = NB3 * 8, K = (TOT + NT - 1) / NT;
+  int32_t ent[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int idx = t + k * NT;
+    ent[k] = (idx < TOT && (idx & 7) < nc) ? g[idx >> 3] : -1;
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if (ent[k] < 0) continue;
+    const int64_t o = off[ent[k] >> 24];
+    if (o < 0) continue;
+    const int idx = t + k * NT;
     const int col = idx & 7, v = idx >> 3;
-    if (col >= nc) continue;
-    const int32_t ent = g[v];
-    if (ent < 0) continue;
-    const int64_t off = s_off[ent >> 24];
-    if (off < 0) continue;
     const int vx = v % NB, vy = (v / NB) % NB, vz = v / (NB * NB);
     double acc = 0.0;
 #pragma unroll
@@ -245,45 +286,216 @@ __device__ __forceinline__ void apply_item(const ApplyParams& a, const ApplyItem
         }
       }
     }
-    unsafeAtomicAdd(a.Y + off + (int64_t)(ent & 0xFFFFFF) * ld + c0 + col, acc);
+    unsafeAtomicAdd(a.Y + o + (int64_t)(ent[k] & 0xFFFFFF) * ld + c0 + col, acc);
   }
 }
 
 template <typename R, int P>
-__global__ __launch_bounds__(64 * (P + 1)) void apply_grid_kernel(ApplyParams a) {
-  using Sh = Shape<R, P>;
-  __shared__ R T[64 * Sh::n3];
-  __shared__ int64_t s_off[27];
-  const int64_t item = xcd_item(blockIdx.x, gridDim.x);
-  if (item >= a.nitems) return;
-  apply_item<R, P>(a, a.items + item, T, s_off);
+struct BatchProc {
+  using D = Dims<P>;
+  static constexpr int NT = 64 * D::n, UPI = 1;
+  struct Smem {
+    R T[64 * D::n3];
+    int64_t off[27];
+  };
+  static __device__ __forceinline__ void run(const ApplyParams& a,
+                                             const ApplyItem* __restrict__ it, int, Smem& sm) {
+    const int t = threadIdx.x;
+    const int c = t & 7, e = (t >> 3) & 7, pl = t >> 6;
+    if (t < 27) sm.off[t] = it->off[t];
+    const int rank = it->rank, c0 = it->c0, nc = it->nc, ld = it->ld;
+    __syncthreads();
+    const int32_t* __restrict__ g = a.gtab + (int64_t)rank * D::NB3;
+    R u[D::n][D::n];
+    const bool any = gather_plane<R, P>(a, g, sm.off, e, pl, c, c0, nc, ld, true, u);
+    if (!__syncthreads_or(any)) return;
+    plane_operator<R, P>(a, sm.T + (t & 63) * D::n3, pl,
+                         a.cV + ((int64_t)rank * 8 + e) * D::n3, true, u);
+    batch_scatter<R, P, NT>(a, sm.T, g, sm.off, c0, nc, ld, t);
+  }
+};
+
+template <typename R, int P>
+struct CellProc {
+  using D = Dims<P>;
+  static constexpr int NT = 64, UPI = 8;
+  struct Smem {
+    R T[8 * D::n3];
+    int64_t off[27];
+  };
+  static __device__ __forceinline__ void run(const ApplyParams& a,
+                                             const ApplyItem* __restrict__ it, int e, Smem& sm) {
+    constexpr int n = D::n, n2 = D::n2, n3 = D::n3, NB = D::NB;
+    const int t = threadIdx.x;
+    const int c = t & 7, pl = t >> 3;
+    const bool act = pl < n;
+    if (t < 27) sm.off[t] = it->off[t];
+    const int rank = it->rank, c0 = it->c0, nc = it->nc, ld = it->ld;
+    __syncthreads();
+    const int32_t* __restrict__ g = a.gtab + (int64_t)rank * D::NB3;
+    R u[n][n];
+    const bool any = gather_plane<R, P>(a, g, sm.off, e, act ? pl : 0, c, c0, nc, ld, act, u);
+    if (!__syncthreads_or(any)) return;
+    plane_operator<R, P>(a, sm.T + c * n3, act ? pl : 0,
+                         a.cV + ((int64_t)rank * 8 + e) * n3, act, u);
+    const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
+    for (int idx = t; idx < n3 * 8; idx += 64) {
+      const int col = idx & 7, loc = idx >> 3;
+      if (col >= nc) continue;
+      const int lx = loc % n, ly = (loc / n) % n, lz = loc / n2;
+      const int v = (ex * P + lx) + NB * ((ey * P + ly) + NB * (ez * P + lz));
+      const int32_t ent = g[v];
+      if (ent < 0) continue;
+      const int64_t o = sm.off[ent >> 24];
+      if (o < 0) continue;
+      unsafeAtomicAdd(a.Y + o + (int64_t)(ent & 0xFFFFFF) * ld + c0 + col,
+                      (double)sm.T[col * n3 + loc]);
+    }
+  }
+};
+
+// In-place 1D contraction of every line along AXIS of a register tensor
+// u[i + n j + n^2 k]: u_line <- M u_line (M^T when TR).
+template <int n, int AXIS, bool TR, typename R>
+__device__ __forceinline__ void sweep(R (&u)[n * n * n], const R* __restrict__ M) {
+  constexpr int S = AXIS == 0 ? 1 : (AXIS == 1 ? n : n * n);
+#pragma unroll
+  for (int l = 0; l < n * n; ++l) {
+    const int base = AXIS == 0 ? l * n : (AXIS == 1 ? (l % n) + (l / n) * n * n : l);
+    R tmp[n];
+#pragma unroll
+    for (int o = 0; o < n; ++o) {
+      R s = 0;
+#pragma unroll
+      for (int k = 0; k < n; ++k) s = __builtin_fma(TR ? M[k * n + o] : M[o * n + k], u[base + k * S], s);
+      tmp[o] = s;
+    }
+#pragma unroll
+    for (int o = 0; o < n; ++o) u[base + o * S] = tmp[o];
+  }
 }
 
-// Persistent form: each workgroup pulls items from the queue of its XCD's
+// w += D_AXIS^T ( wg (.) D_AXIS uq ), line by line (float64 scaling).
+template <int n, int AXIS, typename R>
+__device__ __forceinline__ void grad_pass(const R (&uq)[n * n * n], R (&w)[n * n * n],
+                                          const R* __restrict__ Dm, const double* __restrict__ wg) {
+  constexpr int S = AXIS == 0 ? 1 : (AXIS == 1 ? n : n * n);
+#pragma unroll
+  for (int l = 0; l < n * n; ++l) {
+    const int base = AXIS == 0 ? l * n : (AXIS == 1 ? (l % n) + (l / n) * n * n : l);
+    R gq[n];
+#pragma unroll
+    for (int o = 0; o < n; ++o) {
+      R s = 0;
+#pragma unroll
+      for (int k = 0; k < n; ++k) s = __builtin_fma(Dm[o * n + k], uq[base + k * S], s);
+      gq[o] = (R)((double)s * wg[base + o * S]);
+    }
+#pragma unroll
+    for (int o = 0; o < n; ++o) {
+      R s = w[base + o * S];
+#pragma unroll
+      for (int k = 0; k < n; ++k) s = __builtin_fma(Dm[k * n + o], gq[k], s);
+      w[base + o * S] = s;
+    }
+  }
+}
+
+template <typename R, int P>
+struct RegProc {
+  using D = Dims<P>;
+  static constexpr int NT = 64, UPI = 1;
+  struct Smem {
+    R T[64 * D::n3];
+    int64_t off[27];
+  };
+  static __device__ __forceinline__ void run(const ApplyParams& a,
+                                             const ApplyItem* __restrict__ it, int, Smem& sm) {
+    constexpr int n = D::n, n2 = D::n2, n3 = D::n3, NB = D::NB;
+    const int t = threadIdx.x;
+    const int c = t & 7, e = t >> 3;
+    const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
+    if (t < 27) sm.off[t] = it->off[t];
+    const int rank = it->rank, c0 = it->c0, nc = it->nc, ld = it->ld;
+    __syncthreads();
+    const int32_t* __restrict__ g = a.gtab + (int64_t)rank * D::NB3;
+    R u[n3];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < n; ++k)
+#pragma unroll
+      for (int j = 0; j < n; ++j)
+#pragma unroll
+        for (int i = 0; i < n; ++i) {
+          double x = 0.0;
+          if (c < nc) {
+            const int v = (ex * P + i) + NB * ((ey * P + j) + NB * (ez * P + k));
+            const int32_t ent = g[v];
+            if (ent >= 0) {
+              const int64_t o = sm.off[ent >> 24];
+              if (o >= 0) x = a.X[o + (int64_t)(ent & 0xFFFFFF) * ld + c0 + c];
+            }
+          }
+          u[i + n * j + n2 * k] = (R)x;
+          any |= (x != 0.0);
+        }
+    if (!__syncthreads_or(any)) return;
+    R Sm[n * n], Dm[n * n];
+#pragma unroll
+    for (int i = 0; i < n * n; ++i) {
+      Sm[i] = (R)a.S[i];
+      Dm[i] = (R)a.Dco[i];
+    }
+    sweep<n, 0, false>(u, Sm);
+    sweep<n, 1, false>(u, Sm);
+    sweep<n, 2, false>(u, Sm);
+    R w[n3];
+    const double* __restrict__ cv = a.cV + ((int64_t)rank * 8 + e) * n3;
+#pragma unroll
+    for (int q = 0; q < n3; ++q) w[q] = (R)(cv[q] * (double)u[q]);
+    grad_pass<n, 0>(u, w, Dm, a.Wg);
+    grad_pass<n, 1>(u, w, Dm, a.Wg + n3);
+    grad_pass<n, 2>(u, w, Dm, a.Wg + 2 * n3);
+    sweep<n, 2, true>(w, Sm);
+    sweep<n, 1, true>(w, Sm);
+    sweep<n, 0, true>(w, Sm);
+#pragma unroll
+    for (int q = 0; q < n3; ++q) sm.T[t * n3 + q] = w[q];
+    __syncthreads();
+    batch_scatter<R, P, NT>(a, sm.T, g, sm.off, c0, nc, ld, t);
+  }
+};
+
+// One work unit per workgroup, units dealt to XCDs in contiguous ranges.
+template <class Proc>
+__global__ __launch_bounds__(Proc::NT) void apply_grid_kernel(ApplyParams a) {
+  __shared__ typename Proc::Smem sm;
+  const int64_t unit = xcd_item(blockIdx.x, gridDim.x);
+  if (unit >= a.nitems * Proc::UPI) return;
+  Proc::run(a, a.items + unit / Proc::UPI, (int)(unit % Proc::UPI), sm);
+}
+
+// Persistent form: each workgroup pulls units from the queue of its XCD's
 // contiguous range, then from the other XCDs' ranges.  Every counter only
 // grows, so every workgroup leaves once all eight ranges are exhausted.
-template <typename R, int P>
-__global__ __launch_bounds__(64 * (P + 1)) void apply_queue_kernel(ApplyParams a) {
-  using Sh = Shape<R, P>;
-  __shared__ R T[64 * Sh::n3];
-  __shared__ int64_t s_off[27];
-  __shared__ int64_t s_item;
-  const int64_t per = (a.nitems + 7) >> 3;
+template <class Proc>
+__global__ __launch_bounds__(Proc::NT) void apply_queue_kernel(ApplyParams a) {
+  __shared__ typename Proc::Smem sm;
+  __shared__ int64_t s_unit;
+  const int64_t nunits = a.nitems * Proc::UPI;
+  const int64_t per = (nunits + 7) >> 3;
   const int home = blockIdx.x & 7;
   for (int q = 0; q < 8; ++q) {
     const int xcd = (home + q) & 7;
     const int64_t lo = xcd * per;
-    const int64_t hi = min(a.nitems, lo + per);
+    const int64_t hi = min(nunits, lo + per);
     while (true) {
       __syncthreads();
-      if (threadIdx.x == 0) {
-        const int64_t k = atomicAdd(a.counters + xcd, 1);
-        s_item = lo + k;
-      }
+      if (threadIdx.x == 0) s_unit = lo + atomicAdd(a.counters + xcd, 1);
       __syncthreads();
-      const int64_t item = s_item;
-      if (item >= hi) break;
-      apply_item<R, P>(a, a.items + item, T, s_off);
+      const int64_t unit = s_unit;
+      if (unit >= hi) break;
+      Proc::run(a, a.items + unit / Proc::UPI, (int)(unit % Proc::UPI), sm);
     }
   }
 }
@@ -300,28 +512,66 @@ __global__ void fill_zero_kernel(double* __restrict__ p, int64_t n, int32_t* cou
 }
 
 // -------------------------------------------------------------- overlap
-// Stage 1: one wave per block product X_{r,C1}^T Y_{r,C2}.  Lane (s, a)
-// walks rows s, s+R, ... of the row block (R = 64 / |C1|) and keeps the
-// |C2| products of column a; the R partial rows are summed in LDS in a
-// fixed order.
-constexpr int kTmWaves = 4;
-__global__ __launch_bounds__(64 * kTmWaves) void tm_stage1_kernel(TmParams p) {
-  __shared__ double red[kTmWaves][64][17];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t u = (int64_t)blockIdx.x * kTmWaves + wv;
-  const bool valid = u < p.nunits;
-  TmUnit U;
-  if (valid) U = p.units[u];
-  else U = TmUnit{0, 0, 0, 0, 1, 1, 0};
+// Stage 1: one wave per block product P = X_{r,C1}^T Y_{r,C2} (Alg. 8).
+//  * |C1| = |C2| = 8: lane i takes rows i, i+64, ... and keeps the 64
+//    products of its rows in registers; a butterfly reduce-scatter across the
+//    wave leaves entry j of P in lane j.
+//  * other widths: lane (s, a) walks rows s, s+R, ... (R = 64 / |C1|) and
+//    keeps the |C2| products of column a; the R partial rows are summed in
+//    LDS in a fixed order.
+// Both orders are fixed, so the result is bitwise reproducible.
+__device__ __forceinline__ double shfl_xor_d(double v, int m) {
+  return __shfl_xor(v, m, 64);
+}
+
+__global__ __launch_bounds__(64) void tm_stage1_kernel(TmParams p) {
+  __shared__ double red[64][17];
+  const int lane = threadIdx.x;
+  const int64_t u = blockIdx.x;
+  const TmUnit U = p.units[u];
+  const double* __restrict__ X = p.X + U.off1;
+  const double* __restrict__ Y = p.Y + U.off2;
+  if (U.w1 == 8 && U.w2 == 8 && ((U.off1 | U.off2) & 1) == 0) {
+    double acc[64];
+#pragma unroll
+    for (int j = 0; j < 64; ++j) acc[j] = 0.0;
+    for (int i = lane; i < U.rows; i += 64) {
+      const double2* __restrict__ x2 = reinterpret_cast<const double2*>(X + (int64_t)i * 8);
+      const double2* __restrict__ y2 = reinterpret_cast<const double2*>(Y + (int64_t)i * 8);
+      double x[8], y[8];
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const double2 a = x2[h], b = y2[h];
+        x[2 * h] = a.x; x[2 * h + 1] = a.y;
+        y[2 * h] = b.x; y[2 * h + 1] = b.y;
+      }
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) acc[a * 8 + b] = __builtin_fma(x[a], y[b], acc[a * 8 + b]);
+    }
+    // reduce-scatter: after the step with mask m a lane keeps the m entries
+    // whose index bit log2(m) equals its own lane bit.
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      const bool hi = (lane & m) != 0;
+#pragma unroll
+      for (int j = 0; j < m; ++j) {
+        const double keep = hi ? acc[j + m] : acc[j];
+        const double send = hi ? acc[j] : acc[j + m];
+        acc[j] = keep + shfl_xor_d(send, m);
+      }
+    }
+    p.part[U.part + lane] = acc[0];
+    return;
+  }
   const int w1 = U.w1, w2 = U.w2;
   const int R = 64 / w1;
   const int s = lane / w1, col = lane - s * w1;
   double acc[16];
 #pragma unroll
   for (int b = 0; b < 16; ++b) acc[b] = 0.0;
-  if (valid && s < R) {
-    const double* __restrict__ X = p.X + U.off1;
-    const double* __restrict__ Y = p.Y + U.off2;
+  if (s < R) {
     for (int i = s; i < U.rows; i += R) {
       const double x = X[(int64_t)i * w1 + col];
       const double* __restrict__ y = Y + (int64_t)i * w2;
@@ -331,69 +581,149 @@ __global__ __launch_bounds__(64 * kTmWaves) void tm_stage1_kernel(TmParams p) {
     }
   }
 #pragma unroll
-  for (int b = 0; b < 16; ++b) red[wv][lane][b] = acc[b];
+  for (int b = 0; b < 16; ++b) red[lane][b] = acc[b];
   __syncthreads();
-  if (valid) {
-    for (int idx = lane; idx < w1 * w2; idx += 64) {
-      const int aa = idx / w2, bb = idx - aa * w2;
-      double sum = 0.0;
-      for (int g = 0; g < R; ++g) sum += red[wv][g * w1 + aa][bb];
-      p.part[U.part + idx] = sum;
+  for (int idx = lane; idx < w1 * w2; idx += 64) {
+    const int aa = idx / w2, bb = idx - aa * w2;
+    double sum = 0.0;
+    for (int g = 0; g < R; ++g) sum += red[g * w1 + aa][bb];
+    p.part[U.part + idx] = sum;
+  }
+}
+
+// Stage 2: one workgroup per block (C1, C2) of S.  Thread groups split the
+// block's run of partial products and are combined in a fixed order; blocks
+// outside the product pattern are written as zeros.
+__global__ __launch_bounds__(256) void tm_stage2_kernel(TmParams p) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  const int C1 = blockIdx.x / p.ncb, C2 = blockIdx.x - C1 * p.ncb;
+  const int c1 = p.cb_start[C1], c2 = p.cb_start[C2];
+  const int w1 = p.cb_start[C1 + 1] - c1, w2 = p.cb_start[C2 + 1] - c2;
+  const int E = w1 * w2;
+  const int G = 256 / E;
+  const int g = t / E, e = t - g * E;
+  const int pid = p.pair_tab[(int64_t)C1 * p.ncb + C2];
+  double sum = 0.0;
+  if (pid >= 0 && g < G) {
+    // the pair's n partial products lie back to back: part[base + k E + e]
+    const int n = p.pair_ptr[pid + 1] - p.pair_ptr[pid];
+    const double* __restrict__ src = p.part + p.pair_list[pid] + e;
+    int k = g;
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (; k + 3 * G < n; k += 4 * G) {
+      sum += src[(int64_t)k * E];
+      s1 += src[(int64_t)(k + G) * E];
+      s2 += src[(int64_t)(k + 2 * G) * E];
+      s3 += src[(int64_t)(k + 3 * G) * E];
+    }
+    for (; k < n; k += G) sum += src[(int64_t)k * E];
+    sum = (sum + s1) + (s2 + s3);
+  }
+  red[t] = sum;
+  __syncthreads();
+  if (t < E) {
+    double tot = 0.0;
+    for (int q = 0; q < G; ++q) tot += red[q * E + t];
+    const int a = t / w2, b = t - (t / w2) * w2;
+    p.S[(int64_t)(c1 + a) * p.M + (c2 + b)] = tot;
+  }
+}
+
+// Stage 3: trace of S (its diagonal) with a fixed-shape tree reduction.
+__global__ __launch_bounds__(256) void tm_trace_kernel(TmParams p) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  double d = 0.0;
+  for (int al = t; al < p.M; al += 256) d += p.S[(int64_t)al * p.M + al];
+  red[t] = d;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
+  }
+  if (t == 0) *p.trace = red[0];
+}
+
+// Shell items: batches whose own block is not stored for C.  One wave reads
+// the values the item would gather (the stored rows of its neighbours'
+// blocks); only when one of them is non-zero does it run the single-wave
+// operator (RegProc for p = 2, CellProc over the 8 cells for p = 4).  For
+// orbital-supported inputs all of them are zero and the item ends here.
+template <typename R, int P>
+__global__ __launch_bounds__(64) void apply_shell_kernel(ApplyParams a) {
+  using D = Dims<P>;
+  using Proc = typename std::conditional<P == 2, RegProc<R, P>, CellProc<R, P>>::type;
+  __shared__ typename Proc::Smem sm;
+  const int64_t k = xcd_item(blockIdx.x, gridDim.x);
+  if (k >= a.nshell) return;
+  const ApplyItem* __restrict__ it = a.shell + k;
+  const int t = threadIdx.x;
+  if (t < 27) sm.off[t] = it->off[t];
+  const int rank = it->rank, c0 = it->c0, nc = it->nc, ld = it->ld;
+  __syncthreads();
+  const int32_t* __restrict__ g = a.gtab + (int64_t)rank * D::NB3;
+  bool any = false;
+  for (int v = t; v < D::NB3; v += 64) {
+    const int32_t ent = g[v];
+    if (ent < 0) continue;
+    const int64_t o = sm.off[ent >> 24];
+    if (o < 0) continue;
+    const double* __restrict__ x = a.X + o + (int64_t)(ent & 0xFFFFFF) * ld + c0;
+    for (int c = 0; c < nc; ++c) any |= (x[c] != 0.0);
+  }
+  if (!__syncthreads_or(any)) return;
+  if constexpr (P == 2) {
+    Proc::run(a, it, 0, sm);
+  } else {
+    for (int e = 0; e < 8; ++e) {
+      __syncthreads();
+      Proc::run(a, it, e, sm);
     }
   }
 }
 
-// Stage 2: every entry of S sums the partial products of its block pair in
-// row-block order; entries outside the product pattern are set to zero.
-__global__ __launch_bounds__(256) void tm_stage2_kernel(TmParams p) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t MM = (int64_t)p.M * p.M;
-  if (e >= MM) return;
-  const int al = (int)(e / p.M), be = (int)(e - (int64_t)al * p.M);
-  const int C1 = p.cb_of_col[al], C2 = p.cb_of_col[be];
-  const int pid = p.pair_tab[(int64_t)C1 * p.ncb + C2];
-  double sum = 0.0;
-  if (pid >= 0) {
-    const int a = al - p.cb_start[C1], b = be - p.cb_start[C2];
-    const int w2 = p.cb_start[C2 + 1] - p.cb_start[C2];
-    const int at = a * w2 + b;
-    for (int k = p.pair_ptr[pid]; k < p.pair_ptr[pid + 1]; ++k) sum += p.part[p.pair_list[k] + at];
-  }
-  p.S[e] = sum;
-}
-
-// Stage 3: trace of S with a fixed-shape tree reduction.
-__global__ __launch_bounds__(256) void tm_trace_kernel(TmParams p) {
-  __shared__ double red[256];
-  double s = 0.0;
-  for (int al = threadIdx.x; al < p.M; al += 256) s += p.S[(int64_t)al * p.M + al];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *p.trace = red[0];
-}
-
-template <typename R, int P>
-hipError_t launch_apply_t(const ApplyParams& p, int kernel, hipStream_t st) {
-  using Sh = Shape<R, P>;
-  if (p.nitems == 0) return hipSuccess;
-  if (kernel == 0) {
-    const int64_t nwg = ((p.nitems + 7) / 8) * 8;
-    hipLaunchKernelGGL((apply_grid_kernel<R, P>), dim3((unsigned)nwg), dim3(Sh::NT), 0, st, p);
+template <class Proc>
+hipError_t launch_proc(const ApplyParams& p, bool queue, hipStream_t st) {
+  const int64_t nunits = p.nitems * Proc::UPI;
+  if (nunits == 0) return hipSuccess;
+  if (!queue) {
+    const int64_t nwg = ((nunits + 7) / 8) * 8;
+    hipLaunchKernelGGL((apply_grid_kernel<Proc>), dim3((unsigned)nwg), dim3(Proc::NT), 0, st, p);
   } else {
     int grid = p.grid;
     if (grid <= 0) {
       int per_cu = 0;
       hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, reinterpret_cast<const void*>(&apply_queue_kernel<R, P>), Sh::NT, 0);
+          &per_cu, reinterpret_cast<const void*>(&apply_queue_kernel<Proc>), Proc::NT, 0);
       if (e != hipSuccess) return e;
       grid = std::max(1, per_cu) * std::max(1, device_cu_count());
     }
-    hipLaunchKernelGGL((apply_queue_kernel<R, P>), dim3((unsigned)grid), dim3(Sh::NT), 0, st, p);
+    hipLaunchKernelGGL((apply_queue_kernel<Proc>), dim3((unsigned)grid), dim3(Proc::NT), 0, st, p);
   }
+  return hipGetLastError();
+}
+
+// kernel: even = one work unit per workgroup, odd = persistent queue
+template <typename R, int P>
+hipError_t launch_apply_t(const ApplyParams& p, int kernel, hipStream_t st) {
+  const bool queue = (kernel & 1) != 0;
+  // processor: kernels 0/1 the default for the degree, 2/3 the batch
+  // processor, 4/5 the single-wave processor (RegProc for p = 2, CellProc
+  // for p = 4)
+  const int proc = kernel >> 1;
+  const bool batch = proc == 1 || (proc == 0 && P == 2);
+  hipError_t e;
+  if (batch) {
+    e = launch_proc<BatchProc<R, P>>(p, queue, st);
+  } else if constexpr (P == 2) {
+    e = launch_proc<RegProc<R, 2>>(p, queue, st);
+  } else {
+    e = launch_proc<CellProc<R, P>>(p, queue, st);
+  }
+  if (e != hipSuccess || p.nshell == 0) return e;
+  const int64_t nwg = ((p.nshell + 7) / 8) * 8;
+  hipLaunchKernelGGL((apply_shell_kernel<R, P>), dim3((unsigned)nwg), dim3(64), 0, st, p);
   return hipGetLastError();
 }
 
@@ -413,7 +743,7 @@ int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t
   {
     const int64_t blocks = std::min<int64_t>(4096, std::max<int64_t>(1, (nvalues / 2 + 255) / 256));
     hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p.Y, nvalues,
-                       kernel == 1 ? p.counters : nullptr);
+                       (kernel & 1) ? p.counters : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
   }
@@ -431,13 +761,12 @@ int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t
 int launch_tmmult(const TmParams& p, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   if (p.nunits > 0) {
-    const int64_t g1 = (p.nunits + kTmWaves - 1) / kTmWaves;
-    hipLaunchKernelGGL(tm_stage1_kernel, dim3((unsigned)g1), dim3(64 * kTmWaves), 0, st, p);
+    hipLaunchKernelGGL(tm_stage1_kernel, dim3((unsigned)p.nunits), dim3(64), 0, st, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
   }
-  const int64_t MM = (int64_t)p.M * p.M;
-  hipLaunchKernelGGL(tm_stage2_kernel, dim3((unsigned)((MM + 255) / 256)), dim3(256), 0, st, p);
+  const int64_t nblk = (int64_t)p.ncb * p.ncb;
+  hipLaunchKernelGGL(tm_stage2_kernel, dim3((unsigned)nblk), dim3(256), 0, st, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
   hipLaunchKernelGGL(tm_trace_kernel, dim3(1), dim3(256), 0, st, p);

@@ -13,8 +13,10 @@ namespace gpu {
 struct ApplyParams {
   const double* X;
   double* Y;
-  const ApplyItem* items;
+  const ApplyItem* items;   // items whose batch's own block is stored
   int64_t nitems;
+  const ApplyItem* shell;   // items of batches whose own block is not stored
+  int64_t nshell;
   const int32_t* gtab;   // [rank][ (2p+1)^3 ]
   const double* cV;      // [cell 8 rank + e][ (p+1)^3 ]
   int32_t* counters;     // 8 queue counters (persistent kernel only)
@@ -22,9 +24,7 @@ struct ApplyParams {
   int32_t pad;
   double S[25];          // S[q*n + k] = phi_k(xq_q)
   double Dco[25];        // collocation derivative on the Gauss points
-  double W2[25];         // W2[a*n + b] = w_a w_b
-  double w[5];           // 1D Gauss weights
-  double cg[3];          // 1/2 hx hy hz / h_d^2
+  const double* Wg;      // [3][ (p+1)^3 ]: 1/2 JxW_q / h_d^2 per direction d
 };
 
 struct TmParams {
@@ -34,8 +34,8 @@ struct TmParams {
   int64_t nunits;
   double* part;
   const int32_t* pair_tab;   // [ncb*ncb]
-  const int32_t* pair_ptr;   // [npairs+1]
-  const int64_t* pair_list;
+  const int32_t* pair_ptr;   // [npairs+1] prefix counts of partial products per pair
+  const int64_t* pair_list;  // [npairs] offset of each pair's contiguous partials
   const int32_t* cb_of_col;  // [M]
   const int32_t* cb_start;   // [ncb+1]
   int32_t M, ncb;
@@ -44,7 +44,8 @@ struct TmParams {
 };
 
 // prec: 0 fp64 VALU, 1 fp64 MFMA, 2 fp32 MFMA, 3 fp32 VALU.
-// kernel: 0 one item per workgroup, 1 persistent queue.
+// kernel: 0/1 default processor as grid/queue, 2/3 batch processor, 4/5
+// single-wave processor (register-resident for p = 2, per cell for p = 4).
 // Returns a hipError_t value (0 on success) or -2 for an unsupported variant.
 int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t nvalues,
                  void* stream);

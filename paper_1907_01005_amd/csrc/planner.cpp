@@ -423,6 +423,7 @@ void plan_mv(MvPlan& mv, const MeshPlan& m, int M, const double* centers, const 
   // non-Dirichlet node of the batch; one item per 8-column chunk of C.
   const int NB = m.NB, NB3 = NB * NB * NB, n = m.n;
   mv.items.clear();
+  std::vector<ApplyItem> shell;  // batches whose own block is not stored for C
   mv.apply_pairs = mv.apply_pairs_own = 0;
   mv.cell_colblocks.assign(m.ncells, 0);
   std::vector<int> mark(ncb, 0), list;
@@ -460,11 +461,12 @@ void plan_mv(MvPlan& mv, const MeshPlan& m, int M, const double* centers, const 
         offs[li][s] = it.off[s];
       }
       ++mv.apply_pairs;
-      if (mv.block_index(r, C) >= 0) ++mv.apply_pairs_own;
+      const bool own = mv.block_index(r, C) >= 0;
+      if (own) ++mv.apply_pairs_own;
       for (int c0 = 0; c0 < w[C]; c0 += 8) {
         it.c0 = c0;
         it.nc = std::min(8, w[C] - c0);
-        mv.items.push_back(it);
+        (own ? mv.items : shell).push_back(it);
       }
     }
     // non-empty column blocks per cell (Table 1, last row)
@@ -488,40 +490,61 @@ void plan_mv(MvPlan& mv, const MeshPlan& m, int M, const double* centers, const 
     }
   }
 
-  // overlap products (Alg. 8): every pair of stored blocks of a row block
+  // own items first, then the shell items (processed by a separate kernel)
+  mv.n_own_items = (int64_t)mv.items.size();
+  mv.items.insert(mv.items.end(), shell.begin(), shell.end());
+
+  // overlap products (Alg. 8): every pair of stored blocks of a row block.
+  // Partial products are stored pair by pair (row-block order within a
+  // pair), so that the second stage streams one contiguous run per block of S.
   mv.units.clear();
   mv.pair_tab.assign((size_t)ncb * ncb, -1);
-  std::vector<std::vector<int64_t>> per_pair;
+  std::vector<int64_t> pair_count;
+  for (int r = 0; r < nbt; ++r)
+    for (int64_t k1 = mv.rowptr[r]; k1 < mv.rowptr[r + 1]; ++k1)
+      for (int64_t k2 = mv.rowptr[r]; k2 < mv.rowptr[r + 1]; ++k2) {
+        int32_t& pid = mv.pair_tab[(size_t)mv.colidx[k1] * ncb + mv.colidx[k2]];
+        if (pid < 0) {
+          pid = (int32_t)pair_count.size();
+          pair_count.push_back(0);
+        }
+        ++pair_count[pid];
+      }
+  const int npairs = (int)pair_count.size();
+  std::vector<int32_t> pair_c1(npairs), pair_c2(npairs);
+  for (int C1 = 0; C1 < ncb; ++C1)
+    for (int C2 = 0; C2 < ncb; ++C2) {
+      const int32_t pid = mv.pair_tab[(size_t)C1 * ncb + C2];
+      if (pid >= 0) { pair_c1[pid] = C1; pair_c2[pid] = C2; }
+    }
+  // pair_ptr: first unit slot of each pair; pair_list[pid] = partial base
+  mv.pair_ptr.assign(npairs + 1, 0);
+  mv.pair_list.assign(npairs, 0);
   int64_t part = 0;
+  for (int pid = 0; pid < npairs; ++pid) {
+    mv.pair_ptr[pid + 1] = mv.pair_ptr[pid] + (int32_t)pair_count[pid];
+    mv.pair_list[pid] = part;
+    part += pair_count[pid] * (int64_t)w[pair_c1[pid]] * w[pair_c2[pid]];
+  }
+  mv.part_doubles = part;
+  std::vector<int64_t> fill(npairs, 0);
   for (int r = 0; r < nbt; ++r) {
     const int64_t rows = m.rb_start[r + 1] - m.rb_start[r];
     for (int64_t k1 = mv.rowptr[r]; k1 < mv.rowptr[r + 1]; ++k1)
       for (int64_t k2 = mv.rowptr[r]; k2 < mv.rowptr[r + 1]; ++k2) {
         const int C1 = mv.colidx[k1], C2 = mv.colidx[k2];
+        const int32_t pid = mv.pair_tab[(size_t)C1 * ncb + C2];
+        const int64_t E = (int64_t)w[C1] * w[C2];
         TmUnit u;
         u.off1 = mv.block_offset[k1];
         u.off2 = mv.block_offset[k2];
-        u.part = part;
+        u.part = mv.pair_list[pid] + fill[pid]++ * E;
         u.rows = (int32_t)rows;
         u.w1 = w[C1];
         u.w2 = w[C2];
         u.pad = 0;
         mv.units.push_back(u);
-        int32_t& pid = mv.pair_tab[(size_t)C1 * ncb + C2];
-        if (pid < 0) {
-          pid = (int32_t)per_pair.size();
-          per_pair.emplace_back();
-        }
-        per_pair[pid].push_back(part);
-        part += (int64_t)w[C1] * w[C2];
       }
-  }
-  mv.part_doubles = part;
-  mv.pair_ptr.assign(per_pair.size() + 1, 0);
-  mv.pair_list.clear();
-  for (size_t i = 0; i < per_pair.size(); ++i) {
-    mv.pair_list.insert(mv.pair_list.end(), per_pair[i].begin(), per_pair[i].end());
-    mv.pair_ptr[i + 1] = (int32_t)mv.pair_list.size();
   }
 }
 

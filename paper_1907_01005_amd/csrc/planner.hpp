@@ -103,13 +103,14 @@ struct MvPlan {
   std::vector<int64_t> rowptr;       // nbatch + 1
   std::vector<int32_t> colidx;
   std::vector<int64_t> block_offset; // nblocks + 1
-  std::vector<ApplyItem> items;
+  std::vector<ApplyItem> items;      // own items (batch's own block stored) then shell items
+  int64_t n_own_items = 0;
   int64_t apply_pairs = 0, apply_pairs_own = 0;
   std::vector<TmUnit> units;
   int64_t part_doubles = 0;
   std::vector<int32_t> pair_tab;     // ncb*ncb -> pair id or -1
-  std::vector<int32_t> pair_ptr;     // npairs + 1
-  std::vector<int64_t> pair_list;    // partial offsets per pair, in row-block order
+  std::vector<int32_t> pair_ptr;     // npairs + 1: prefix count of partial products per pair
+  std::vector<int64_t> pair_list;    // npairs: offset of the pair's contiguous partials
   // cell statistics
   std::vector<int32_t> cell_colblocks; // per library cell: non-empty column blocks
   int64_t block_index(int r, int C) const;  // -1 if (r, C) not stored
