@@ -233,7 +233,7 @@ int mfb_apply_H(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X, doubl
 /* Same result through an explicitly configured kernel (used by the
  * autotuner).  kernel: even values launch one work unit per workgroup, odd
  * values launch persistent workgroups that pull units from a queue; kernel/2
- * selects how a unit maps onto threads: 0 = the default for the degree,
+ * selects how a unit maps onto threads: 0 = the default (currently 1),
  * 1 = a workgroup of 64(p+1) threads per (batch, 8-column chunk) with LDS
  * layout switches, 2 = one wave per unit (p = 2: the whole cell tensor in
  * registers; p = 4: one wave per cell).  grid: persistent workgroups (0 =

@@ -390,6 +390,8 @@ static void fill_apply_params(const mfb_mesh* mesh, const mfb_mv* mv, const doub
   for (int i = 0; i < n * n; ++i) {
     a.S[i] = b.S[i];
     a.Dco[i] = b.Dco[i];
+    a.Sf[i] = (float)b.S[i];
+    a.Df[i] = (float)b.Dco[i];
   }
 }
 

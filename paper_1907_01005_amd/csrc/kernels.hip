@@ -70,6 +70,20 @@ __device__ __forceinline__ void contract_add(const R* __restrict__ M, const R (&
     }
 }
 
+// The 1D tables in the contraction type (kernel arguments, uniform).
+template <typename R>
+__device__ __forceinline__ const R* tab_S(const ApplyParams& a);
+template <>
+__device__ __forceinline__ const double* tab_S<double>(const ApplyParams& a) { return a.S; }
+template <>
+__device__ __forceinline__ const float* tab_S<float>(const ApplyParams& a) { return a.Sf; }
+template <typename R>
+__device__ __forceinline__ const R* tab_D(const ApplyParams& a);
+template <>
+__device__ __forceinline__ const double* tab_D<double>(const ApplyParams& a) { return a.Dco; }
+template <>
+__device__ __forceinline__ const float* tab_D<float>(const ApplyParams& a) { return a.Df; }
+
 // Workgroup index -> item index so that each XCD (workgroups are dealt to
 // the 8 XCDs round robin) walks one contiguous, Hilbert-ordered range.
 __device__ __forceinline__ int64_t xcd_item(int64_t wg, int64_t nwg) {
@@ -129,18 +143,15 @@ __device__ __forceinline__ bool gather_plane(const ApplyParams& a, const int32_t
 // Sum-factorised cell operator on planes.  On entry u holds the z = pl plane
 // of the nodal values (layout A); on exit Tc holds the cell's output values
 // (index i + n j + n^2 k).  Threads with act == false only join the barriers.
-template <typename R, int P>
+template <typename R, int P, class Hook>
 __device__ __forceinline__ void plane_operator(const ApplyParams& a, R* __restrict__ Tc, int pl,
                                                const double* __restrict__ cv, bool act,
-                                               const R (&u)[P + 1][P + 1]) {
+                                               const R (&u)[P + 1][P + 1], R (&out)[P + 1][P + 1],
+                                               Hook after_first_barrier) {
   using D = Dims<P>;
   constexpr int n = D::n, n2 = D::n2, n3 = D::n3;
-  R Sm[n * n], Dm[n * n];
-#pragma unroll
-  for (int i = 0; i < n * n; ++i) {
-    Sm[i] = (R)a.S[i];
-    Dm[i] = (R)a.Dco[i];
-  }
+  const R* __restrict__ Sm = tab_S<R>(a);
+  const R* __restrict__ Dm = tab_D<R>(a);
   const double* __restrict__ wg = a.Wg;
   R A[n][n], B[n][n];
   contract<n, 0, false>(Sm, u, A);
@@ -152,6 +163,7 @@ __device__ __forceinline__ void plane_operator(const ApplyParams& a, R* __restri
       for (int i = 0; i < n; ++i) Tc[i + n * j + n2 * pl] = B[i][j];
   }
   __syncthreads();
+  after_first_barrier();
   // layout B: plane y = pl
   if (act) {
 #pragma unroll
@@ -233,15 +245,7 @@ __device__ __forceinline__ void plane_operator(const ApplyParams& a, R* __restri
       for (int i = 0; i < n; ++i) A[i][j] = Tc[i + n * j + n2 * pl];
   }
   contract<n, 1, true>(Sm, A, B);
-  contract<n, 0, true>(Sm, B, A);
-  __syncthreads();
-  if (act) {
-#pragma unroll
-    for (int j = 0; j < n; ++j)
-#pragma unroll
-      for (int i = 0; i < n; ++i) Tc[i + n * j + n2 * pl] = A[i][j];
-  }
-  __syncthreads();
+  contract<n, 0, true>(Sm, B, out);
 }
 
 // Sum the 8 cell results of a batch per batch node (T holds cell-column
@@ -294,24 +298,89 @@ template <typename R, int P>
 struct BatchProc {
   using D = Dims<P>;
   static constexpr int NT = 64 * D::n, UPI = 1;
-  struct Smem {
+  static constexpr int NV = D::NB3 * 8, K = (NV + NT - 1) / NT;
+  // p = 4: the gather/sum buffer shares the storage of the transpose tiles
+  // (three more barriers, half the LDS); p = 2: separate buffers.
+  static constexpr bool ALIAS = P >= 4;
+  struct SepBuf {
     R T[64 * D::n3];
+    double G[NV];
+  };
+  union AliasBuf {
+    R T[64 * D::n3];
+    double G[NV];
+  };
+  struct Smem {
+    typename std::conditional<ALIAS, AliasBuf, SepBuf>::type b;
     int64_t off[27];
   };
   static __device__ __forceinline__ void run(const ApplyParams& a,
                                              const ApplyItem* __restrict__ it, int, Smem& sm) {
+    constexpr int n = D::n, NB = D::NB;
     const int t = threadIdx.x;
-    const int c = t & 7, e = (t >> 3) & 7, pl = t >> 6;
+    const int c = t & 7, e = (t >> 3) & 7;
+    const int pl = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
     if (t < 27) sm.off[t] = it->off[t];
     const int rank = it->rank, c0 = it->c0, nc = it->nc, ld = it->ld;
     __syncthreads();
     const int32_t* __restrict__ g = a.gtab + (int64_t)rank * D::NB3;
-    R u[D::n][D::n];
-    const bool any = gather_plane<R, P>(a, g, sm.off, e, pl, c, c0, nc, ld, true, u);
+    double* __restrict__ G = sm.b.G;
+    R* __restrict__ Gr = reinterpret_cast<R*>(G);
+    // coalesced gather of the batch's (node, column) values
+    int32_t ent[K];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int idx = t + k * NT;
+      ent[k] = -1;
+      double x = 0.0;
+      if (idx < NV && (idx & 7) < nc) {
+        const int32_t en = g[idx >> 3];
+        if (en >= 0 && sm.off[en >> 24] >= 0) {
+          ent[k] = en;
+          x = a.X[sm.off[en >> 24] + (int64_t)(en & 0xFFFFFF) * ld + c0 + (idx & 7)];
+        }
+      }
+      if (idx < NV) Gr[idx] = (R)x;
+      any |= (x != 0.0);
+    }
     if (!__syncthreads_or(any)) return;
-    plane_operator<R, P>(a, sm.T + (t & 63) * D::n3, pl,
-                         a.cV + ((int64_t)rank * 8 + e) * D::n3, true, u);
-    batch_scatter<R, P, NT>(a, sm.T, g, sm.off, c0, nc, ld, t);
+    R u[n][n];
+    const int base = ((ex * P) + NB * ((ey * P) + NB * (ez * P + pl))) * 8 + c;
+#pragma unroll
+    for (int j = 0; j < n; ++j)
+#pragma unroll
+      for (int i = 0; i < n; ++i) u[i][j] = Gr[base + (i + NB * j) * 8];
+    auto zero_sums = [&]() {
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (t + k * NT < NV) G[t + k * NT] = 0.0;
+    };
+    R out[n][n];
+    const double* cv = a.cV + ((int64_t)rank * 8 + e) * D::n3;
+    if constexpr (ALIAS) {
+      __syncthreads();
+      plane_operator<R, P>(a, sm.b.T + (t & 63) * D::n3, pl, cv, true, u, out, []() {});
+      __syncthreads();
+      zero_sums();
+      __syncthreads();
+    } else {
+      // every thread has read its plane by the first barrier: reuse G for the sums
+      plane_operator<R, P>(a, sm.b.T + (t & 63) * D::n3, pl, cv, true, u, out, zero_sums);
+    }
+#pragma unroll
+    for (int j = 0; j < n; ++j)
+#pragma unroll
+      for (int i = 0; i < n; ++i) unsafeAtomicAdd(&G[base + (i + NB * j) * 8], (double)out[i][j]);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (ent[k] < 0) continue;
+      const int idx = t + k * NT;
+      unsafeAtomicAdd(a.Y + sm.off[ent[k] >> 24] + (int64_t)(ent[k] & 0xFFFFFF) * ld + c0 + (idx & 7),
+                      G[idx]);
+    }
   }
 };
 
@@ -325,32 +394,35 @@ struct CellProc {
   };
   static __device__ __forceinline__ void run(const ApplyParams& a,
                                              const ApplyItem* __restrict__ it, int e, Smem& sm) {
-    constexpr int n = D::n, n2 = D::n2, n3 = D::n3, NB = D::NB;
+    constexpr int n = D::n, n3 = D::n3, NB = D::NB;
     const int t = threadIdx.x;
-    const int c = t & 7, pl = t >> 3;
+    const int c = t & 7;
+    const int pl = t >> 3;  // varies within the wave
     const bool act = pl < n;
+    const int pq = act ? pl : 0;
     if (t < 27) sm.off[t] = it->off[t];
     const int rank = it->rank, c0 = it->c0, nc = it->nc, ld = it->ld;
     __syncthreads();
     const int32_t* __restrict__ g = a.gtab + (int64_t)rank * D::NB3;
     R u[n][n];
-    const bool any = gather_plane<R, P>(a, g, sm.off, e, act ? pl : 0, c, c0, nc, ld, act, u);
+    const bool any = gather_plane<R, P>(a, g, sm.off, e, pq, c, c0, nc, ld, act, u);
     if (!__syncthreads_or(any)) return;
-    plane_operator<R, P>(a, sm.T + c * n3, act ? pl : 0,
-                         a.cV + ((int64_t)rank * 8 + e) * n3, act, u);
+    R out[n][n];
+    plane_operator<R, P>(a, sm.T + c * n3, pq, a.cV + ((int64_t)rank * 8 + e) * n3, act, u, out,
+                         []() {});
+    if (!act || c >= nc) return;
     const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
-    for (int idx = t; idx < n3 * 8; idx += 64) {
-      const int col = idx & 7, loc = idx >> 3;
-      if (col >= nc) continue;
-      const int lx = loc % n, ly = (loc / n) % n, lz = loc / n2;
-      const int v = (ex * P + lx) + NB * ((ey * P + ly) + NB * (ez * P + lz));
-      const int32_t ent = g[v];
-      if (ent < 0) continue;
-      const int64_t o = sm.off[ent >> 24];
-      if (o < 0) continue;
-      unsafeAtomicAdd(a.Y + o + (int64_t)(ent & 0xFFFFFF) * ld + c0 + col,
-                      (double)sm.T[col * n3 + loc]);
-    }
+#pragma unroll
+    for (int j = 0; j < n; ++j)
+#pragma unroll
+      for (int i = 0; i < n; ++i) {
+        const int v = (ex * P + i) + NB * ((ey * P + j) + NB * (ez * P + pq));
+        const int32_t ent = g[v];
+        if (ent < 0) continue;
+        const int64_t o = sm.off[ent >> 24];
+        if (o < 0) continue;
+        unsafeAtomicAdd(a.Y + o + (int64_t)(ent & 0xFFFFFF) * ld + c0 + c, (double)out[i][j]);
+      }
   }
 };
 
@@ -401,12 +473,12 @@ __device__ __forceinline__ void grad_pass(const R (&uq)[n * n * n], R (&w)[n * n
   }
 }
 
-template <typename R, int P>
+template <typename R, int P, bool LDS_SUM = true>
 struct RegProc {
   using D = Dims<P>;
   static constexpr int NT = 64, UPI = 1;
   struct Smem {
-    R T[64 * D::n3];
+    R T[LDS_SUM ? 64 * D::n3 : 1];
     int64_t off[27];
   };
   static __device__ __forceinline__ void run(const ApplyParams& a,
@@ -440,12 +512,8 @@ struct RegProc {
           any |= (x != 0.0);
         }
     if (!__syncthreads_or(any)) return;
-    R Sm[n * n], Dm[n * n];
-#pragma unroll
-    for (int i = 0; i < n * n; ++i) {
-      Sm[i] = (R)a.S[i];
-      Dm[i] = (R)a.Dco[i];
-    }
+    const R* __restrict__ Sm = tab_S<R>(a);
+    const R* __restrict__ Dm = tab_D<R>(a);
     sweep<n, 0, false>(u, Sm);
     sweep<n, 1, false>(u, Sm);
     sweep<n, 2, false>(u, Sm);
@@ -459,10 +527,28 @@ struct RegProc {
     sweep<n, 2, true>(w, Sm);
     sweep<n, 1, true>(w, Sm);
     sweep<n, 0, true>(w, Sm);
+    if constexpr (LDS_SUM) {
 #pragma unroll
-    for (int q = 0; q < n3; ++q) sm.T[t * n3 + q] = w[q];
-    __syncthreads();
-    batch_scatter<R, P, NT>(a, sm.T, g, sm.off, c0, nc, ld, t);
+      for (int q = 0; q < n3; ++q) sm.T[t * n3 + q] = w[q];
+      __syncthreads();
+      batch_scatter<R, P, NT>(a, sm.T, g, sm.off, c0, nc, ld, t);
+    } else {
+      if (c >= nc) return;
+#pragma unroll
+      for (int k = 0; k < n; ++k)
+#pragma unroll
+        for (int j = 0; j < n; ++j)
+#pragma unroll
+          for (int i = 0; i < n; ++i) {
+            const int v = (ex * P + i) + NB * ((ey * P + j) + NB * (ez * P + k));
+            const int32_t ent = g[v];
+            if (ent < 0) continue;
+            const int64_t o = sm.off[ent >> 24];
+            if (o < 0) continue;
+            unsafeAtomicAdd(a.Y + o + (int64_t)(ent & 0xFFFFFF) * ld + c0 + c,
+                            (double)w[i + n * j + n2 * k]);
+          }
+    }
   }
 };
 
@@ -647,13 +733,13 @@ __global__ __launch_bounds__(256) void tm_trace_kernel(TmParams p) {
 
 // Shell items: batches whose own block is not stored for C.  One wave reads
 // the values the item would gather (the stored rows of its neighbours'
-// blocks); only when one of them is non-zero does it run the single-wave
-// operator (RegProc for p = 2, CellProc over the 8 cells for p = 4).  For
-// orbital-supported inputs all of them are zero and the item ends here.
+// blocks); only when one of them is non-zero does it run the operator, one
+// cell at a time.  For orbital-supported inputs all of them are zero and
+// the item ends after the check.
 template <typename R, int P>
-__global__ __launch_bounds__(64) void apply_shell_kernel(ApplyParams a) {
+__global__ __launch_bounds__(64, P == 2 ? 4 : 2) void apply_shell_kernel(ApplyParams a) {
   using D = Dims<P>;
-  using Proc = typename std::conditional<P == 2, RegProc<R, P>, CellProc<R, P>>::type;
+  using Proc = CellProc<R, P>;
   __shared__ typename Proc::Smem sm;
   const int64_t k = xcd_item(blockIdx.x, gridDim.x);
   if (k >= a.nshell) return;
@@ -673,13 +759,9 @@ __global__ __launch_bounds__(64) void apply_shell_kernel(ApplyParams a) {
     for (int c = 0; c < nc; ++c) any |= (x[c] != 0.0);
   }
   if (!__syncthreads_or(any)) return;
-  if constexpr (P == 2) {
-    Proc::run(a, it, 0, sm);
-  } else {
-    for (int e = 0; e < 8; ++e) {
-      __syncthreads();
-      Proc::run(a, it, e, sm);
-    }
+  for (int e = 0; e < 8; ++e) {
+    __syncthreads();
+    Proc::run(a, it, e, sm);
   }
 }
 
@@ -712,7 +794,7 @@ hipError_t launch_apply_t(const ApplyParams& p, int kernel, hipStream_t st) {
   // processor, 4/5 the single-wave processor (RegProc for p = 2, CellProc
   // for p = 4)
   const int proc = kernel >> 1;
-  const bool batch = proc == 1 || (proc == 0 && P == 2);
+  const bool batch = proc <= 1;
   hipError_t e;
   if (batch) {
     e = launch_proc<BatchProc<R, P>>(p, queue, st);

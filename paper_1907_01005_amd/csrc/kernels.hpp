@@ -24,6 +24,8 @@ struct ApplyParams {
   int32_t pad;
   double S[25];          // S[q*n + k] = phi_k(xq_q)
   double Dco[25];        // collocation derivative on the Gauss points
+  float Sf[25];          // float copies of S and Dco for the float contractions
+  float Df[25];
   const double* Wg;      // [3][ (p+1)^3 ]: 1/2 JxW_q / h_d^2 per direction d
 };
 
