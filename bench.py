@@ -99,16 +99,80 @@ def measured_traffic(workload: str, prec: str):
     return rec.get("apply_H_bytes_per_launch")
 
 
-def build_problem(cfg: int):
+def build_problem(cfg: int, mesh_index: int = 0):
     import synth
     from paper_1907_01005_amd.problem import DeviceProblem
     wl = synth.make_workload(cfg)
-    ms = wl.mesh
+    ms = wl.meshes[mesh_index]
     dp = DeviceProblem((ms.nx, ms.ny, ms.nz), ms.L, ms.degree, ms.dirichlet, wl.centres,
                        wl.radius, wl.colblock_sizes, lambda P: synth.potential_at(wl, P))
-    node, orb, val = synth.orbital_values(wl)
+    node, orb, val = synth.orbital_values(wl, mesh_index)
     dp.set_X_coo(node, orb, val)
     return wl, dp
+
+
+def graph_form(dp, prec: int, n: int = 20, reps: int = 5):
+    """Autotuned kernel, n iterations of apply_H + tmmult in one hipGraph."""
+    import torch
+    from paper_1907_01005_amd.autotune import GraphLoop, tune
+    choice = tune(dp, prec, iters=10, warmup=2)
+    loop = GraphLoop(dp, choice, n=n)
+    loop.replay()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        loop.replay()
+        b.record()
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b) * 1e-3 / n)
+    it = float(np.median(times))
+    return {"tuned": choice.describe(), "iter_ms": it * 1e3,
+            "gdofcols_s": dp.nvalues / it / 1e9, "iterations_per_graph": n}
+
+
+def config4_forms():
+    """640 orbitals in uneven column blocks on the 1686177-DoF Q2 and Q4 meshes:
+    autotuned kernels, hipGraph of 20 iterations, fp32-MFMA operator with fp64
+    overlap, error against the fp64 operator on the same GPU."""
+    import torch
+    out = {}
+    for mi, tag in ((0, "Q2"), (1, "Q4")):
+        print(f"[bench] config 4 mesh {tag}", file=sys.stderr, flush=True)
+        wl, dp = build_problem(4, mi)
+        rec = {"workload": f"{wl.meshes[mi].nx}x{wl.meshes[mi].ny}x{wl.meshes[mi].nz}-{tag}",
+               "stored_entries": dp.nvalues, "colblock_sizes": [int(wl.colblock_sizes.min()),
+                                                               int(wl.colblock_sizes.max())]}
+        dp.apply(0)
+        dp.overlap()
+        torch.cuda.synchronize()
+        Y64 = dp.Y.clone()
+        S64 = dp.S.clone()
+        t64 = dp.trace.clone()
+        rec["fp64"] = graph_form(dp, 0)
+        rec["fp32-mfma"] = graph_form(dp, 2)
+        dp.apply(2)
+        dp.overlap()
+        torch.cuda.synchronize()
+        rec["fp32-mfma"]["rel_err_Y"] = float((dp.Y - Y64).norm() / Y64.norm())
+        rec["fp32-mfma"]["rel_err_S"] = float((dp.S - S64).norm() / S64.norm())
+        rec["fp32-mfma"]["rel_err_trace"] = float(((dp.trace - t64).abs() / t64.abs()).item())
+        rec["fp32-mfma"]["speedup_vs_fp64"] = rec["fp64"]["iter_ms"] / rec["fp32-mfma"]["iter_ms"]
+        out[tag] = rec
+        del dp
+    return out
+
+
+def serving_form(n: int, budget_mb: int):
+    from paper_1907_01005_amd.serving import GpuExecutor, Server, request_stream, summarize
+    reqs = request_stream(n=n)
+    ex = GpuExecutor(planner_threads=8)
+    rep = Server(ex, byte_budget=budget_mb << 20, max_slots=8).run(reqs)
+    s = summarize(rep)
+    s.update({"requests": n, "rate_per_s": 40.0, "byte_budget_mb": budget_mb})
+    return s
 
 
 def time_path(dp, prec: int, steps: int, warmup: int, kernel: int = 0):
@@ -157,6 +221,11 @@ def main(argv=None):
     ap.add_argument("--kernel", type=int, default=0, choices=[0, 1])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--config4", action="store_true",
+                    help="also run the 640-orbital uneven-block workload (tuned + hipGraph)")
+    ap.add_argument("--serve", type=int, default=0, metavar="N",
+                    help="also run the serving stream with N requests")
+    ap.add_argument("--serve-budget-mb", type=int, default=1024)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args(argv)
@@ -226,7 +295,7 @@ def main(argv=None):
     }
     if not args.no_forms:
         forms = {}
-        for name in ("fp32",):
+        for name in ("fp32", "fp32-mfma"):
             try:
                 _, ta, _ = time_path(dp, PRECS[name], 50, 5)
                 forms[name] = {"apply_ms_mean": float(np.mean(ta) * 1e3),
@@ -235,7 +304,14 @@ def main(argv=None):
                 forms[name] = {"error": str(e)}
         _, ta, _ = time_path(dp, prec, 50, 5, kernel=1)
         forms["queue-kernel"] = {"apply_ms_mean": float(np.mean(ta) * 1e3)}
+        forms["graph20-" + args.prec] = graph_form(dp, prec)
+        forms["graph20-fp32-mfma"] = graph_form(dp, PRECS["fp32-mfma"])
         out["forms"] = forms
+    if args.config4:
+        out["config4"] = config4_forms()
+    if args.serve:
+        print(f"[bench] serving {args.serve} requests", file=sys.stderr, flush=True)
+        out["serving"] = serving_form(args.serve, args.serve_budget_mb)
     if args.copy_calibration:
         src = torch.ones(args.copy_calibration << 17, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)

@@ -257,6 +257,16 @@ int mfb_apply_H_tuned(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X,
 int mfb_tmmult(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d_S,
                double* d_trace, void* d_work, void* stream);
 
+/* Column-scaled update on the stored entries of X, the iteration of the
+ * serving loop: X <- X - tau (Y - X diag(S) / diag(S2)), where column c of X
+ * is scaled by S[c][c] / S2[c][c] (0 when S2[c][c] == 0).  S and S2 are M x M
+ * as written by mfb_tmmult (for instance S = X^T Y and S2 = X^T X), so each
+ * column moves along its own residual Y_c - X_c (X_c.Y_c / X_c.X_c)
+ * (eq. G_ops4 supplies the column-wise inner products).  The pattern of X is
+ * kept.  Errors: ESTATE (not bound), EHIP.                                  */
+int mfb_mv_update(const mfb_mv* mv, double* d_X, const double* d_Y, const double* d_S,
+                  const double* d_S2, double tau, void* stream);
+
 /* Thread-local message describing the last error (empty if none).           */
 const char* mfb_last_error(void);
 

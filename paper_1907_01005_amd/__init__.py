@@ -15,6 +15,7 @@ from .api import (  # noqa: F401
     Mesh,
     apply_H,
     apply_H_tuned,
+    mv_update,
     tmmult,
 )
 from ._native import MfbError, lib  # noqa: F401

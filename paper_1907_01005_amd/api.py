@@ -203,3 +203,9 @@ def tmmult(layout: Layout, X, Y, S, trace, work, stream=None) -> None:
     """mfb_tmmult: S = X^T Y (M x M, library column order) and trace."""
     check(lib().mfb_tmmult(layout.handle, _dev_ptr(X), _dev_ptr(Y), _dev_ptr(S), _dev_ptr(trace),
                            _dev_ptr(work), _stream(stream)))
+
+
+def mv_update(layout: Layout, X, Y, S, S2, tau: float, stream=None) -> None:
+    """mfb_mv_update: X <- X - tau (Y - X diag(S)/diag(S2)) on the stored entries."""
+    check(lib().mfb_mv_update(layout.handle, _dev_ptr(X), _dev_ptr(Y), _dev_ptr(S), _dev_ptr(S2),
+                              float(tau), _stream(stream)))

@@ -1,0 +1,140 @@
+"""Autotuner for the apply kernels and a HIP-graph-captured apply loop.
+
+The apply work list has uneven units (column blocks of 4-16 orbitals; batches
+with or without their own block stored), and three thread mappings
+(batch/LDS, one wave per unit, one wave per cell) each come as a one-unit-
+per-workgroup grid or as persistent workgroups pulling from a queue.  The
+tuner times every variant (and a few persistent grid sizes) on the caller's
+layout with HIP events and keeps the fastest; the choice is cached per layout
+signature.  `GraphLoop` captures `n` iterations of apply_H + tmmult with the
+chosen variant in one hipGraph and replays it.
+"""
+
+from __future__ import annotations
+
+import json
+import os
+import statistics
+from dataclasses import asdict, dataclass
+from typing import Dict, List, Optional
+
+from . import api
+
+KERNEL_NAMES = {0: "default-grid", 1: "default-queue", 2: "batch-grid", 3: "batch-queue",
+                4: "wave-grid", 5: "wave-queue"}
+
+
+@dataclass(frozen=True)
+class TuneChoice:
+    prec: int
+    kernel: int
+    grid: int          # persistent workgroups (0 = device-filling default)
+    us: float          # median apply time measured by the tuner
+
+    def describe(self) -> str:
+        g = f", grid {self.grid}" if self.kernel & 1 else ""
+        return f"{KERNEL_NAMES[self.kernel]}{g} ({api.PREC_NAMES[self.prec]}): {self.us:.1f} us"
+
+
+_CACHE: Dict[str, TuneChoice] = {}
+
+
+def layout_signature(dp, prec: int) -> str:
+    info = dp.layout.info
+    m = dp.mesh
+    return json.dumps([m.cells_shape, m.degree, m.dirichlet, info["M"], info["ncolblocks"],
+                       info["nblocks"], info["nvalues"], info["apply_items"], prec])
+
+
+def candidates(cu_count: int) -> List[tuple]:
+    out = [(k, 0) for k in (0, 2, 4)]
+    for k in (1, 3, 5):
+        for per_cu in (0, 1, 2, 4):
+            out.append((k, per_cu * cu_count))
+    return out
+
+
+def _time_apply(dp, prec: int, kernel: int, grid: int, iters: int, warmup: int) -> float:
+    import torch
+    for _ in range(warmup):
+        dp.apply_tuned(prec, kernel=kernel, grid=grid)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(iters)]
+    for a, b in evs:
+        a.record()
+        dp.apply_tuned(prec, kernel=kernel, grid=grid)
+        b.record()
+    torch.cuda.synchronize()
+    return statistics.median(a.elapsed_time(b) for a, b in evs) * 1e3
+
+
+def tune(dp, prec: int, iters: int = 20, warmup: int = 3, cache_file: Optional[str] = None,
+         verbose: bool = False) -> TuneChoice:
+    """Time every kernel variant on this layout and return the fastest."""
+    import torch
+    key = layout_signature(dp, prec)
+    if key in _CACHE:
+        return _CACHE[key]
+    if cache_file and os.path.exists(cache_file):
+        try:
+            saved = json.load(open(cache_file))
+            if key in saved:
+                _CACHE[key] = TuneChoice(**saved[key])
+                return _CACHE[key]
+        except (OSError, ValueError, TypeError):
+            pass
+    cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    best: Optional[TuneChoice] = None
+    for kernel, grid in candidates(cus):
+        us = _time_apply(dp, prec, kernel, grid, iters, warmup)
+        if verbose:
+            print(f"[tune] {KERNEL_NAMES[kernel]} grid={grid}: {us:.1f} us", flush=True)
+        if best is None or us < best.us:
+            best = TuneChoice(prec, kernel, grid, us)
+    assert best is not None
+    _CACHE[key] = best
+    if cache_file:
+        try:
+            saved = json.load(open(cache_file)) if os.path.exists(cache_file) else {}
+        except (OSError, ValueError):
+            saved = {}
+        saved[key] = asdict(best)
+        os.makedirs(os.path.dirname(os.path.abspath(cache_file)), exist_ok=True)
+        json.dump(saved, open(cache_file, "w"))
+    return best
+
+
+class GraphLoop:
+    """`n` iterations of apply_H + tmmult captured once in a hipGraph.
+
+    Every iteration applies H to the same X (the loop is a throughput
+    harness, as a solver iteration would be with X updated between
+    iterations); Y, S and the trace hold the last iteration's results.
+    """
+
+    def __init__(self, dp, choice: TuneChoice, n: int = 20):
+        import torch
+        self.dp = dp
+        self.n = n
+        self.choice = choice
+        # warm up outside the capture (lazy module loads, occupancy queries)
+        self._body()
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(self.graph, stream=side):
+                for _ in range(n):
+                    self._body()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+
+    def _body(self):
+        c = self.choice
+        self.dp.apply_tuned(c.prec, kernel=c.kernel, grid=c.grid)
+        self.dp.overlap()
+
+    def replay(self):
+        self.graph.replay()

@@ -51,7 +51,8 @@ std::vector<double> grad_scales(const mfb::MeshPlan& m) {
 
 struct MvLayout {
   size_t off_items = 0, off_units = 0, off_pair_tab = 0, off_pair_ptr = 0, off_pair_list = 0,
-         off_cb_of_col = 0, off_cb_start = 0, bytes = 0;
+         off_cb_of_col = 0, off_cb_start = 0, off_blk_off = 0, off_blk_col0 = 0, off_blk_w = 0,
+         bytes = 0;
 };
 
 MvLayout mv_layout(const mfb::MvPlan& v) {
@@ -71,6 +72,12 @@ MvLayout mv_layout(const mfb::MvPlan& v) {
   o = align256(o + sizeof(int32_t) * v.cb_of_col.size());
   L.off_cb_start = o;
   o = align256(o + sizeof(int32_t) * v.cb_start.size());
+  L.off_blk_off = o;
+  o = align256(o + sizeof(int64_t) * v.block_offset.size());
+  L.off_blk_col0 = o;
+  o = align256(o + sizeof(int32_t) * v.colidx.size());
+  L.off_blk_w = o;
+  o = align256(o + sizeof(int32_t) * v.colidx.size());
   L.bytes = std::max<size_t>(o, 256);
   return L;
 }
@@ -358,6 +365,16 @@ int mfb_mv_bind(mfb_mv* mv, void* d_meta, void* stream) {
   put(L.off_pair_list, p.pair_list.data(), sizeof(int64_t) * p.pair_list.size());
   put(L.off_cb_of_col, p.cb_of_col.data(), sizeof(int32_t) * p.cb_of_col.size());
   put(L.off_cb_start, p.cb_start.data(), sizeof(int32_t) * p.cb_start.size());
+  put(L.off_blk_off, p.block_offset.data(), sizeof(int64_t) * p.block_offset.size());
+  {
+    std::vector<int32_t> col0(p.colidx.size()), wid(p.colidx.size());
+    for (size_t k = 0; k < p.colidx.size(); ++k) {
+      col0[k] = p.cb_start[p.colidx[k]];
+      wid[k] = p.cb_start[p.colidx[k] + 1] - p.cb_start[p.colidx[k]];
+    }
+    put(L.off_blk_col0, col0.data(), sizeof(int32_t) * col0.size());
+    put(L.off_blk_w, wid.data(), sizeof(int32_t) * wid.size());
+  }
   hipStream_t st = (hipStream_t)stream;
   check_hip(hipMemcpyAsync(d_meta, host.data(), host.size(), hipMemcpyHostToDevice, st),
             "hipMemcpyAsync(layout metadata)");
@@ -462,6 +479,30 @@ int mfb_tmmult(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d
   t.S = d_S;
   t.trace = d_trace;
   const int rc = mfb::gpu::launch_tmmult(t, stream);
+  if (rc != 0) fail(MFB_EHIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)rc));
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_mv_update(const mfb_mv* mv, double* d_X, const double* d_Y, const double* d_S,
+                  const double* d_S2, double tau, void* stream) {
+  MFB_TRY
+  if (!mv || !d_X || !d_Y || !d_S || !d_S2) fail(MFB_EINVAL, "null argument");
+  if (!mv->bound) fail(MFB_ESTATE, "layout metadata not bound");
+  if (!std::isfinite(tau)) fail(MFB_EINVAL, "tau must be finite");
+  const char* mb = (const char*)mv->d_meta;
+  mfb::gpu::UpdateParams u;
+  u.X = d_X;
+  u.Y = d_Y;
+  u.S = d_S;
+  u.S2 = d_S2;
+  u.blk_off = (const int64_t*)(mb + mv->lay.off_blk_off);
+  u.blk_col0 = (const int32_t*)(mb + mv->lay.off_blk_col0);
+  u.blk_w = (const int32_t*)(mb + mv->lay.off_blk_w);
+  u.nblocks = (int64_t)mv->plan.colidx.size();
+  u.M = mv->plan.M;
+  u.tau = tau;
+  const int rc = mfb::gpu::launch_update(u, stream);
   if (rc != 0) fail(MFB_EHIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)rc));
   return MFB_OK;
   MFB_CATCH

@@ -84,6 +84,84 @@ __device__ __forceinline__ const double* tab_D<double>(const ApplyParams& a) { r
 template <>
 __device__ __forceinline__ const float* tab_D<float>(const ApplyParams& a) { return a.Df; }
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Contractions on the vector ALUs; MAT selects S (0) or D (1).
+template <typename R, int n>
+struct ValuCtr {
+  const R* __restrict__ S;
+  const R* __restrict__ D;
+  template <int AX, bool TR, int MAT>
+  __device__ __forceinline__ void c(const R (&in)[n][n], R (&out)[n][n]) const {
+    contract<n, AX, TR>(MAT ? D : S, in, out);
+  }
+  template <int AX, bool TR, int MAT>
+  __device__ __forceinline__ void ca(const R (&in)[n][n], R (&acc)[n][n]) const {
+    contract_add<n, AX, TR>(MAT ? D : S, in, acc);
+  }
+};
+
+// fp32 contractions on the matrix cores.  v_mfma_f32_4x4x1f32 treats the 64
+// lanes as 16 blocks of 4: lane 4b+j contributes B = its own pencil value of
+// step k and receives rows 0..3 of the 4x4 block product, while lane 4b+a
+// contributes A = M(a, k).  Every lane therefore gets M times its own pencil
+// (rows 0..3; a second row group covers rows 4..7 when n = 5), accumulated in
+// fp32 over the n steps k.
+template <int n>
+struct MfmaCtr {
+  static constexpr int G = (n + 3) / 4;
+  float m[4][G][n];  // [S, S^T, D, D^T][row group][k] = M(4 g + lane % 4, k)
+  __device__ __forceinline__ void init(const float* __restrict__ S, const float* __restrict__ D) {
+    const int r = threadIdx.x & 3;
+#pragma unroll
+    for (int mat = 0; mat < 4; ++mat)
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+          const float* M = mat < 2 ? S : D;
+          const bool tr = mat & 1;
+          const int row = 4 * g + r;
+          m[mat][g][k] = row < n ? (tr ? M[k * n + row] : M[row * n + k]) : 0.f;
+        }
+  }
+  template <int AX, bool TR, int MAT, bool ADD>
+  __device__ __forceinline__ void run(const float (&in)[n][n], float (&out)[n][n]) const {
+    constexpr int mi = 2 * MAT + (TR ? 1 : 0);
+#pragma unroll
+    for (int line = 0; line < n; ++line)
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        v4f acc;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int o = 4 * g + q;
+          acc[q] = (ADD && o < n) ? (AX == 0 ? out[o < n ? o : 0][line] : out[line][o < n ? o : 0]) : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < n; ++k)
+          acc = __builtin_amdgcn_mfma_f32_4x4x1f32(m[mi][g][k], AX == 0 ? in[k][line] : in[line][k],
+                                                  acc, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int o = 4 * g + q;
+          if (o < n) {
+            if (AX == 0) out[o][line] = acc[q];
+            else out[line][o] = acc[q];
+          }
+        }
+      }
+  }
+  template <int AX, bool TR, int MAT>
+  __device__ __forceinline__ void c(const float (&in)[n][n], float (&out)[n][n]) const {
+    run<AX, TR, MAT, false>(in, out);
+  }
+  template <int AX, bool TR, int MAT>
+  __device__ __forceinline__ void ca(const float (&in)[n][n], float (&acc)[n][n]) const {
+    run<AX, TR, MAT, true>(in, acc);
+  }
+};
+
 // Workgroup index -> item index so that each XCD (workgroups are dealt to
 // the 8 XCDs round robin) walks one contiguous, Hilbert-ordered range.
 __device__ __forceinline__ int64_t xcd_item(int64_t wg, int64_t nwg) {
@@ -143,19 +221,18 @@ __device__ __forceinline__ bool gather_plane(const ApplyParams& a, const int32_t
 // Sum-factorised cell operator on planes.  On entry u holds the z = pl plane
 // of the nodal values (layout A); on exit Tc holds the cell's output values
 // (index i + n j + n^2 k).  Threads with act == false only join the barriers.
-template <typename R, int P, class Hook>
-__device__ __forceinline__ void plane_operator(const ApplyParams& a, R* __restrict__ Tc, int pl,
+template <typename R, int P, class Ctr, class Hook>
+__device__ __forceinline__ void plane_operator(const ApplyParams& a, const Ctr& ctr,
+                                               R* __restrict__ Tc, int pl,
                                                const double* __restrict__ cv, bool act,
                                                const R (&u)[P + 1][P + 1], R (&out)[P + 1][P + 1],
                                                Hook after_first_barrier) {
   using D = Dims<P>;
   constexpr int n = D::n, n2 = D::n2, n3 = D::n3;
-  const R* __restrict__ Sm = tab_S<R>(a);
-  const R* __restrict__ Dm = tab_D<R>(a);
   const double* __restrict__ wg = a.Wg;
   R A[n][n], B[n][n];
-  contract<n, 0, false>(Sm, u, A);
-  contract<n, 1, false>(Sm, A, B);
+  ctr.template c<0, false, 0>(u, A);
+  ctr.template c<1, false, 0>(A, B);
   if (act) {
 #pragma unroll
     for (int j = 0; j < n; ++j)
@@ -172,19 +249,19 @@ __device__ __forceinline__ void plane_operator(const ApplyParams& a, R* __restri
       for (int i = 0; i < n; ++i) A[i][k] = Tc[i + n * pl + n2 * k];
   }
   R uq[n][n], wB[n][n];
-  contract<n, 1, false>(Sm, A, uq);
-  contract<n, 0, false>(Dm, uq, A);
+  ctr.template c<1, false, 0>(A, uq);
+  ctr.template c<0, false, 1>(uq, A);
 #pragma unroll
   for (int i = 0; i < n; ++i)
 #pragma unroll
     for (int k = 0; k < n; ++k) A[i][k] = (R)((double)A[i][k] * wg[i + n * pl + n2 * k]);
-  contract<n, 0, true>(Dm, A, wB);
-  contract<n, 1, false>(Dm, uq, A);
+  ctr.template c<0, true, 1>(A, wB);
+  ctr.template c<1, false, 1>(uq, A);
 #pragma unroll
   for (int i = 0; i < n; ++i)
 #pragma unroll
     for (int k = 0; k < n; ++k) A[i][k] = (R)((double)A[i][k] * wg[2 * n3 + i + n * pl + n2 * k]);
-  contract_add<n, 1, true>(Dm, A, wB);
+  ctr.template ca<1, true, 1>(A, wB);
   if (act) {
 #pragma unroll
     for (int i = 0; i < n; ++i)
@@ -207,12 +284,12 @@ __device__ __forceinline__ void plane_operator(const ApplyParams& a, R* __restri
 #pragma unroll
       for (int i = 0; i < n; ++i) A[i][j] = Tc[i + n * j + n2 * pl];
   }
-  contract<n, 1, false>(Dm, A, B);
+  ctr.template c<1, false, 1>(A, B);
 #pragma unroll
   for (int i = 0; i < n; ++i)
 #pragma unroll
     for (int j = 0; j < n; ++j) B[i][j] = (R)((double)B[i][j] * wg[n3 + i + n * j + n2 * pl]);
-  contract<n, 1, true>(Dm, B, A);
+  ctr.template c<1, true, 1>(B, A);
   __syncthreads();
   if (act) {
 #pragma unroll
@@ -228,7 +305,7 @@ __device__ __forceinline__ void plane_operator(const ApplyParams& a, R* __restri
 #pragma unroll
       for (int i = 0; i < n; ++i) wB[i][k] += Tc[i + n * pl + n2 * k];
   }
-  contract<n, 1, true>(Sm, wB, A);
+  ctr.template c<1, true, 0>(wB, A);
   __syncthreads();
   if (act) {
 #pragma unroll
@@ -244,8 +321,8 @@ __device__ __forceinline__ void plane_operator(const ApplyParams& a, R* __restri
 #pragma unroll
       for (int i = 0; i < n; ++i) A[i][j] = Tc[i + n * j + n2 * pl];
   }
-  contract<n, 1, true>(Sm, A, B);
-  contract<n, 0, true>(Sm, B, out);
+  ctr.template c<1, true, 0>(A, B);
+  ctr.template c<0, true, 0>(B, out);
 }
 
 // Sum the 8 cell results of a batch per batch node (T holds cell-column
@@ -294,7 +371,22 @@ __device__ __forceinline__ void batch_scatter(const ApplyParams& a, const R* __r
   }
 }
 
-template <typename R, int P>
+template <typename R, int P, bool MF>
+using Contractor = typename std::conditional<MF, MfmaCtr<P + 1>, ValuCtr<R, P + 1>>::type;
+
+template <typename R, int P, bool MF>
+__device__ __forceinline__ Contractor<R, P, MF> make_ctr(const ApplyParams& a) {
+  Contractor<R, P, MF> c;
+  if constexpr (MF) {
+    c.init(a.Sf, a.Df);
+  } else {
+    c.S = tab_S<R>(a);
+    c.D = tab_D<R>(a);
+  }
+  return c;
+}
+
+template <typename R, int P, bool MF = false>
 struct BatchProc {
   using D = Dims<P>;
   static constexpr int NT = 64 * D::n, UPI = 1;
@@ -361,13 +453,15 @@ struct BatchProc {
     const double* cv = a.cV + ((int64_t)rank * 8 + e) * D::n3;
     if constexpr (ALIAS) {
       __syncthreads();
-      plane_operator<R, P>(a, sm.b.T + (t & 63) * D::n3, pl, cv, true, u, out, []() {});
+      plane_operator<R, P>(a, make_ctr<R, P, MF>(a), sm.b.T + (t & 63) * D::n3, pl, cv, true, u,
+                           out, []() {});
       __syncthreads();
       zero_sums();
       __syncthreads();
     } else {
       // every thread has read its plane by the first barrier: reuse G for the sums
-      plane_operator<R, P>(a, sm.b.T + (t & 63) * D::n3, pl, cv, true, u, out, zero_sums);
+      plane_operator<R, P>(a, make_ctr<R, P, MF>(a), sm.b.T + (t & 63) * D::n3, pl, cv, true, u,
+                           out, zero_sums);
     }
 #pragma unroll
     for (int j = 0; j < n; ++j)
@@ -384,7 +478,7 @@ struct BatchProc {
   }
 };
 
-template <typename R, int P>
+template <typename R, int P, bool MF = false>
 struct CellProc {
   using D = Dims<P>;
   static constexpr int NT = 64, UPI = 8;
@@ -408,8 +502,8 @@ struct CellProc {
     const bool any = gather_plane<R, P>(a, g, sm.off, e, pq, c, c0, nc, ld, act, u);
     if (!__syncthreads_or(any)) return;
     R out[n][n];
-    plane_operator<R, P>(a, sm.T + c * n3, pq, a.cV + ((int64_t)rank * 8 + e) * n3, act, u, out,
-                         []() {});
+    plane_operator<R, P>(a, make_ctr<R, P, MF>(a), sm.T + c * n3, pq,
+                         a.cV + ((int64_t)rank * 8 + e) * n3, act, u, out, []() {});
     if (!act || c >= nc) return;
     const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
 #pragma unroll
@@ -736,10 +830,10 @@ __global__ __launch_bounds__(256) void tm_trace_kernel(TmParams p) {
 // blocks); only when one of them is non-zero does it run the operator, one
 // cell at a time.  For orbital-supported inputs all of them are zero and
 // the item ends after the check.
-template <typename R, int P>
+template <typename R, int P, bool MF>
 __global__ __launch_bounds__(64, P == 2 ? 4 : 2) void apply_shell_kernel(ApplyParams a) {
   using D = Dims<P>;
-  using Proc = CellProc<R, P>;
+  using Proc = CellProc<R, P, MF>;
   __shared__ typename Proc::Smem sm;
   const int64_t k = xcd_item(blockIdx.x, gridDim.x);
   if (k >= a.nshell) return;
@@ -787,7 +881,7 @@ hipError_t launch_proc(const ApplyParams& p, bool queue, hipStream_t st) {
 }
 
 // kernel: even = one work unit per workgroup, odd = persistent queue
-template <typename R, int P>
+template <typename R, int P, bool MF = false>
 hipError_t launch_apply_t(const ApplyParams& p, int kernel, hipStream_t st) {
   const bool queue = (kernel & 1) != 0;
   // processor: kernels 0/1 the default for the degree, 2/3 the batch
@@ -797,19 +891,39 @@ hipError_t launch_apply_t(const ApplyParams& p, int kernel, hipStream_t st) {
   const bool batch = proc <= 1;
   hipError_t e;
   if (batch) {
-    e = launch_proc<BatchProc<R, P>>(p, queue, st);
-  } else if constexpr (P == 2) {
+    e = launch_proc<BatchProc<R, P, MF>>(p, queue, st);
+  } else if constexpr (P == 2 && !MF) {
     e = launch_proc<RegProc<R, 2>>(p, queue, st);
   } else {
-    e = launch_proc<CellProc<R, P>>(p, queue, st);
+    e = launch_proc<CellProc<R, P, MF>>(p, queue, st);
   }
   if (e != hipSuccess || p.nshell == 0) return e;
   const int64_t nwg = ((p.nshell + 7) / 8) * 8;
-  hipLaunchKernelGGL((apply_shell_kernel<R, P>), dim3((unsigned)nwg), dim3(64), 0, st, p);
+  hipLaunchKernelGGL((apply_shell_kernel<R, P, MF>), dim3((unsigned)nwg), dim3(64), 0, st, p);
   return hipGetLastError();
 }
 
+// -------------------------------------------------------------- update
+__global__ __launch_bounds__(256) void update_kernel(UpdateParams p) {
+  const int64_t k = blockIdx.x;
+  const int64_t o0 = p.blk_off[k], o1 = p.blk_off[k + 1];
+  const int c0 = p.blk_col0[k], w = p.blk_w[k];
+  for (int64_t e = o0 + threadIdx.x; e < o1; e += blockDim.x) {
+    const int c = c0 + (int)((e - o0) % w);
+    const double s2 = p.S2[(int64_t)c * p.M + c];
+    const double d = s2 != 0.0 ? p.S[(int64_t)c * p.M + c] / s2 : 0.0;
+    const double x = p.X[e];
+    p.X[e] = x - p.tau * (p.Y[e] - x * d);
+  }
+}
+
 }  // namespace
+
+int launch_update(const UpdateParams& p, void* stream) {
+  if (p.nblocks == 0) return 0;
+  hipLaunchKernelGGL(update_kernel, dim3((unsigned)p.nblocks), dim3(256), 0, (hipStream_t)stream, p);
+  return (int)hipGetLastError();
+}
 
 int device_cu_count() {
   int dev = 0, cus = 0;
@@ -834,6 +948,9 @@ int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t
     e = degree == 2 ? launch_apply_t<double, 2>(p, kernel, st) : launch_apply_t<double, 4>(p, kernel, st);
   } else if (prec == 3) {
     e = degree == 2 ? launch_apply_t<float, 2>(p, kernel, st) : launch_apply_t<float, 4>(p, kernel, st);
+  } else if (prec == 2) {
+    e = degree == 2 ? launch_apply_t<float, 2, true>(p, kernel, st)
+                    : launch_apply_t<float, 4, true>(p, kernel, st);
   } else {
     return -2;
   }

@@ -52,6 +52,21 @@ struct TmParams {
 int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t nvalues,
                  void* stream);
 int launch_tmmult(const TmParams& p, void* stream);
+
+// X <- X - tau (Y - X d), d_c = S[c][c] / S2[c][c], one workgroup per stored block.
+struct UpdateParams {
+  double* X;
+  const double* Y;
+  const double* S;
+  const double* S2;
+  const int64_t* blk_off;   // [nblocks+1] value offsets
+  const int32_t* blk_col0;  // [nblocks] first column of the block's column block
+  const int32_t* blk_w;     // [nblocks] width of the column block
+  int64_t nblocks;
+  int32_t M;
+  double tau;
+};
+int launch_update(const UpdateParams& p, void* stream);
 int device_cu_count();
 
 }  // namespace gpu

@@ -11,7 +11,7 @@ from typing import Callable, Optional, Sequence
 
 import numpy as np
 
-from .api import FP64, Layout, Mesh, apply_H, apply_H_tuned, tmmult
+from .api import FP64, Layout, Mesh, apply_H, apply_H_tuned, mv_update, tmmult
 
 
 class DeviceProblem:
@@ -55,6 +55,13 @@ class DeviceProblem:
     def overlap(self, stream=None, X=None, Y=None) -> None:
         tmmult(self.layout, self.X if X is None else X, self.Y if Y is None else Y, self.S,
                self.trace, self.work, stream)
+
+    def overlap_into(self, S, trace, X=None, Y=None, stream=None) -> None:
+        tmmult(self.layout, self.X if X is None else X, self.Y if Y is None else Y, S, trace,
+               self.work, stream)
+
+    def update(self, S, S2, tau: float, stream=None) -> None:
+        mv_update(self.layout, self.X, self.Y, S, S2, tau, stream)
 
     def S_original_order(self) -> np.ndarray:
         """S permuted back to original orbital ids."""

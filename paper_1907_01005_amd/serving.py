@@ -1,0 +1,325 @@
+"""Continuous-batching request loop over device-resident BCSR multivectors.
+
+A request is a small minimisation run on its own mesh: ``iters`` iterations
+of
+
+    Y = H X;  S = X^T Y;  S2 = X^T X;  X <- X - tau (Y - X diag(S)/diag(S2))
+
+on the pattern of X (the required operations of Sec. 2 with a column-wise
+Rayleigh-quotient step standing in for the paper's minimiser).  Requests
+arrive over time; the server admits a waiting request as soon as a slot is
+free and its device footprint (BCSR values, metadata, workspace, S) fits in
+the byte budget, so requests that arrive while others run are started at
+once and their kernels overlap on the device (one HIP stream per slot).
+Completion is detected with events, memory is released, and the next
+waiting request is admitted: the batch changes continuously.
+
+The scheduler is independent of the GPU: it drives an ``Executor``.  The GPU
+executor here plans each request on the host (mesh, layout, potential and
+orbital values) in a worker pool when it arrives, and on admission allocates,
+uploads and enqueues all iterations on the slot's stream.
+"""
+
+from __future__ import annotations
+
+import math
+import statistics
+import threading
+import time
+from concurrent.futures import Future, ThreadPoolExecutor
+from dataclasses import dataclass, field
+from typing import Any, Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from .api import FP32_MFMA, FP64
+
+# mesh choices of the request stream (cells, unit cell width)
+MESHES = [(16, 16, 16), (24, 16, 16), (32, 20, 20), (32, 32, 32), (48, 32, 32), (64, 40, 40)]
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float                 # seconds after the stream starts
+    cells: Tuple[int, int, int]
+    degree: int
+    M: int
+    radius: float
+    prec: int
+    iters: int
+    seed: int
+
+
+def request_stream(n: int = 96, rate: float = 40.0, seed: int = 5, meshes=MESHES,
+                   m_range=(32, 640), r_range=(3.0, 5.0), precs=(FP32_MFMA, FP64),
+                   degrees=(2, 4), iters: int = 10) -> List[Request]:
+    """Poisson arrivals; mesh uniform over `meshes`; degree and precision 50/50;
+    M log-uniform in m_range; support radius uniform in r_range."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n):
+        t += float(rng.exponential(1.0 / rate))
+        cells = tuple(int(c) for c in meshes[int(rng.integers(len(meshes)))])
+        degree = int(degrees[int(rng.integers(len(degrees)))])
+        M = int(round(math.exp(rng.uniform(math.log(m_range[0]), math.log(m_range[1])))))
+        r = float(rng.uniform(*r_range))
+        prec = int(precs[int(rng.integers(len(precs)))])
+        out.append(Request(i, t, cells, degree, M, r, prec, iters, seed * 1000 + i))
+    return out
+
+
+# ----------------------------------------------------------------- scheduler
+@dataclass
+class Slot:
+    req: Request
+    handle: Any
+    token: Any
+    admitted: float
+
+
+@dataclass
+class ServeReport:
+    results: Dict[int, dict] = field(default_factory=dict)
+    admit_order: List[int] = field(default_factory=list)
+    max_bytes_in_use: int = 0
+    max_concurrent: int = 0
+    wall_s: float = 0.0
+
+
+class Server:
+    """FIFO admission by slot count and device-byte budget."""
+
+    def __init__(self, executor, byte_budget: int, max_slots: int = 8):
+        self.ex = executor
+        self.budget = int(byte_budget)
+        self.max_slots = int(max_slots)
+
+    def run(self, requests: Sequence[Request], realtime: bool = True,
+            poll_s: float = 0.0005) -> ServeReport:
+        rep = ServeReport()
+        queue = sorted(requests, key=lambda r: r.arrival)
+        arrived: List[Tuple[Request, Future]] = []
+        active: List[Slot] = []
+        in_use = 0
+        t0 = time.perf_counter()
+        nxt = 0
+        clock = (lambda: time.perf_counter() - t0) if realtime else None
+        sim_now = 0.0
+        while nxt < len(queue) or arrived or active:
+            now = clock() if realtime else sim_now
+            while nxt < len(queue) and queue[nxt].arrival <= now:
+                arrived.append((queue[nxt], self.ex.prepare_async(queue[nxt])))
+                nxt += 1
+            # admit in arrival order while slots and bytes allow
+            while arrived and len(active) < self.max_slots:
+                req, fut = arrived[0]
+                if not fut.done():
+                    break
+                handle = fut.result()
+                need = self.ex.footprint(handle)
+                if need > self.budget:
+                    arrived.pop(0)
+                    rep.results[req.rid] = {"rejected": True, "bytes": need}
+                    continue
+                if in_use + need > self.budget:
+                    break
+                arrived.pop(0)
+                in_use += need
+                tok = self.ex.start(handle)
+                active.append(Slot(req, handle, tok, clock() if realtime else sim_now))
+                rep.admit_order.append(req.rid)
+                rep.max_bytes_in_use = max(rep.max_bytes_in_use, in_use)
+                rep.max_concurrent = max(rep.max_concurrent, len(active))
+            # retire finished requests
+            still = []
+            for s in active:
+                if self.ex.done(s.token):
+                    res = self.ex.finish(s.token)
+                    end = clock() if realtime else sim_now
+                    res.update({"arrival": s.req.arrival, "admitted": s.admitted, "finished": end,
+                                "latency_s": end - s.req.arrival})
+                    rep.results[s.req.rid] = res
+                    in_use -= self.ex.footprint(s.handle)
+                    self.ex.release(s.handle)
+                else:
+                    still.append(s)
+            active = still
+            if realtime:
+                time.sleep(poll_s)
+            else:
+                sim_now = self.ex.advance(sim_now)
+        rep.wall_s = (time.perf_counter() - t0) if realtime else sim_now
+        return rep
+
+
+def summarize(rep: ServeReport) -> dict:
+    done = [r for r in rep.results.values() if not r.get("rejected")]
+    applies = [t for r in done for t in r.get("apply_s", [])]
+    entries = sum(r.get("entries", 0) * len(r.get("apply_s", [])) for r in done)
+    gpu_apply_s = sum(applies)
+    out = {
+        "requests_done": len(done),
+        "requests_rejected": len(rep.results) - len(done),
+        "wall_s": rep.wall_s,
+        "requests_per_s": len(done) / rep.wall_s if rep.wall_s > 0 else 0.0,
+        "max_concurrent": rep.max_concurrent,
+        "max_bytes_in_use": rep.max_bytes_in_use,
+    }
+    if applies:
+        out.update({
+            "apply_ms_p50": 1e3 * statistics.median(applies),
+            "apply_ms_p99": 1e3 * float(np.percentile(applies, 99)),
+            "aggregate_gdofcols_s": entries / rep.wall_s / 1e9 if rep.wall_s > 0 else 0.0,
+            "apply_gdofcols_s_busy": entries / gpu_apply_s / 1e9 if gpu_apply_s > 0 else 0.0,
+            "latency_s_p50": statistics.median(r["latency_s"] for r in done),
+            "latency_s_p99": float(np.percentile([r["latency_s"] for r in done], 99)),
+        })
+    return out
+
+
+# ----------------------------------------------------------------- GPU executor
+@dataclass
+class _Plan:
+    req: Request
+    mesh: Any
+    layout: Any
+    values: np.ndarray
+    nbytes: int
+    h: float
+
+
+class GpuExecutor:
+    """Plans on the host (worker pool), runs each request on its own stream."""
+
+    def __init__(self, device: str = "cuda", planner_threads: int = 4, tau_scale: float = 0.05,
+                 keep_X: bool = False):
+        self.device = device
+        self.pool = ThreadPoolExecutor(max_workers=planner_threads)
+        self.tau_scale = tau_scale
+        self.keep_X = keep_X
+        self._lock = threading.Lock()
+
+    # -- planning (host only)
+    def _plan(self, req: Request) -> _Plan:
+        import synth
+        from .api import Layout, Mesh
+        cells = req.cells
+        L = tuple(float(c) for c in cells)        # unit cell width
+        ms = synth.MeshSpec(*cells, L, req.degree)
+        wl = synth.custom_workload(ms, req.M, req.radius, req.seed, potential="wells")
+        mesh = Mesh(*cells, L, req.degree, ms.dirichlet)
+        mesh.set_potential(synth.potential_at(wl, mesh.qp_points().reshape(-1, 3)))
+        layout = Layout(mesh, wl.centres, wl.radius, wl.colblock_sizes)
+        node, orb, val = synth.orbital_values(wl)
+        values = layout.pack(node, orb, val)
+        M = layout.M
+        nbytes = (2 * 8 * max(layout.nvalues, 1) + mesh.meta_bytes + layout.meta_bytes
+                  + layout.work_bytes + 2 * 8 * M * M + 16)
+        return _Plan(req, mesh, layout, values, nbytes, 1.0)
+
+    def prepare_async(self, req: Request) -> Future:
+        return self.pool.submit(self._plan, req)
+
+    def footprint(self, plan: _Plan) -> int:
+        return plan.nbytes
+
+    # -- execution
+    def start(self, plan: _Plan):
+        import torch
+        from .api import mv_update, apply_H, tmmult
+        stream = torch.cuda.Stream(device=self.device)
+        with torch.cuda.stream(stream):
+            plan.mesh.bind(self.device, stream)
+            plan.layout.bind(self.device, stream)
+            lay = plan.layout
+            X = torch.from_numpy(plan.values).to(self.device, non_blocking=False) \
+                if lay.nvalues else torch.zeros(1, dtype=torch.float64, device=self.device)
+            Y = lay.new_values(self.device)
+            work = lay.new_work(self.device)
+            S = torch.zeros((lay.M, lay.M), dtype=torch.float64, device=self.device)
+            S2 = torch.zeros_like(S)
+            tr = torch.zeros(2, dtype=torch.float64, device=self.device)
+            tau = self.tau_scale * plan.h * plan.h
+            evs = []
+            for _ in range(plan.req.iters):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                apply_H(plan.mesh, lay, X, Y, plan.req.prec, stream)
+                b.record(stream)
+                tmmult(lay, X, Y, S, tr[0:1], work, stream)
+                tmmult(lay, X, X, S2, tr[1:2], work, stream)
+                mv_update(lay, X, Y, S, S2, tau, stream)
+                evs.append((a, b))
+            end = torch.cuda.Event()
+            end.record(stream)
+        return {"plan": plan, "stream": stream, "evs": evs, "end": end,
+                "bufs": (X, Y, work, S, S2, tr)}
+
+    def done(self, tok) -> bool:
+        return tok["end"].query()
+
+    def finish(self, tok) -> dict:
+        tok["end"].synchronize()
+        X, Y, work, S, S2, tr = tok["bufs"]
+        plan = tok["plan"]
+        apply_s = [a.elapsed_time(b) * 1e-3 for a, b in tok["evs"]]
+        trs = tr.cpu().numpy()
+        out = {"apply_s": apply_s, "entries": plan.layout.nvalues, "trace": float(trs[0]),
+               "trace_xx": float(trs[1]), "x_norm2": float((X[:plan.layout.nvalues] ** 2).sum()),
+               "prec": plan.req.prec, "bytes": plan.nbytes}
+        if self.keep_X:
+            out["X"] = X[:plan.layout.nvalues].cpu().numpy()
+        return out
+
+    def release(self, plan: _Plan) -> None:
+        # device buffers die with the token; drop the device copies of the metadata
+        plan.mesh._meta = None
+        plan.layout._meta = None
+
+    def advance(self, now: float) -> float:
+        return now
+
+
+# ----------------------------------------------------------------- fake executor (tests)
+class FakeExecutor:
+    """Counts bytes and simulates run time in a virtual clock (scheduler tests)."""
+
+    def __init__(self, bytes_of=None, seconds_of=None, dt: float = 0.001):
+        self.bytes_of = bytes_of or (lambda r: r.M * 1000)
+        self.seconds_of = seconds_of or (lambda r: 0.01 * r.iters)
+        self.dt = dt
+        self.now = 0.0
+        self.live_bytes = 0
+        self.max_live = 0
+        self.events: List[Tuple[str, int, float]] = []
+
+    def prepare_async(self, req):
+        f: Future = Future()
+        f.set_result(req)
+        return f
+
+    def footprint(self, req):
+        return self.bytes_of(req)
+
+    def start(self, req):
+        self.live_bytes += self.bytes_of(req)
+        self.max_live = max(self.max_live, self.live_bytes)
+        self.events.append(("start", req.rid, self.now))
+        return {"req": req, "t_end": self.now + self.seconds_of(req)}
+
+    def done(self, tok):
+        return tok["t_end"] <= self.now
+
+    def finish(self, tok):
+        self.events.append(("finish", tok["req"].rid, self.now))
+        return {"apply_s": [1e-3] * tok["req"].iters, "entries": tok["req"].M}
+
+    def release(self, req):
+        self.live_bytes -= self.bytes_of(req)
+
+    def advance(self, now: float) -> float:
+        self.now = now + self.dt
+        return self.now

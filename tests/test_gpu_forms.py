@@ -1,0 +1,149 @@
+"""GPU tests of the execution forms: autotuned kernels, the hipGraph loop, the
+serving loop (each result the same alone and in the mix), the update kernel
+and the 640-orbital uneven-block workload."""
+
+import numpy as np
+import pytest
+
+import synth
+from helpers import device_problem, gpu_available, oracle_Y_at, rel_fro, say
+from oracle.workload import OracleProblem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not gpu_available():
+        pytest.fail("GPU tests need a visible GPU (run with -m 'not gpu' on CPU)")
+
+
+def _small(seed=11, degree=2, M=29, sizes=(8, 5, 12, 4)):
+    ms = synth.MeshSpec(8, 6, 4, (8.0, 6.0, 4.0), degree)
+    wl = synth.custom_workload(ms, M, 2.2, seed, potential="wells")
+    wl.colblock_sizes = np.asarray(sizes, dtype=np.int32)
+    return wl
+
+
+def test_autotune_and_graph_loop_match_eager():
+    import torch
+    from paper_1907_01005_amd import FP32_MFMA, FP64
+    from paper_1907_01005_amd.autotune import GraphLoop, tune
+    wl = synth.make_workload(1)
+    say("autotune + graph")
+    op = OracleProblem(wl)
+    dp = device_problem(wl)
+    dp.set_X_coo(op.node, op.orb, op.val)
+    dp.apply(FP64)
+    dp.overlap()
+    torch.cuda.synchronize()
+    Y0 = dp.Y.clone()
+    S0 = dp.S.clone()
+    for prec, tol in ((FP64, 1e-14), (FP32_MFMA, 1e-5)):
+        choice = tune(dp, prec, iters=5, warmup=1)
+        say(f"tuned {choice.describe()}")
+        loop = GraphLoop(dp, choice, n=3)
+        for rep in range(3):
+            dp.Y.zero_()
+            dp.S.zero_()
+            torch.cuda.synchronize()
+            loop.replay()
+            torch.cuda.synchronize()
+            eY = (dp.Y - Y0).abs().max().item() / Y0.abs().max().item()
+            eS = (dp.S - S0).abs().max().item() / S0.abs().max().item()
+            say(f"graph replay {rep} prec={prec}: maxrel Y {eY:.2e} S {eS:.2e}")
+            assert eY <= tol and eS <= tol
+            # eager work between replays
+            dp.apply(FP64)
+            dp.overlap()
+            torch.cuda.synchronize()
+            assert (dp.S - S0).abs().max().item() <= 1e-14 * S0.abs().max().item()
+
+
+def test_update_kernel_definition():
+    import torch
+    from paper_1907_01005_amd import FP64
+    wl = _small()
+    say("update kernel")
+    op = OracleProblem(wl, values="generic", value_seed=4)
+    dp = device_problem(wl)
+    dp.set_X_coo(op.node, op.orb, op.val)
+    dp.apply(FP64)
+    S = torch.zeros_like(dp.S)
+    S2 = torch.zeros_like(dp.S)
+    tr = torch.zeros(2, dtype=torch.float64, device=dp.S.device)
+    dp.overlap_into(S, tr[0:1])
+    dp.overlap_into(S2, tr[1:2], Y=dp.X)
+    torch.cuda.synchronize()
+    X0 = dp.X.cpu().numpy()[:dp.nvalues].copy()
+    Yh = dp.Y.cpu().numpy()[:dp.nvalues]
+    d = np.diag(S.cpu().numpy()) / np.diag(S2.cpu().numpy())
+    pat = dp.layout.pattern()
+    col = np.empty(dp.nvalues, dtype=np.int64)
+    sizes = np.diff(pat["col_block_start"])
+    for k, C in enumerate(pat["colidx"]):
+        o0, o1 = pat["block_offset"][k], pat["block_offset"][k + 1]
+        col[o0:o1] = pat["col_block_start"][C] + np.arange(o1 - o0) % sizes[C]
+    tau = 0.07
+    expect = X0 - tau * (Yh - X0 * d[col])
+    dp.update(S, S2, tau)
+    torch.cuda.synchronize()
+    got = dp.X.cpu().numpy()[:dp.nvalues]
+    assert np.abs(got - expect).max() <= 1e-14 * np.abs(expect).max()
+    # X^T X through tmmult equals the plain column dots
+    Xd = X0
+    for c in range(dp.M):
+        assert abs(S2.cpu().numpy()[c, c] - np.sum(Xd[col == c] ** 2)) <= 1e-12 * max(1.0, S2.cpu().numpy()[c, c])
+
+
+def test_serving_results_same_alone_and_in_mix():
+    from paper_1907_01005_amd import FP32_MFMA, FP64
+    from paper_1907_01005_amd.serving import GpuExecutor, Request, Server, summarize
+    say("serving alone vs mix")
+    reqs = []
+    shapes = [((8, 8, 8), 2), ((10, 8, 6), 4), ((12, 8, 8), 2), ((8, 6, 6), 4), ((16, 8, 8), 2),
+              ((8, 8, 8), 4)]
+    for i, (cells, deg) in enumerate(shapes):
+        prec = FP64 if i % 2 == 0 else FP32_MFMA
+        reqs.append(Request(i, 0.002 * i, cells, deg, 20 + 7 * i, 3.0, prec, 4, 100 + i))
+    ex = GpuExecutor(planner_threads=2, keep_X=True)
+    budget = 3 * max(ex.footprint(ex._plan(r)) for r in reqs)   # forces queueing
+    mix = Server(ex, byte_budget=budget, max_slots=3).run(reqs)
+    s = summarize(mix)
+    say(f"mix: {s}")
+    assert s["requests_done"] == len(reqs) and mix.max_concurrent >= 2
+    for r in reqs:
+        alone = Server(GpuExecutor(planner_threads=1, keep_X=True), byte_budget=budget,
+                       max_slots=1).run([Request(r.rid, 0.0, r.cells, r.degree, r.M, r.radius,
+                                                 r.prec, r.iters, r.seed)])
+        a, b = alone.results[r.rid]["X"], mix.results[r.rid]["X"]
+        tol = 1e-12 if r.prec == FP64 else 1e-5
+        err = rel_fro(b, a)
+        say(f"request {r.rid} prec={r.prec}: alone-vs-mix rel {err:.2e}")
+        assert err <= tol
+
+
+@pytest.mark.parametrize("mesh_index", [0, 1])
+def test_uneven_blocks_640_orbitals_sampled(mesh_index):
+    """128x40x40 Q2 / 64x20x20 Q4, 640 orbitals in column blocks of 4-15."""
+    from paper_1907_01005_amd import FP32_MFMA, FP64
+    wl = synth.make_workload(4)
+    say(f"640 orbitals mesh {mesh_index}")
+    op = OracleProblem(wl, mesh_index)
+    dp = device_problem(wl, mesh_index)
+    dp.set_X_coo(op.node, op.orb, op.val)
+    node, orb = dp.layout.entry_coords()
+    ncb = len(wl.colblock_sizes)
+    widths = wl.colblock_sizes
+    blocks = [int(np.argmax(widths)), int(np.argmin(widths)), ncb // 2]
+    sel_orbs = np.concatenate([op.block_orbitals(C) for C in blocks])
+    sel = np.isin(orb, sel_orbs)
+    Yo = oracle_Y_at(op, node[sel], orb[sel], blocks)
+    import torch
+    for prec, tol in ((FP64, 1e-12), (FP32_MFMA, 1e-5)):
+        dp.apply(prec)
+        torch.cuda.synchronize()
+        Yg = dp.Y.cpu().numpy()[:dp.nvalues]
+        e = rel_fro(Yg[sel], Yo)
+        say(f"640 orbitals mesh {mesh_index} prec={prec}: relY(sampled) {e:.2e}")
+        assert e <= tol

@@ -59,7 +59,7 @@ def _small(cfg_cells, degree, M, radius, seed, sizes=None, dirichlet=0x3F, poten
     return wl
 
 
-@pytest.mark.parametrize("prec,tol", [(0, TOL64), (3, TOL32)])
+@pytest.mark.parametrize("prec,tol", [(0, TOL64), (3, TOL32), (2, TOL32)])
 def test_config1_full(prec, tol):
     wl = synth.make_workload(1)
     say(f"config1 prec={prec}")
@@ -77,10 +77,11 @@ def test_generic_values_ragged_blocks(degree):
     op = OracleProblem(wl, values="generic", value_seed=3)
     dp = device_problem(wl)
     dp.set_X_coo(op.node, op.orb, op.val)
-    for prec, tol in ((0, TOL64), (3, TOL32)):
+    for prec, tol in ((0, TOL64), (3, TOL32), (2, TOL32)):
         _check_full(wl, op, dp, prec, tol)
     for kernel in range(1, 6):
         _check_full(wl, op, dp, 0, TOL64, tuned=kernel)
+        _check_full(wl, op, dp, 2, TOL32, tuned=kernel)
 
 
 def test_natural_bc_lexicographic_free_faces():
@@ -183,7 +184,7 @@ def test_paper_scale_sampled(cfg):
     op = OracleProblem(wl)
     dp = device_problem(wl)
     dp.set_X_coo(op.node, op.orb, op.val)
-    for prec, tol in ((0, TOL64), (3, TOL32)):
+    for prec, tol in ((0, TOL64), (3, TOL32), (2, TOL32)):
         Yg, S, tr = _run(dp, prec)
         node, orb = dp.layout.entry_coords()
         blocks = [0, wl.colblock_sizes.size // 2, wl.colblock_sizes.size - 1]
@@ -193,9 +194,9 @@ def test_paper_scale_sampled(cfg):
         eY = rel_fro(Yg[sel], Yo)
         say(f"config{cfg} prec={prec} relY(sampled)={eY:.2e}")
         assert eY <= tol
-        if prec == 0:
+        if prec in (0, 2):
             So, tro = op.overlap()
             eS = rel_fro(S, So)
             et = abs(tr - tro) / abs(tro)
-            say(f"config{cfg} relS={eS:.2e} relTr={et:.2e}")
+            say(f"config{cfg} prec={prec} relS={eS:.2e} relTr={et:.2e}")
             assert eS <= tol and et <= tol
