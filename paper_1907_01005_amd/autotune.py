@@ -21,7 +21,7 @@ from typing import Dict, List, Optional
 from . import api
 
 KERNEL_NAMES = {0: "default-grid", 1: "default-queue", 2: "batch-grid", 3: "batch-queue",
-                4: "wave-grid", 5: "wave-queue"}
+                4: "wave-grid", 5: "wave-queue", 6: "batch-pipelined"}
 
 
 @dataclass(frozen=True)
@@ -32,7 +32,7 @@ class TuneChoice:
     us: float          # median apply time measured by the tuner
 
     def describe(self) -> str:
-        g = f", grid {self.grid}" if self.kernel & 1 else ""
+        g = f", grid {self.grid}" if (self.kernel & 1 or self.kernel == 6) else ""
         return f"{KERNEL_NAMES[self.kernel]}{g} ({api.PREC_NAMES[self.prec]}): {self.us:.1f} us"
 
 
@@ -48,6 +48,8 @@ def layout_signature(dp, prec: int) -> str:
 
 def candidates(cu_count: int) -> List[tuple]:
     out = [(k, 0) for k in (0, 2, 4)]
+    for per_cu in (0, 1, 2, 3):
+        out.append((6, per_cu * cu_count))
     for k in (1, 3, 5):
         for per_cu in (0, 1, 2, 4):
             out.append((k, per_cu * cu_count))

@@ -52,7 +52,7 @@ std::vector<double> grad_scales(const mfb::MeshPlan& m) {
 struct MvLayout {
   size_t off_items = 0, off_units = 0, off_pair_tab = 0, off_pair_ptr = 0, off_pair_list = 0,
          off_cb_of_col = 0, off_cb_start = 0, off_blk_off = 0, off_blk_col0 = 0, off_blk_w = 0,
-         bytes = 0;
+         off_rowoff = 0, off_shell_ptr = 0, off_shell_ro = 0, bytes = 0;
 };
 
 MvLayout mv_layout(const mfb::MvPlan& v) {
@@ -78,6 +78,13 @@ MvLayout mv_layout(const mfb::MvPlan& v) {
   o = align256(o + sizeof(int32_t) * v.colidx.size());
   L.off_blk_w = o;
   o = align256(o + sizeof(int32_t) * v.colidx.size());
+  L.off_rowoff = o;
+  o = align256(o + sizeof(int32_t) * v.rowoff.size());
+  L.off_shell_ptr = o;
+  o = align256(o + sizeof(int32_t) * v.shell_ptr.size());
+  L.off_shell_ro = o;
+  o = align256(o + sizeof(int32_t) * v.shell_ro.size());
+
   L.bytes = std::max<size_t>(o, 256);
   return L;
 }
@@ -366,6 +373,10 @@ int mfb_mv_bind(mfb_mv* mv, void* d_meta, void* stream) {
   put(L.off_cb_of_col, p.cb_of_col.data(), sizeof(int32_t) * p.cb_of_col.size());
   put(L.off_cb_start, p.cb_start.data(), sizeof(int32_t) * p.cb_start.size());
   put(L.off_blk_off, p.block_offset.data(), sizeof(int64_t) * p.block_offset.size());
+  put(L.off_rowoff, p.rowoff.data(), sizeof(int32_t) * p.rowoff.size());
+  put(L.off_shell_ptr, p.shell_ptr.data(), sizeof(int32_t) * p.shell_ptr.size());
+  put(L.off_shell_ro, p.shell_ro.data(), sizeof(int32_t) * p.shell_ro.size());
+
   {
     std::vector<int32_t> col0(p.colidx.size()), wid(p.colidx.size());
     for (size_t k = 0; k < p.colidx.size(); ++k) {
@@ -400,6 +411,9 @@ static void fill_apply_params(const mfb_mesh* mesh, const mfb_mv* mv, const doub
   a.nitems = mv->plan.n_own_items;
   a.shell = a.items + mv->plan.n_own_items;
   a.nshell = (int64_t)mv->plan.items.size() - mv->plan.n_own_items;
+  a.rowoff = (const int32_t*)(mb + mv->lay.off_rowoff);
+  a.shell_ptr = (const int32_t*)(mb + mv->lay.off_shell_ptr);
+  a.shell_ro = (const int32_t*)(mb + mv->lay.off_shell_ro);
   a.gtab = (const int32_t*)(gb + mesh->lay.off_gtab);
   a.cV = (const double*)(gb + mesh->lay.off_cv);
   a.Wg = (const double*)(gb + mesh->lay.off_wg);
@@ -440,9 +454,10 @@ int mfb_apply_H_tuned(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X,
   check_apply_args(mesh, mv, d_X, d_Y);
   if (!tune) fail(MFB_EINVAL, "null tune");
   if (tune->prec < 0 || tune->prec > 3) fail(MFB_EINVAL, "unknown precision");
-  if (tune->kernel < 0 || tune->kernel > 5) fail(MFB_EINVAL, "kernel must be in 0..5");
+  if (tune->kernel < 0 || tune->kernel > 6) fail(MFB_EINVAL, "kernel must be in 0..6");
   if (tune->grid < 0) fail(MFB_EINVAL, "negative grid");
-  if ((tune->kernel & 1) && !d_work) fail(MFB_EINVAL, "the queue kernels need the workspace");
+  if ((tune->kernel & 1) && tune->kernel != 6 && !d_work)
+    fail(MFB_EINVAL, "the queue kernels need the workspace");
   mfb::gpu::ApplyParams a;
   fill_apply_params(mesh, mv, d_X, d_Y, a);
   a.counters = (int32_t*)d_work;
@@ -476,6 +491,7 @@ int mfb_tmmult(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d
   t.cb_start = (const int32_t*)(mb + mv->lay.off_cb_start);
   t.M = p.M;
   t.ncb = p.ncb;
+
   t.S = d_S;
   t.trace = d_trace;
   const int rc = mfb::gpu::launch_tmmult(t, stream);

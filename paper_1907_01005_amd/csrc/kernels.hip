@@ -191,9 +191,8 @@ struct Dims {
 // Gather the z = pl plane of cell e of the item into u[i][j] (layout A).
 // Returns whether any gathered value is non-zero.
 template <typename R, int P>
-__device__ __forceinline__ bool gather_plane(const ApplyParams& a, const int32_t* __restrict__ g,
-                                             const int64_t* __restrict__ off, int e, int pl, int c,
-                                             int c0, int nc, int ld, bool act,
+__device__ __forceinline__ bool gather_plane(const ApplyParams& a, const int32_t* __restrict__ ro,
+                                             int e, int pl, int c, int c0, int nc, bool act,
                                              R (&u)[P + 1][P + 1]) {
   using D = Dims<P>;
   constexpr int n = D::n, NB = D::NB;
@@ -205,12 +204,8 @@ __device__ __forceinline__ bool gather_plane(const ApplyParams& a, const int32_t
     for (int i = 0; i < n; ++i) {
       double x = 0.0;
       if (act && c < nc) {
-        const int v = (ex * P + i) + NB * ((ey * P + j) + NB * (ez * P + pl));
-        const int32_t ent = g[v];
-        if (ent >= 0) {
-          const int64_t o = off[ent >> 24];
-          if (o >= 0) x = a.X[o + (int64_t)(ent & 0xFFFFFF) * ld + c0 + c];
-        }
+        const int32_t r = ro[(ex * P + i) + NB * ((ey * P + j) + NB * (ez * P + pl))];
+        if (r >= 0) x = a.X[(int64_t)r + c0 + c];
       }
       u[i][j] = (R)x;
       any |= (x != 0.0);
@@ -329,9 +324,8 @@ __device__ __forceinline__ void plane_operator(const ApplyParams& a, const Ctr& 
 // tensors at T[(e*8 + col)*n^3 + local]) and add them into stored rows of Y.
 template <typename R, int P, int NT>
 __device__ __forceinline__ void batch_scatter(const ApplyParams& a, const R* __restrict__ T,
-                                              const int32_t* __restrict__ g,
-                                              const int64_t* __restrict__ off, int c0, int nc,
-                                              int ld, int t) {
+                                              const int32_t* __restrict__ ro, int c0, int nc,
+                                              int t) {
   using D = Dims<P>;
   constexpr int n = D::n, n2 = D::n2, n3 = D::n3, NB = D::NB, NB3 = D::NB3;
   constexpr int TOT = NB3 * 8, K = (TOT + NT - 1) / NT;
@@ -339,13 +333,11 @@ __device__ __forceinline__ void batch_scatter(const ApplyParams& a, const R* __r
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int idx = t + k * NT;
-    ent[k] = (idx < TOT && (idx & 7) < nc) ? g[idx >> 3] : -1;
+    ent[k] = (idx < TOT && (idx & 7) < nc) ? ro[idx >> 3] : -1;
   }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     if (ent[k] < 0) continue;
-    const int64_t o = off[ent[k] >> 24];
-    if (o < 0) continue;
     const int idx = t + k * NT;
     const int col = idx & 7, v = idx >> 3;
     const int vx = v % NB, vy = (v / NB) % NB, vz = v / (NB * NB);
@@ -367,7 +359,7 @@ __device__ __forceinline__ void batch_scatter(const ApplyParams& a, const R* __r
         }
       }
     }
-    unsafeAtomicAdd(a.Y + o + (int64_t)(ent[k] & 0xFFFFFF) * ld + c0 + col, acc);
+    unsafeAtomicAdd(a.Y + (int64_t)ent[k] + c0 + col, acc);
   }
 }
 
@@ -404,38 +396,40 @@ struct BatchProc {
   };
   struct Smem {
     typename std::conditional<ALIAS, AliasBuf, SepBuf>::type b;
-    int64_t off[27];
   };
-  static __device__ __forceinline__ void run(const ApplyParams& a,
-                                             const ApplyItem* __restrict__ it, int, Smem& sm) {
+  // Gathered values of item `idx` (coalesced (node, column) order): xv[k]
+  // for entry t + k NT, with the row offsets kept in ro[k] for the flush.
+  static __device__ __forceinline__ void load(const ApplyParams& a, int64_t idx, int t,
+                                              int32_t (&ro)[K]) {
+    const int32_t* __restrict__ r = a.rowoff + idx * D::NB3;
+    const int nc = a.items[idx].nc;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int e = t + k * NT;
+      ro[k] = (e < NV && (e & 7) < nc) ? r[e >> 3] : -1;
+    }
+  }
+  static __device__ __forceinline__ void fetch(const ApplyParams& a, int c0, int t,
+                                               const int32_t (&ro)[K], double (&xv)[K]) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      xv[k] = ro[k] >= 0 ? a.X[(int64_t)ro[k] + c0 + ((t + k * NT) & 7)] : 0.0;
+  }
+  // Everything after the gather: returns without work when all values are 0.
+  static __device__ __forceinline__ void compute(const ApplyParams& a, int rank, int c0, int t,
+                                                 const int32_t (&ro)[K], const double (&xv)[K],
+                                                 Smem& sm) {
     constexpr int n = D::n, NB = D::NB;
-    const int t = threadIdx.x;
     const int c = t & 7, e = (t >> 3) & 7;
     const int pl = __builtin_amdgcn_readfirstlane(t >> 6);
     const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
-    if (t < 27) sm.off[t] = it->off[t];
-    const int rank = it->rank, c0 = it->c0, nc = it->nc, ld = it->ld;
-    __syncthreads();
-    const int32_t* __restrict__ g = a.gtab + (int64_t)rank * D::NB3;
     double* __restrict__ G = sm.b.G;
     R* __restrict__ Gr = reinterpret_cast<R*>(G);
-    // coalesced gather of the batch's (node, column) values
-    int32_t ent[K];
     bool any = false;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const int idx = t + k * NT;
-      ent[k] = -1;
-      double x = 0.0;
-      if (idx < NV && (idx & 7) < nc) {
-        const int32_t en = g[idx >> 3];
-        if (en >= 0 && sm.off[en >> 24] >= 0) {
-          ent[k] = en;
-          x = a.X[sm.off[en >> 24] + (int64_t)(en & 0xFFFFFF) * ld + c0 + (idx & 7)];
-        }
-      }
-      if (idx < NV) Gr[idx] = (R)x;
-      any |= (x != 0.0);
+      if (t + k * NT < NV) Gr[t + k * NT] = (R)xv[k];
+      any |= (xv[k] != 0.0);
     }
     if (!__syncthreads_or(any)) return;
     R u[n][n];
@@ -470,11 +464,19 @@ struct BatchProc {
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      if (ent[k] < 0) continue;
-      const int idx = t + k * NT;
-      unsafeAtomicAdd(a.Y + sm.off[ent[k] >> 24] + (int64_t)(ent[k] & 0xFFFFFF) * ld + c0 + (idx & 7),
-                      G[idx]);
+      if (ro[k] < 0) continue;
+      unsafeAtomicAdd(a.Y + (int64_t)ro[k] + c0 + ((t + k * NT) & 7), G[t + k * NT]);
     }
+  }
+  static __device__ __forceinline__ void run(const ApplyParams& a, int64_t idx, int, Smem& sm) {
+    const int t = threadIdx.x;
+    const ApplyItem* __restrict__ it = a.items + idx;
+    const int rank = it->rank, c0 = it->c0;
+    int32_t ro[K];
+    double xv[K];
+    load(a, idx, t, ro);
+    fetch(a, c0, t, ro, xv);
+    compute(a, rank, c0, t, ro, xv, sm);
   }
 };
 
@@ -484,22 +486,19 @@ struct CellProc {
   static constexpr int NT = 64, UPI = 8;
   struct Smem {
     R T[8 * D::n3];
-    int64_t off[27];
   };
-  static __device__ __forceinline__ void run(const ApplyParams& a,
-                                             const ApplyItem* __restrict__ it, int e, Smem& sm) {
+  static __device__ __forceinline__ void run(const ApplyParams& a, int64_t idx, int e, Smem& sm) {
     constexpr int n = D::n, n3 = D::n3, NB = D::NB;
     const int t = threadIdx.x;
     const int c = t & 7;
     const int pl = t >> 3;  // varies within the wave
     const bool act = pl < n;
     const int pq = act ? pl : 0;
-    if (t < 27) sm.off[t] = it->off[t];
-    const int rank = it->rank, c0 = it->c0, nc = it->nc, ld = it->ld;
-    __syncthreads();
-    const int32_t* __restrict__ g = a.gtab + (int64_t)rank * D::NB3;
+    const ApplyItem* __restrict__ it = a.items + idx;
+    const int rank = it->rank, c0 = it->c0, nc = it->nc;
+    const int32_t* __restrict__ ro = a.rowoff + idx * D::NB3;
     R u[n][n];
-    const bool any = gather_plane<R, P>(a, g, sm.off, e, pq, c, c0, nc, ld, act, u);
+    const bool any = gather_plane<R, P>(a, ro, e, pq, c, c0, nc, act, u);
     if (!__syncthreads_or(any)) return;
     R out[n][n];
     plane_operator<R, P>(a, make_ctr<R, P, MF>(a), sm.T + c * n3, pq,
@@ -510,12 +509,8 @@ struct CellProc {
     for (int j = 0; j < n; ++j)
 #pragma unroll
       for (int i = 0; i < n; ++i) {
-        const int v = (ex * P + i) + NB * ((ey * P + j) + NB * (ez * P + pq));
-        const int32_t ent = g[v];
-        if (ent < 0) continue;
-        const int64_t o = sm.off[ent >> 24];
-        if (o < 0) continue;
-        unsafeAtomicAdd(a.Y + o + (int64_t)(ent & 0xFFFFFF) * ld + c0 + c, (double)out[i][j]);
+        const int32_t r = ro[(ex * P + i) + NB * ((ey * P + j) + NB * (ez * P + pq))];
+        if (r >= 0) unsafeAtomicAdd(a.Y + (int64_t)r + c0 + c, (double)out[i][j]);
       }
   }
 };
@@ -573,18 +568,15 @@ struct RegProc {
   static constexpr int NT = 64, UPI = 1;
   struct Smem {
     R T[LDS_SUM ? 64 * D::n3 : 1];
-    int64_t off[27];
   };
-  static __device__ __forceinline__ void run(const ApplyParams& a,
-                                             const ApplyItem* __restrict__ it, int, Smem& sm) {
+  static __device__ __forceinline__ void run(const ApplyParams& a, int64_t idx, int, Smem& sm) {
     constexpr int n = D::n, n2 = D::n2, n3 = D::n3, NB = D::NB;
     const int t = threadIdx.x;
     const int c = t & 7, e = t >> 3;
     const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
-    if (t < 27) sm.off[t] = it->off[t];
-    const int rank = it->rank, c0 = it->c0, nc = it->nc, ld = it->ld;
-    __syncthreads();
-    const int32_t* __restrict__ g = a.gtab + (int64_t)rank * D::NB3;
+    const ApplyItem* __restrict__ it = a.items + idx;
+    const int rank = it->rank, c0 = it->c0, nc = it->nc;
+    const int32_t* __restrict__ ro = a.rowoff + idx * D::NB3;
     R u[n3];
     bool any = false;
 #pragma unroll
@@ -595,12 +587,8 @@ struct RegProc {
         for (int i = 0; i < n; ++i) {
           double x = 0.0;
           if (c < nc) {
-            const int v = (ex * P + i) + NB * ((ey * P + j) + NB * (ez * P + k));
-            const int32_t ent = g[v];
-            if (ent >= 0) {
-              const int64_t o = sm.off[ent >> 24];
-              if (o >= 0) x = a.X[o + (int64_t)(ent & 0xFFFFFF) * ld + c0 + c];
-            }
+            const int32_t r = ro[(ex * P + i) + NB * ((ey * P + j) + NB * (ez * P + k))];
+            if (r >= 0) x = a.X[(int64_t)r + c0 + c];
           }
           u[i + n * j + n2 * k] = (R)x;
           any |= (x != 0.0);
@@ -625,7 +613,7 @@ struct RegProc {
 #pragma unroll
       for (int q = 0; q < n3; ++q) sm.T[t * n3 + q] = w[q];
       __syncthreads();
-      batch_scatter<R, P, NT>(a, sm.T, g, sm.off, c0, nc, ld, t);
+      batch_scatter<R, P, NT>(a, sm.T, ro, c0, nc, t);
     } else {
       if (c >= nc) return;
 #pragma unroll
@@ -634,13 +622,8 @@ struct RegProc {
         for (int j = 0; j < n; ++j)
 #pragma unroll
           for (int i = 0; i < n; ++i) {
-            const int v = (ex * P + i) + NB * ((ey * P + j) + NB * (ez * P + k));
-            const int32_t ent = g[v];
-            if (ent < 0) continue;
-            const int64_t o = sm.off[ent >> 24];
-            if (o < 0) continue;
-            unsafeAtomicAdd(a.Y + o + (int64_t)(ent & 0xFFFFFF) * ld + c0 + c,
-                            (double)w[i + n * j + n2 * k]);
+            const int32_t r = ro[(ex * P + i) + NB * ((ey * P + j) + NB * (ez * P + k))];
+            if (r >= 0) unsafeAtomicAdd(a.Y + (int64_t)r + c0 + c, (double)w[i + n * j + n2 * k]);
           }
     }
   }
@@ -652,7 +635,7 @@ __global__ __launch_bounds__(Proc::NT) void apply_grid_kernel(ApplyParams a) {
   __shared__ typename Proc::Smem sm;
   const int64_t unit = xcd_item(blockIdx.x, gridDim.x);
   if (unit >= a.nitems * Proc::UPI) return;
-  Proc::run(a, a.items + unit / Proc::UPI, (int)(unit % Proc::UPI), sm);
+  Proc::run(a, unit / Proc::UPI, (int)(unit % Proc::UPI), sm);
 }
 
 // Persistent form: each workgroup pulls units from the queue of its XCD's
@@ -675,7 +658,7 @@ __global__ __launch_bounds__(Proc::NT) void apply_queue_kernel(ApplyParams a) {
       __syncthreads();
       const int64_t unit = s_unit;
       if (unit >= hi) break;
-      Proc::run(a, a.items + unit / Proc::UPI, (int)(unit % Proc::UPI), sm);
+      Proc::run(a, unit / Proc::UPI, (int)(unit % Proc::UPI), sm);
     }
   }
 }
@@ -832,30 +815,83 @@ __global__ __launch_bounds__(256) void tm_trace_kernel(TmParams p) {
 // the item ends after the check.
 template <typename R, int P, bool MF>
 __global__ __launch_bounds__(64, P == 2 ? 4 : 2) void apply_shell_kernel(ApplyParams a) {
-  using D = Dims<P>;
   using Proc = CellProc<R, P, MF>;
+  // shell items per wave: p = 2 items have few present rows (8 lanes each),
+  // p = 4 items many (the whole wave)
+  constexpr int SPW = P == 2 ? 8 : 1, LPI = 64 / SPW;
   __shared__ typename Proc::Smem sm;
-  const int64_t k = xcd_item(blockIdx.x, gridDim.x);
-  if (k >= a.nshell) return;
-  const ApplyItem* __restrict__ it = a.shell + k;
-  const int t = threadIdx.x;
-  if (t < 27) sm.off[t] = it->off[t];
-  const int rank = it->rank, c0 = it->c0, nc = it->nc, ld = it->ld;
-  __syncthreads();
-  const int32_t* __restrict__ g = a.gtab + (int64_t)rank * D::NB3;
+  const int64_t grp = xcd_item(blockIdx.x, gridDim.x);
+  const int t = threadIdx.x, sub = t / LPI, l = t % LPI;
+  const int64_t k = grp * SPW + sub;
   bool any = false;
-  for (int v = t; v < D::NB3; v += 64) {
-    const int32_t ent = g[v];
-    if (ent < 0) continue;
-    const int64_t o = sm.off[ent >> 24];
-    if (o < 0) continue;
-    const double* __restrict__ x = a.X + o + (int64_t)(ent & 0xFFFFFF) * ld + c0;
-    for (int c = 0; c < nc; ++c) any |= (x[c] != 0.0);
+  if (k < a.nshell) {
+    const ApplyItem* __restrict__ it = a.items + a.nitems + k;
+    const int c0 = it->c0, nc = it->nc;
+    const int32_t e1 = a.shell_ptr[k + 1];
+    for (int32_t e = a.shell_ptr[k] + l; e < e1; e += LPI) {
+      const double* __restrict__ x = a.X + (int64_t)a.shell_ro[e] + c0;
+      for (int c = 0; c < nc; ++c) any |= (x[c] != 0.0);
+    }
   }
-  if (!__syncthreads_or(any)) return;
-  for (int e = 0; e < 8; ++e) {
-    __syncthreads();
-    Proc::run(a, it, e, sm);
+  const uint64_t hit = __ballot(any);
+  if (hit == 0) return;
+  constexpr uint64_t sub_mask = LPI == 64 ? ~0ull : ((1ull << LPI) - 1);
+  for (int s2 = 0; s2 < SPW; ++s2) {
+    if (((hit >> (LPI * s2)) & sub_mask) == 0) continue;
+    const int64_t idx = a.nitems + grp * SPW + s2;
+    for (int e = 0; e < 8; ++e) {
+      __syncthreads();
+      Proc::run(a, idx, e, sm);
+    }
+  }
+}
+
+// Software-pipelined persistent form of BatchProc.  Workgroup w of XCD x
+// walks a strided list of the own items of x's contiguous range, then of
+// its shell items.  Before computing item j it issues the value loads of
+// item j+1 and the row-offset loads of item j+2, so the gather latency of
+// the next items overlaps the arithmetic of the current one.
+template <typename R, int P, bool MF>
+__global__ __launch_bounds__(64 * (P + 1)) void apply_pipe_kernel(ApplyParams a) {
+  using Proc = BatchProc<R, P, MF>;
+  constexpr int K = Proc::K;
+  __shared__ typename Proc::Smem sm;
+  const int t = threadIdx.x;
+  const int x = blockIdx.x & 7;
+  const int64_t w = blockIdx.x >> 3, gx = gridDim.x >> 3;
+  // per-XCD contiguous ranges of own and shell items
+  const int64_t po = (a.nitems + 7) >> 3, ps = (a.nshell + 7) >> 3;
+  const int64_t ol = min(a.nitems, x * po), oh = min(a.nitems, ol + po);
+  const int64_t sl = a.nitems + min(a.nshell, x * ps), sh = a.nitems + min(a.nshell, (x + 1) * ps);
+  const int64_t no = (oh - ol > w) ? (oh - ol - w + gx - 1) / gx : 0;
+  const int64_t ns = (sh - sl > w) ? (sh - sl - w + gx - 1) / gx : 0;
+  auto item_of = [&](int64_t j) -> int64_t {
+    if (j < no) return ol + w + j * gx;
+    if (j < no + ns) return sl + w + (j - no) * gx;
+    return -1;
+  };
+  const int64_t total = no + ns;
+  if (total == 0) return;
+  int32_t ro_c[K], ro_n[K], ro_nn[K];
+  double xv[K];
+  Proc::load(a, item_of(0), t, ro_c);
+  Proc::fetch(a, a.items[item_of(0)].c0, t, ro_c, xv);
+  if (total > 1) Proc::load(a, item_of(1), t, ro_n);
+  for (int64_t j = 0; j < total; ++j) {
+    const int64_t cur = item_of(j);
+    const int rank = a.items[cur].rank, c0 = a.items[cur].c0;
+    __syncthreads();  // the previous item is done with the LDS buffers
+    double xcur[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) xcur[k] = xv[k];
+    if (j + 1 < total) Proc::fetch(a, a.items[item_of(j + 1)].c0, t, ro_n, xv);
+    if (j + 2 < total) Proc::load(a, item_of(j + 2), t, ro_nn);
+    Proc::compute(a, rank, c0, t, ro_c, xcur, sm);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      ro_c[k] = ro_n[k];
+      ro_n[k] = ro_nn[k];
+    }
   }
 }
 
@@ -881,8 +917,26 @@ hipError_t launch_proc(const ApplyParams& p, bool queue, hipStream_t st) {
 }
 
 // kernel: even = one work unit per workgroup, odd = persistent queue
+template <typename R, int P, bool MF>
+hipError_t launch_pipe(const ApplyParams& p, hipStream_t st) {
+  if (p.nitems + p.nshell == 0) return hipSuccess;
+  int grid = p.grid;
+  if (grid <= 0) {
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(&apply_pipe_kernel<R, P, MF>), 64 * (P + 1), 0);
+    if (e != hipSuccess) return e;
+    grid = std::max(1, per_cu) * std::max(1, device_cu_count());
+  }
+  grid = std::max(8, (grid / 8) * 8);
+  hipLaunchKernelGGL((apply_pipe_kernel<R, P, MF>), dim3((unsigned)grid), dim3(64 * (P + 1)), 0,
+                     st, p);
+  return hipGetLastError();
+}
+
 template <typename R, int P, bool MF = false>
 hipError_t launch_apply_t(const ApplyParams& p, int kernel, hipStream_t st) {
+  if (kernel == 6) return launch_pipe<R, P, MF>(p, st);
   const bool queue = (kernel & 1) != 0;
   // processor: kernels 0/1 the default for the degree, 2/3 the batch
   // processor, 4/5 the single-wave processor (RegProc for p = 2, CellProc
@@ -898,7 +952,8 @@ hipError_t launch_apply_t(const ApplyParams& p, int kernel, hipStream_t st) {
     e = launch_proc<CellProc<R, P, MF>>(p, queue, st);
   }
   if (e != hipSuccess || p.nshell == 0) return e;
-  const int64_t nwg = ((p.nshell + 7) / 8) * 8;
+  const int64_t spw = P == 2 ? 8 : 1;
+  const int64_t nwg = ((p.nshell + 8 * spw - 1) / (8 * spw)) * 8;
   hipLaunchKernelGGL((apply_shell_kernel<R, P, MF>), dim3((unsigned)nwg), dim3(64), 0, st, p);
   return hipGetLastError();
 }

@@ -17,6 +17,9 @@ struct ApplyParams {
   int64_t nitems;
   const ApplyItem* shell;   // items of batches whose own block is not stored
   int64_t nshell;
+  const int32_t* rowoff;    // [own items, shell items][(2p+1)^3]: row offset of each node or -1
+  const int32_t* shell_ptr; // [nshell+1] CSR over the present rows of the shell items
+  const int32_t* shell_ro;  // present row offsets
   const int32_t* gtab;   // [rank][ (2p+1)^3 ]
   const double* cV;      // [cell 8 rank + e][ (p+1)^3 ]
   int32_t* counters;     // 8 queue counters (persistent kernel only)

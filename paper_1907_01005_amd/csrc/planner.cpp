@@ -494,6 +494,32 @@ void plan_mv(MvPlan& mv, const MeshPlan& m, int M, const double* centers, const 
   mv.n_own_items = (int64_t)mv.items.size();
   mv.items.insert(mv.items.end(), shell.begin(), shell.end());
 
+  // per item, the value offset of every batch node's row in its block of C
+  // (-1 when the node is on a Dirichlet face or its block is not stored)
+  if (mv.block_offset.back() >= ((int64_t)1 << 31))
+    throw Error(-2, "multivectors of 2^31 or more stored values are not supported");
+  mv.rowoff.assign(mv.items.size() * (size_t)NB3, -1);
+  for (size_t q = 0; q < mv.items.size(); ++q) {
+    const ApplyItem& it = mv.items[q];
+    const int32_t* g = m.gtab.data() + (size_t)it.rank * NB3;
+    int32_t* ro = mv.rowoff.data() + q * NB3;
+    for (int v = 0; v < NB3; ++v) {
+      if (g[v] < 0) continue;
+      const int64_t o = it.off[g[v] >> 24];
+      if (o < 0) continue;
+      ro[v] = (int32_t)(o + (int64_t)(g[v] & 0xFFFFFF) * it.ld);
+    }
+  }
+  // compact lists of the present row offsets of the shell items
+  mv.shell_ptr.assign(1, 0);
+  mv.shell_ro.clear();
+  for (size_t q = (size_t)mv.n_own_items; q < mv.items.size(); ++q) {
+    const int32_t* ro = mv.rowoff.data() + q * NB3;
+    for (int v = 0; v < NB3; ++v)
+      if (ro[v] >= 0) mv.shell_ro.push_back(ro[v]);
+    mv.shell_ptr.push_back((int32_t)mv.shell_ro.size());
+  }
+
   // overlap products (Alg. 8): every pair of stored blocks of a row block.
   // Partial products are stored pair by pair (row-block order within a
   // pair), so that the second stage streams one contiguous run per block of S.
