@@ -676,9 +676,11 @@ __global__ void fill_zero_kernel(double* __restrict__ p, int64_t n, int32_t* cou
 
 // -------------------------------------------------------------- overlap
 // Stage 1: one wave per block product P = X_{r,C1}^T Y_{r,C2} (Alg. 8).
-//  * |C1| = |C2| = 8: lane i takes rows i, i+64, ... and keeps the 64
-//    products of its rows in registers; a butterfly reduce-scatter across the
-//    wave leaves entry j of P in lane j.
+//  * |C1| = |C2| = 8 and at most 128 rows: lane (s, a) takes rows s, s+8, ...
+//    and column a, summed over s with an xor butterfly.
+//  * |C1| = |C2| = 8, longer blocks: lane i takes rows i, i+64, ... and keeps
+//    the 64 products of its rows in registers; a butterfly reduce-scatter
+//    across the wave leaves entry j of P in lane j.
 //  * other widths: lane (s, a) walks rows s, s+R, ... (R = 64 / |C1|) and
 //    keeps the |C2| products of column a; the R partial rows are summed in
 //    LDS in a fixed order.
@@ -694,6 +696,29 @@ __global__ __launch_bounds__(64) void tm_stage1_kernel(TmParams p) {
   const TmUnit U = p.units[u];
   const double* __restrict__ X = p.X + U.off1;
   const double* __restrict__ Y = p.Y + U.off2;
+  if (U.w1 == 8 && U.w2 == 8 && U.rows <= 128) {
+    // short row blocks: lane (s, a) takes rows s, s+8, ... and column a of X,
+    // keeping the 8 products with the columns of Y; sum over s by butterfly
+    const int s8 = lane >> 3, a8 = lane & 7;
+    double acc8[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) acc8[b] = 0.0;
+    for (int i = s8; i < U.rows; i += 8) {
+      const double x = X[(int64_t)i * 8 + a8];
+      const double* __restrict__ y = Y + (int64_t)i * 8;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) acc8[b] = __builtin_fma(x, y[b], acc8[b]);
+    }
+#pragma unroll
+    for (int m = 8; m <= 32; m <<= 1)
+#pragma unroll
+      for (int b = 0; b < 8; ++b) acc8[b] += shfl_xor_d(acc8[b], m);
+    double v = acc8[0];
+#pragma unroll
+    for (int b = 1; b < 8; ++b) v = (s8 == b) ? acc8[b] : v;
+    p.part[U.part + a8 * 8 + s8] = v;
+    return;
+  }
   if (U.w1 == 8 && U.w2 == 8 && ((U.off1 | U.off2) & 1) == 0) {
     double acc[64];
 #pragma unroll
