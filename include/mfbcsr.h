@@ -236,10 +236,14 @@ int mfb_apply_H(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X, doubl
  * selects how a unit maps onto threads: 0 = the default (currently 1),
  * 1 = a workgroup of 64(p+1) threads per (batch, 8-column chunk) with LDS
  * layout switches, 2 = one wave per unit (p = 2: the whole cell tensor in
- * registers; p = 4: one wave per cell).  kernel 6: persistent workgroups of
- * the batch mapping walking a static strided list, with the loads of the
- * next items issued before the current item is computed (no workspace).  grid: persistent workgroups (0 =
- * as many as fit on the device).  d_work: the workspace (info.work_bytes);
+ * registers; p = 4: one wave per cell).  Kernels 0 and 2 run own and shell
+ * items in one grid; the others check shell items (batches whose own block
+ * of C is not stored) in a second kernel.  kernel 6: persistent workgroups
+ * of the batch mapping walking a static strided list, with the loads of the
+ * next items issued before the current item is computed (no workspace).
+ * grid: for kernels 0 and 2, the shell items checked per wave (a power of
+ * two up to 64; 0 = 2); for the persistent kernels, the
+ * number of workgroups (0 = as many as fit on the device); else unused.  d_work: the workspace (info.work_bytes);
  * it holds the queue counters, so two tuned applies sharing a workspace must
  * not overlap in time.                                                      */
 typedef struct {

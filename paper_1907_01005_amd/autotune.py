@@ -4,8 +4,9 @@ The apply work list has uneven units (column blocks of 4-16 orbitals; batches
 with or without their own block stored), and three thread mappings
 (batch/LDS, one wave per unit, one wave per cell) each come as a one-unit-
 per-workgroup grid or as persistent workgroups pulling from a queue.  The
-tuner times every variant (and a few persistent grid sizes) on the caller's
-layout with HIP events and keeps the fastest; the choice is cached per layout
+tuner times every variant (a few persistent grid sizes, and for the fused
+grid the number of shell items each wave checks) on the caller's layout with
+HIP events and keeps the fastest; the choice is cached per layout
 signature.  `GraphLoop` captures `n` iterations of apply_H + tmmult with the
 chosen variant in one hipGraph and replays it.
 """
@@ -32,7 +33,12 @@ class TuneChoice:
     us: float          # median apply time measured by the tuner
 
     def describe(self) -> str:
-        g = f", grid {self.grid}" if (self.kernel & 1 or self.kernel == 6) else ""
+        if self.kernel & 1 or self.kernel == 6:
+            g = f", grid {self.grid}"
+        elif self.kernel in (0, 2) and self.grid:
+            g = f", {self.grid} shell items/wave"
+        else:
+            g = ""
         return f"{KERNEL_NAMES[self.kernel]}{g} ({api.PREC_NAMES[self.prec]}): {self.us:.1f} us"
 
 
@@ -47,7 +53,9 @@ def layout_signature(dp, prec: int) -> str:
 
 
 def candidates(cu_count: int) -> List[tuple]:
-    out = [(k, 0) for k in (0, 2, 4)]
+    # kernel 0: own and shell items in one grid, grid = shell items checked
+    # per wave; 4: one wave per unit; 6 and odd: persistent (grid = workgroups)
+    out = [(0, spw) for spw in (0, 1, 4, 8)] + [(4, 0)]
     for per_cu in (0, 1, 2, 3):
         out.append((6, per_cu * cu_count))
     for k in (1, 3, 5):

@@ -456,6 +456,9 @@ int mfb_apply_H_tuned(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X,
   if (tune->prec < 0 || tune->prec > 3) fail(MFB_EINVAL, "unknown precision");
   if (tune->kernel < 0 || tune->kernel > 6) fail(MFB_EINVAL, "kernel must be in 0..6");
   if (tune->grid < 0) fail(MFB_EINVAL, "negative grid");
+  if ((tune->kernel == 0 || tune->kernel == 2) &&
+      (tune->grid > 64 || (tune->grid & (tune->grid - 1)) != 0))
+    fail(MFB_EINVAL, "kernels 0 and 2 take grid = 0 or a power of two up to 64");
   if ((tune->kernel & 1) && tune->kernel != 6 && !d_work)
     fail(MFB_EINVAL, "the queue kernels need the workspace");
   mfb::gpu::ApplyParams a;

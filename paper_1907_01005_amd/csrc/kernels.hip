@@ -192,7 +192,7 @@ struct Dims {
 // Returns whether any gathered value is non-zero.
 template <typename R, int P>
 __device__ __forceinline__ bool gather_plane(const ApplyParams& a, const int32_t* __restrict__ ro,
-                                             int e, int pl, int c, int c0, int nc, bool act,
+                                             int e, int pl, int c, int nc, bool act,
                                              R (&u)[P + 1][P + 1]) {
   using D = Dims<P>;
   constexpr int n = D::n, NB = D::NB;
@@ -205,7 +205,7 @@ __device__ __forceinline__ bool gather_plane(const ApplyParams& a, const int32_t
       double x = 0.0;
       if (act && c < nc) {
         const int32_t r = ro[(ex * P + i) + NB * ((ey * P + j) + NB * (ez * P + pl))];
-        if (r >= 0) x = a.X[(int64_t)r + c0 + c];
+        if (r >= 0) x = a.X[(int64_t)r + c];
       }
       u[i][j] = (R)x;
       any |= (x != 0.0);
@@ -215,16 +215,17 @@ __device__ __forceinline__ bool gather_plane(const ApplyParams& a, const int32_t
 
 // Sum-factorised cell operator on planes.  On entry u holds the z = pl plane
 // of the nodal values (layout A); on exit Tc holds the cell's output values
-// (index i + n j + n^2 k).  Threads with act == false only join the barriers.
+// (index i + n j + n^2 k).  cv: the cell's JxW V; wg: the three gradient
+// scales (global memory or LDS copies).  Threads with act == false only join
+// the barriers.
 template <typename R, int P, class Ctr, class Hook>
-__device__ __forceinline__ void plane_operator(const ApplyParams& a, const Ctr& ctr,
-                                               R* __restrict__ Tc, int pl,
-                                               const double* __restrict__ cv, bool act,
+__device__ __forceinline__ void plane_operator(const Ctr& ctr, R* __restrict__ Tc, int pl,
+                                               const double* __restrict__ cv,
+                                               const double* __restrict__ wg, bool act,
                                                const R (&u)[P + 1][P + 1], R (&out)[P + 1][P + 1],
                                                Hook after_first_barrier) {
   using D = Dims<P>;
   constexpr int n = D::n, n2 = D::n2, n3 = D::n3;
-  const double* __restrict__ wg = a.Wg;
   R A[n][n], B[n][n];
   ctr.template c<0, false, 0>(u, A);
   ctr.template c<1, false, 0>(A, B);
@@ -324,8 +325,7 @@ __device__ __forceinline__ void plane_operator(const ApplyParams& a, const Ctr& 
 // tensors at T[(e*8 + col)*n^3 + local]) and add them into stored rows of Y.
 template <typename R, int P, int NT>
 __device__ __forceinline__ void batch_scatter(const ApplyParams& a, const R* __restrict__ T,
-                                              const int32_t* __restrict__ ro, int c0, int nc,
-                                              int t) {
+                                              const int32_t* __restrict__ ro, int nc, int t) {
   using D = Dims<P>;
   constexpr int n = D::n, n2 = D::n2, n3 = D::n3, NB = D::NB, NB3 = D::NB3;
   constexpr int TOT = NB3 * 8, K = (TOT + NT - 1) / NT;
@@ -359,7 +359,7 @@ __device__ __forceinline__ void batch_scatter(const ApplyParams& a, const R* __r
         }
       }
     }
-    unsafeAtomicAdd(a.Y + (int64_t)ent[k] + c0 + col, acc);
+    unsafeAtomicAdd(a.Y + (int64_t)ent[k] + col, acc);
   }
 }
 
@@ -397,26 +397,29 @@ struct BatchProc {
   struct Smem {
     typename std::conditional<ALIAS, AliasBuf, SepBuf>::type b;
   };
-  // Gathered values of item `idx` (coalesced (node, column) order): xv[k]
-  // for entry t + k NT, with the row offsets kept in ro[k] for the flush.
+  // The row offsets are read independently of the item record (they already
+  // hold the chunk's first column); the column count only masks them.
   static __device__ __forceinline__ void load(const ApplyParams& a, int64_t idx, int t,
                                               int32_t (&ro)[K]) {
     const int32_t* __restrict__ r = a.rowoff + idx * D::NB3;
-    const int nc = a.items[idx].nc;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int e = t + k * NT;
-      ro[k] = (e < NV && (e & 7) < nc) ? r[e >> 3] : -1;
+      ro[k] = e < NV ? r[e >> 3] : -1;
     }
+    const int nc = a.items[idx].nc;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (((t + k * NT) & 7) >= nc) ro[k] = -1;
   }
-  static __device__ __forceinline__ void fetch(const ApplyParams& a, int c0, int t,
+  static __device__ __forceinline__ void fetch(const ApplyParams& a, int t,
                                                const int32_t (&ro)[K], double (&xv)[K]) {
 #pragma unroll
     for (int k = 0; k < K; ++k)
-      xv[k] = ro[k] >= 0 ? a.X[(int64_t)ro[k] + c0 + ((t + k * NT) & 7)] : 0.0;
+      xv[k] = ro[k] >= 0 ? a.X[(int64_t)ro[k] + ((t + k * NT) & 7)] : 0.0;
   }
   // Everything after the gather: returns without work when all values are 0.
-  static __device__ __forceinline__ void compute(const ApplyParams& a, int rank, int c0, int t,
+  static __device__ __forceinline__ void compute(const ApplyParams& a, int rank, int t,
                                                  const int32_t (&ro)[K], const double (&xv)[K],
                                                  Smem& sm) {
     constexpr int n = D::n, NB = D::NB;
@@ -445,16 +448,17 @@ struct BatchProc {
     };
     R out[n][n];
     const double* cv = a.cV + ((int64_t)rank * 8 + e) * D::n3;
+    const double* wg = a.Wg;
     if constexpr (ALIAS) {
       __syncthreads();
-      plane_operator<R, P>(a, make_ctr<R, P, MF>(a), sm.b.T + (t & 63) * D::n3, pl, cv, true, u,
+      plane_operator<R, P>(make_ctr<R, P, MF>(a), sm.b.T + (t & 63) * D::n3, pl, cv, wg, true, u,
                            out, []() {});
       __syncthreads();
       zero_sums();
       __syncthreads();
     } else {
       // every thread has read its plane by the first barrier: reuse G for the sums
-      plane_operator<R, P>(a, make_ctr<R, P, MF>(a), sm.b.T + (t & 63) * D::n3, pl, cv, true, u,
+      plane_operator<R, P>(make_ctr<R, P, MF>(a), sm.b.T + (t & 63) * D::n3, pl, cv, wg, true, u,
                            out, zero_sums);
     }
 #pragma unroll
@@ -465,18 +469,16 @@ struct BatchProc {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       if (ro[k] < 0) continue;
-      unsafeAtomicAdd(a.Y + (int64_t)ro[k] + c0 + ((t + k * NT) & 7), G[t + k * NT]);
+      unsafeAtomicAdd(a.Y + (int64_t)ro[k] + ((t + k * NT) & 7), G[t + k * NT]);
     }
   }
   static __device__ __forceinline__ void run(const ApplyParams& a, int64_t idx, int, Smem& sm) {
     const int t = threadIdx.x;
-    const ApplyItem* __restrict__ it = a.items + idx;
-    const int rank = it->rank, c0 = it->c0;
     int32_t ro[K];
     double xv[K];
     load(a, idx, t, ro);
-    fetch(a, c0, t, ro, xv);
-    compute(a, rank, c0, t, ro, xv, sm);
+    fetch(a, t, ro, xv);
+    compute(a, a.items[idx].rank, t, ro, xv, sm);
   }
 };
 
@@ -495,14 +497,14 @@ struct CellProc {
     const bool act = pl < n;
     const int pq = act ? pl : 0;
     const ApplyItem* __restrict__ it = a.items + idx;
-    const int rank = it->rank, c0 = it->c0, nc = it->nc;
+    const int rank = it->rank, nc = it->nc;
     const int32_t* __restrict__ ro = a.rowoff + idx * D::NB3;
     R u[n][n];
-    const bool any = gather_plane<R, P>(a, ro, e, pq, c, c0, nc, act, u);
+    const bool any = gather_plane<R, P>(a, ro, e, pq, c, nc, act, u);
     if (!__syncthreads_or(any)) return;
     R out[n][n];
-    plane_operator<R, P>(a, make_ctr<R, P, MF>(a), sm.T + c * n3, pq,
-                         a.cV + ((int64_t)rank * 8 + e) * n3, act, u, out, []() {});
+    plane_operator<R, P>(make_ctr<R, P, MF>(a), sm.T + c * n3, pq,
+                         a.cV + ((int64_t)rank * 8 + e) * n3, a.Wg, act, u, out, []() {});
     if (!act || c >= nc) return;
     const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
 #pragma unroll
@@ -510,7 +512,7 @@ struct CellProc {
 #pragma unroll
       for (int i = 0; i < n; ++i) {
         const int32_t r = ro[(ex * P + i) + NB * ((ey * P + j) + NB * (ez * P + pq))];
-        if (r >= 0) unsafeAtomicAdd(a.Y + (int64_t)r + c0 + c, (double)out[i][j]);
+        if (r >= 0) unsafeAtomicAdd(a.Y + (int64_t)r + c, (double)out[i][j]);
       }
   }
 };
@@ -575,7 +577,7 @@ struct RegProc {
     const int c = t & 7, e = t >> 3;
     const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
     const ApplyItem* __restrict__ it = a.items + idx;
-    const int rank = it->rank, c0 = it->c0, nc = it->nc;
+    const int rank = it->rank, nc = it->nc;
     const int32_t* __restrict__ ro = a.rowoff + idx * D::NB3;
     R u[n3];
     bool any = false;
@@ -588,7 +590,7 @@ struct RegProc {
           double x = 0.0;
           if (c < nc) {
             const int32_t r = ro[(ex * P + i) + NB * ((ey * P + j) + NB * (ez * P + k))];
-            if (r >= 0) x = a.X[(int64_t)r + c0 + c];
+            if (r >= 0) x = a.X[(int64_t)r + c];
           }
           u[i + n * j + n2 * k] = (R)x;
           any |= (x != 0.0);
@@ -613,7 +615,7 @@ struct RegProc {
 #pragma unroll
       for (int q = 0; q < n3; ++q) sm.T[t * n3 + q] = w[q];
       __syncthreads();
-      batch_scatter<R, P, NT>(a, sm.T, ro, c0, nc, t);
+      batch_scatter<R, P, NT>(a, sm.T, ro, nc, t);
     } else {
       if (c >= nc) return;
 #pragma unroll
@@ -623,7 +625,7 @@ struct RegProc {
 #pragma unroll
           for (int i = 0; i < n; ++i) {
             const int32_t r = ro[(ex * P + i) + NB * ((ey * P + j) + NB * (ez * P + k))];
-            if (r >= 0) unsafeAtomicAdd(a.Y + (int64_t)r + c0 + c, (double)w[i + n * j + n2 * k]);
+            if (r >= 0) unsafeAtomicAdd(a.Y + (int64_t)r + c, (double)w[i + n * j + n2 * k]);
           }
     }
   }
@@ -851,10 +853,10 @@ __global__ __launch_bounds__(64, P == 2 ? 4 : 2) void apply_shell_kernel(ApplyPa
   bool any = false;
   if (k < a.nshell) {
     const ApplyItem* __restrict__ it = a.items + a.nitems + k;
-    const int c0 = it->c0, nc = it->nc;
+    const int nc = it->nc;
     const int32_t e1 = a.shell_ptr[k + 1];
     for (int32_t e = a.shell_ptr[k] + l; e < e1; e += LPI) {
-      const double* __restrict__ x = a.X + (int64_t)a.shell_ro[e] + c0;
+      const double* __restrict__ x = a.X + (int64_t)a.shell_ro[e];
       for (int c = 0; c < nc; ++c) any |= (x[c] != 0.0);
     }
   }
@@ -867,6 +869,85 @@ __global__ __launch_bounds__(64, P == 2 ? 4 : 2) void apply_shell_kernel(ApplyPa
     for (int e = 0; e < 8; ++e) {
       __syncthreads();
       Proc::run(a, idx, e, sm);
+    }
+  }
+}
+
+// Own and shell items in one grid.  Workgroup j of XCD x takes own item
+// x*po + j for j < po (po = own items per XCD), else shell group
+// x*pg + (j - po): the XCD's own range first, then the shell items of about
+// the same mesh region.  A shell group of NW waves checks NW*spw shell items
+// (spw per wave, 64/spw lanes each) and runs every item that holds a
+// non-zero value with the whole workgroup through BatchProc.  Both cases
+// share one call site in a workgroup-uniform loop.
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+template <typename R, int P, bool MF>
+__global__ __launch_bounds__(64 * (P + 1)) void apply_fused_kernel(ApplyParams a, int spw) {
+  using Proc = BatchProc<R, P, MF>;
+  constexpr int NW = Proc::NT / 64;
+  __shared__ typename Proc::Smem sm;
+  __shared__ uint64_t s_hit[NW];
+  const int x = blockIdx.x & 7;
+  const int64_t j = blockIdx.x >> 3;
+  const int64_t po = (a.nitems + 7) >> 3;
+  const int t = threadIdx.x;
+  if constexpr (MF) {
+    // the matrix-core form keeps a straight-line own-item path: through the
+    // loop below its register allocation costs about 9 us at p = 2
+    if (j < po) {
+      const int64_t idx = x * po + j;
+      if (idx < a.nitems) Proc::run(a, idx, 0, sm);
+      return;
+    }
+  }
+  // bit b of word w of `hit`: item base + w*spw + b/lpi of this workgroup
+  int64_t base;
+  int lpi;
+  if (j < po) {
+    base = x * po + j;
+    if (base >= a.nitems) return;
+    lpi = 64;
+    if (t == 0) s_hit[0] = 1;
+    for (int w = 1 + t; w < NW; w += Proc::NT) s_hit[w] = 0;
+  } else {
+    const int G = NW * spw;
+    lpi = 64 / spw;
+    const int64_t ng = (a.nshell + G - 1) / G, pg = (ng + 7) >> 3;
+    const int64_t g = x * pg + (j - po);
+    if (j - po >= pg || g >= ng) return;
+    const int wv = t >> 6, sub = (t & 63) / lpi, l = (t & 63) % lpi;
+    const int64_t k = g * G + wv * spw + sub;
+    bool any = false;
+    if (k < a.nshell) {
+      const int nc = a.items[a.nitems + k].nc;
+      const int32_t e1 = a.shell_ptr[k + 1];
+      for (int32_t e = a.shell_ptr[k] + l; e < e1; e += lpi) {
+        const double* __restrict__ xp = a.X + (int64_t)a.shell_ro[e];
+        for (int c = 0; c < nc; ++c) any |= (xp[c] != 0.0);
+      }
+    }
+    const uint64_t hit = __ballot(any);
+    if ((t & 63) == 0) s_hit[wv] = hit;
+    base = a.nitems + g * G;
+  }
+  __syncthreads();
+  const int per_w = 64 / lpi;
+  bool ran = false;
+  for (int w = 0; w < NW; ++w) {
+    uint64_t h = uniform64(s_hit[w]);
+    while (h != 0) {
+      const int b = __builtin_ctzll(h);
+      const int s2 = b / lpi;
+      // clear the lanes of sub-item s2
+      h &= (lpi == 64) ? 0ull : ~(((1ull << lpi) - 1) << (s2 * lpi));
+      if (ran) __syncthreads();  // the previous item is done with the LDS buffers
+      Proc::run(a, base + w * per_w + s2, 0, sm);
+      ran = true;
     }
   }
 }
@@ -900,18 +981,18 @@ __global__ __launch_bounds__(64 * (P + 1)) void apply_pipe_kernel(ApplyParams a)
   int32_t ro_c[K], ro_n[K], ro_nn[K];
   double xv[K];
   Proc::load(a, item_of(0), t, ro_c);
-  Proc::fetch(a, a.items[item_of(0)].c0, t, ro_c, xv);
+  Proc::fetch(a, t, ro_c, xv);
   if (total > 1) Proc::load(a, item_of(1), t, ro_n);
   for (int64_t j = 0; j < total; ++j) {
     const int64_t cur = item_of(j);
-    const int rank = a.items[cur].rank, c0 = a.items[cur].c0;
+    const int rank = a.items[cur].rank;
     __syncthreads();  // the previous item is done with the LDS buffers
     double xcur[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) xcur[k] = xv[k];
-    if (j + 1 < total) Proc::fetch(a, a.items[item_of(j + 1)].c0, t, ro_n, xv);
+    if (j + 1 < total) Proc::fetch(a, t, ro_n, xv);
     if (j + 2 < total) Proc::load(a, item_of(j + 2), t, ro_nn);
-    Proc::compute(a, rank, c0, t, ro_c, xcur, sm);
+    Proc::compute(a, rank, t, ro_c, xcur, sm);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       ro_c[k] = ro_n[k];
@@ -968,6 +1049,19 @@ hipError_t launch_apply_t(const ApplyParams& p, int kernel, hipStream_t st) {
   // for p = 4)
   const int proc = kernel >> 1;
   const bool batch = proc <= 1;
+  if (batch && !queue) {
+    // own and shell items in one grid; p.grid = shell items checked per wave
+    // (a power of two up to 64; 0 = 2)
+    using Proc = BatchProc<R, P, MF>;
+    int spw = p.grid > 0 ? p.grid : 2;
+    if (spw > 64 || (spw & (spw - 1)) != 0) return hipErrorInvalidValue;
+    const int64_t G = (Proc::NT / 64) * spw;
+    const int64_t po = (p.nitems + 7) >> 3, pg = ((p.nshell + G - 1) / G + 7) >> 3;
+    if (po + pg == 0) return hipSuccess;
+    hipLaunchKernelGGL((apply_fused_kernel<R, P, MF>), dim3((unsigned)(8 * (po + pg))),
+                       dim3(Proc::NT), 0, st, p, spw);
+    return hipGetLastError();
+  }
   hipError_t e;
   if (batch) {
     e = launch_proc<BatchProc<R, P, MF>>(p, queue, st);

@@ -17,13 +17,13 @@ struct ApplyParams {
   int64_t nitems;
   const ApplyItem* shell;   // items of batches whose own block is not stored
   int64_t nshell;
-  const int32_t* rowoff;    // [own items, shell items][(2p+1)^3]: row offset of each node or -1
+  const int32_t* rowoff;    // [own items, shell items][(2p+1)^3]: offset of each node's row at the item's first column, or -1
   const int32_t* shell_ptr; // [nshell+1] CSR over the present rows of the shell items
   const int32_t* shell_ro;  // present row offsets
   const int32_t* gtab;   // [rank][ (2p+1)^3 ]
   const double* cV;      // [cell 8 rank + e][ (p+1)^3 ]
   int32_t* counters;     // 8 queue counters (persistent kernel only)
-  int32_t grid;          // persistent workgroups
+  int32_t grid;          // persistent workgroups, or shell items per wave (fused grid)
   int32_t pad;
   double S[25];          // S[q*n + k] = phi_k(xq_q)
   double Dco[25];        // collocation derivative on the Gauss points

@@ -494,8 +494,9 @@ void plan_mv(MvPlan& mv, const MeshPlan& m, int M, const double* centers, const 
   mv.n_own_items = (int64_t)mv.items.size();
   mv.items.insert(mv.items.end(), shell.begin(), shell.end());
 
-  // per item, the value offset of every batch node's row in its block of C
-  // (-1 when the node is on a Dirichlet face or its block is not stored)
+  // per item, the value offset of every batch node's row in its block of C,
+  // at the item's first column (-1 when the node is on a Dirichlet face or
+  // its block is not stored)
   if (mv.block_offset.back() >= ((int64_t)1 << 31))
     throw Error(-2, "multivectors of 2^31 or more stored values are not supported");
   mv.rowoff.assign(mv.items.size() * (size_t)NB3, -1);
@@ -507,7 +508,7 @@ void plan_mv(MvPlan& mv, const MeshPlan& m, int M, const double* centers, const 
       if (g[v] < 0) continue;
       const int64_t o = it.off[g[v] >> 24];
       if (o < 0) continue;
-      ro[v] = (int32_t)(o + (int64_t)(g[v] & 0xFFFFFF) * it.ld);
+      ro[v] = (int32_t)(o + (int64_t)(g[v] & 0xFFFFFF) * it.ld + it.c0);
     }
   }
   // compact lists of the present row offsets of the shell items

@@ -105,7 +105,7 @@ struct MvPlan {
   std::vector<int64_t> block_offset; // nblocks + 1
   std::vector<ApplyItem> items;      // own items (batch's own block stored) then shell items
   int64_t n_own_items = 0;
-  std::vector<int32_t> rowoff;       // [item][(2p+1)^3] value offset of each node's row, or -1
+  std::vector<int32_t> rowoff;       // [item][(2p+1)^3] value offset of each node's row at the item's first column, or -1
   std::vector<int32_t> shell_ptr;    // [nshell+1] CSR over the shell items' present rows
   std::vector<int32_t> shell_ro;     // present row offsets of the shell items
   int64_t apply_pairs = 0, apply_pairs_own = 0;

@@ -28,6 +28,8 @@ def _run(dp, prec, tuned=None):
     import torch
     if tuned is None:
         dp.apply(prec)
+    elif isinstance(tuned, tuple):
+        dp.apply_tuned(prec, kernel=tuned[0], grid=tuned[1])
     else:
         dp.apply_tuned(prec, kernel=tuned)
     dp.overlap()
@@ -82,6 +84,36 @@ def test_generic_values_ragged_blocks(degree):
     for kernel in range(1, 7):
         _check_full(wl, op, dp, 0, TOL64, tuned=kernel)
         _check_full(wl, op, dp, 2, TOL32, tuned=kernel)
+    for spw in (1, 4, 64):
+        _check_full(wl, op, dp, 0, TOL64, tuned=(0, spw))
+
+
+@pytest.mark.parametrize("degree", [2, 4])
+def test_few_nonzero_shell_items(degree):
+    """Orbital values plus a few values at stored entries off the supports:
+    only some shell items of a checked group hold non-zeros."""
+    from oracle.pattern import entry_coords
+    wl = _small((8, 6, 4), degree, 29, 2.2, 11, sizes=[8, 5, 12, 4])
+    say(f"few non-zero shell items Q{degree}")
+    op = OracleProblem(wl)
+    node, orb = entry_coords(op.pattern)
+    dmask = op.mesh.dirichlet_mask()
+    n_all = int(op.mesh.ndofs)
+    on_support = np.zeros(n_all * wl.M, dtype=bool)
+    on_support[op.node.astype(np.int64) * wl.M + op.orb] = True
+    free = np.flatnonzero(~on_support[node.astype(np.int64) * wl.M + orb] & ~dmask[node])
+    rng = np.random.default_rng(17)
+    pick = rng.choice(free, size=min(12, len(free)), replace=False)
+    op.node = np.concatenate([op.node, node[pick]])
+    op.orb = np.concatenate([op.orb, orb[pick].astype(op.orb.dtype)])
+    op.val = np.concatenate([op.val, rng.standard_normal(len(pick))])
+    dp = device_problem(wl)
+    dp.set_X_coo(op.node, op.orb, op.val)
+    _check_full(wl, op, dp, 0, TOL64)
+    for spw in (1, 2, 8, 64):
+        _check_full(wl, op, dp, 0, TOL64, tuned=(0, spw))
+    _check_full(wl, op, dp, 2, TOL32, tuned=(0, 4))
+    _check_full(wl, op, dp, 0, TOL64, tuned=1)
 
 
 def test_natural_bc_lexicographic_free_faces():
