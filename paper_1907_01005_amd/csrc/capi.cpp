@@ -52,7 +52,7 @@ std::vector<double> grad_scales(const mfb::MeshPlan& m) {
 struct MvLayout {
   size_t off_items = 0, off_units = 0, off_pair_tab = 0, off_pair_ptr = 0, off_pair_list = 0,
          off_cb_of_col = 0, off_cb_start = 0, off_blk_off = 0, off_blk_col0 = 0, off_blk_w = 0,
-         off_rowoff = 0, off_shell_ptr = 0, off_shell_ro = 0, bytes = 0;
+         off_rowoff = 0, off_shell_ptr = 0, off_shell_ro = 0, off_s2 = 0, bytes = 0;
 };
 
 MvLayout mv_layout(const mfb::MvPlan& v) {
@@ -84,6 +84,8 @@ MvLayout mv_layout(const mfb::MvPlan& v) {
   o = align256(o + sizeof(int32_t) * v.shell_ptr.size());
   L.off_shell_ro = o;
   o = align256(o + sizeof(int32_t) * v.shell_ro.size());
+  L.off_s2 = o;
+  o = align256(o + sizeof(mfb::S2Desc) * v.s2.size());
 
   L.bytes = std::max<size_t>(o, 256);
   return L;
@@ -376,6 +378,7 @@ int mfb_mv_bind(mfb_mv* mv, void* d_meta, void* stream) {
   put(L.off_rowoff, p.rowoff.data(), sizeof(int32_t) * p.rowoff.size());
   put(L.off_shell_ptr, p.shell_ptr.data(), sizeof(int32_t) * p.shell_ptr.size());
   put(L.off_shell_ro, p.shell_ro.data(), sizeof(int32_t) * p.shell_ro.size());
+  put(L.off_s2, p.s2.data(), sizeof(mfb::S2Desc) * p.s2.size());
 
   {
     std::vector<int32_t> col0(p.colidx.size()), wid(p.colidx.size());
@@ -486,12 +489,14 @@ int mfb_tmmult(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d
   t.Y = d_Y;
   t.units = (const mfb::TmUnit*)(mb + mv->lay.off_units);
   t.nunits = (int64_t)p.units.size();
+  for (int c = 0; c < 4; ++c) t.class_end[c] = p.tm_class_end[c];
   t.part = (double*)((char*)d_work + kCounterBytes);
   t.pair_tab = (const int32_t*)(mb + mv->lay.off_pair_tab);
   t.pair_ptr = (const int32_t*)(mb + mv->lay.off_pair_ptr);
   t.pair_list = (const int64_t*)(mb + mv->lay.off_pair_list);
   t.cb_of_col = (const int32_t*)(mb + mv->lay.off_cb_of_col);
   t.cb_start = (const int32_t*)(mb + mv->lay.off_cb_start);
+  t.s2 = (const mfb::S2Desc*)(mb + mv->lay.off_s2);
   t.M = p.M;
   t.ncb = p.ncb;
 

@@ -677,34 +677,36 @@ __global__ void fill_zero_kernel(double* __restrict__ p, int64_t n, int32_t* cou
 }
 
 // -------------------------------------------------------------- overlap
-// Stage 1: one wave per block product P = X_{r,C1}^T Y_{r,C2} (Alg. 8).
-//  * |C1| = |C2| = 8 and at most 128 rows: lane (s, a) takes rows s, s+8, ...
-//    and column a, summed over s with an xor butterfly.
-//  * |C1| = |C2| = 8, longer blocks: lane i takes rows i, i+64, ... and keeps
-//    the 64 products of its rows in registers; a butterfly reduce-scatter
-//    across the wave leaves entry j of P in lane j.
-//  * other widths: lane (s, a) walks rows s, s+R, ... (R = 64 / |C1|) and
-//    keeps the |C2| products of column a; the R partial rows are summed in
-//    LDS in a fixed order.
-// Both orders are fixed, so the result is bitwise reproducible.
+// Stage 1 of Alg. 8: one workgroup per block product X_{r,C1}^T Y_{r,C2},
+// written to its own slot of the partial products.  The planner sorts the
+// units into four classes, one kernel each (own thread count, register
+// budget and occupancy).  Every sum is taken in a fixed order, so the result
+// is bitwise reproducible.
+//  * 8x8 blocks of at most 128 rows: lane (s, a) takes rows s, s+8, ... and
+//    column a, summed over s with an xor butterfly.
+//  * longer 8x8 blocks with even offsets: each lane takes every 64th row and
+//    keeps the 64 products of its rows in registers; a butterfly
+//    reduce-scatter across the wave leaves entry j of the product in lane j.
+//  * other widths: fp64 matrix-core products over groups of 4 rows, one
+//    wave up to 128 rows, four waves beyond.
 __device__ __forceinline__ double shfl_xor_d(double v, int m) {
   return __shfl_xor(v, m, 64);
 }
 
-__global__ __launch_bounds__(64) void tm_stage1_kernel(TmParams p) {
-  __shared__ double red[64][17];
+template <int CLASS>
+__global__ __launch_bounds__(64) void tm_stage1_kernel(TmParams p, int64_t first) {
   const int lane = threadIdx.x;
-  const int64_t u = blockIdx.x;
-  const TmUnit U = p.units[u];
+  const TmUnit U = p.units[first + blockIdx.x];
   const double* __restrict__ X = p.X + U.off1;
   const double* __restrict__ Y = p.Y + U.off2;
-  if (U.w1 == 8 && U.w2 == 8 && U.rows <= 128) {
-    // short row blocks: lane (s, a) takes rows s, s+8, ... and column a of X,
-    // keeping the 8 products with the columns of Y; sum over s by butterfly
+  if constexpr (CLASS == 0) {
+    // short 8x8 blocks: lane (s, a) takes rows s, s+8, ... and column a of
+    // X, keeping the 8 products with the columns of Y; sum over s by butterfly
     const int s8 = lane >> 3, a8 = lane & 7;
     double acc8[8];
 #pragma unroll
     for (int b = 0; b < 8; ++b) acc8[b] = 0.0;
+#pragma unroll 4
     for (int i = s8; i < U.rows; i += 8) {
       const double x = X[(int64_t)i * 8 + a8];
       const double* __restrict__ y = Y + (int64_t)i * 8;
@@ -719,9 +721,9 @@ __global__ __launch_bounds__(64) void tm_stage1_kernel(TmParams p) {
 #pragma unroll
     for (int b = 1; b < 8; ++b) v = (s8 == b) ? acc8[b] : v;
     p.part[U.part + a8 * 8 + s8] = v;
-    return;
-  }
-  if (U.w1 == 8 && U.w2 == 8 && ((U.off1 | U.off2) & 1) == 0) {
+  } else if constexpr (CLASS == 1) {
+    // long 8x8 blocks with even offsets: lane i takes rows i, i + 64, ...
+    // with 16-byte loads and keeps all 64 products
     double acc[64];
 #pragma unroll
     for (int j = 0; j < 64; ++j) acc[j] = 0.0;
@@ -753,52 +755,79 @@ __global__ __launch_bounds__(64) void tm_stage1_kernel(TmParams p) {
       }
     }
     p.part[U.part + lane] = acc[0];
-    return;
-  }
-  const int w1 = U.w1, w2 = U.w2;
-  const int R = 64 / w1;
-  const int s = lane / w1, col = lane - s * w1;
-  double acc[16];
-#pragma unroll
-  for (int b = 0; b < 16; ++b) acc[b] = 0.0;
-  if (s < R) {
-    for (int i = s; i < U.rows; i += R) {
-      const double x = X[(int64_t)i * w1 + col];
-      const double* __restrict__ y = Y + (int64_t)i * w2;
-#pragma unroll
-      for (int b = 0; b < 16; ++b)
-        if (b < w2) acc[b] = __builtin_fma(x, y[b], acc[b]);
-    }
-  }
-#pragma unroll
-  for (int b = 0; b < 16; ++b) red[lane][b] = acc[b];
-  __syncthreads();
-  for (int idx = lane; idx < w1 * w2; idx += 64) {
-    const int aa = idx / w2, bb = idx - aa * w2;
-    double sum = 0.0;
-    for (int g = 0; g < R; ++g) sum += red[g * w1 + aa][bb];
-    p.part[U.part + idx] = sum;
   }
 }
 
-// Stage 2: one workgroup per block (C1, C2) of S.  Thread groups split the
-// block's run of partial products and are combined in a fixed order; blocks
-// outside the product pattern are written as zeros.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Stage 1 for other widths (up to 16) on the fp64 matrix cores: the product
+// is a chain of 16x16x4 products over groups of 4 rows, zero-padded.  In
+// v_mfma_f64_16x16x4f64 lane l supplies A(l % 16, l / 16) and
+// B(l / 16, l % 16) and receives rows l / 16 + 4 r (r = 0..3) of column
+// l % 16 of the result; here A = X^T and B = Y, so lane l loads column l % 16
+// of row 4 g + l / 16 of both blocks.  Wave w of NW takes the row groups
+// g = w, w + NW, ... dealt round robin to NACC accumulators; accumulators and
+// waves are summed in a fixed order.
+template <int NW, int NACC>
+__global__ __launch_bounds__(64 * NW) void tm_stage1_mfma_kernel(TmParams p, int64_t first) {
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, col = l & 15, kr = l >> 4;
+  const TmUnit U = p.units[first + blockIdx.x];
+  const int w1 = U.w1, w2 = U.w2, rows = U.rows;
+  const bool okx = col < w1, oky = col < w2;
+  const double* __restrict__ X = p.X + U.off1 + (okx ? col : 0);
+  const double* __restrict__ Y = p.Y + U.off2 + (oky ? col : 0);
+  v4d acc[NACC];
+#pragma unroll
+  for (int q = 0; q < NACC; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int i0 = 4 * wv; i0 < rows; i0 += 4 * NW * NACC) {
+#pragma unroll
+    for (int q = 0; q < NACC; ++q) {
+      const int i = i0 + 4 * NW * q + kr;
+      const double a = (okx && i < rows) ? X[(int64_t)i * w1] : 0.0;
+      const double b = (oky && i < rows) ? Y[(int64_t)i * w2] : 0.0;
+      acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
+    }
+  }
+  v4d t = acc[0];
+#pragma unroll
+  for (int q = 1; q < NACC; ++q) t += acc[q];
+  if constexpr (NW > 1) {
+    __shared__ double red[NW][4][64];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[wv][r][l] = t[r];
+    __syncthreads();
+    if (wv != 0) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double v = red[0][r][l];
+#pragma unroll
+      for (int q = 1; q < NW; ++q) v += red[q][r][l];
+      t[r] = v;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int a = kr + 4 * r;
+    if (a < w1 && oky) p.part[U.part + a * w2 + col] = t[r];
+  }
+}
+
 __global__ __launch_bounds__(256) void tm_stage2_kernel(TmParams p) {
   __shared__ double red[256];
   const int t = threadIdx.x;
-  const int C1 = blockIdx.x / p.ncb, C2 = blockIdx.x - C1 * p.ncb;
-  const int c1 = p.cb_start[C1], c2 = p.cb_start[C2];
-  const int w1 = p.cb_start[C1 + 1] - c1, w2 = p.cb_start[C2 + 1] - c2;
-  const int E = w1 * w2;
+  const S2Desc d = p.s2[blockIdx.x];
+  const int E = d.w1 * d.w2;
+  if (d.n == 0) {  // block outside the product pattern
+    if (t < E) p.S[(int64_t)(d.c1 + t / d.w2) * p.M + (d.c2 + t % d.w2)] = 0.0;
+    return;
+  }
   const int G = 256 / E;
   const int g = t / E, e = t - g * E;
-  const int pid = p.pair_tab[(int64_t)C1 * p.ncb + C2];
   double sum = 0.0;
-  if (pid >= 0 && g < G) {
+  if (g < G) {
     // the pair's n partial products lie back to back: part[base + k E + e]
-    const int n = p.pair_ptr[pid + 1] - p.pair_ptr[pid];
-    const double* __restrict__ src = p.part + p.pair_list[pid] + e;
+    const int n = d.n;
+    const double* __restrict__ src = p.part + d.base + e;
     int k = g;
     double s1 = 0.0, s2 = 0.0, s3 = 0.0;
     for (; k + 3 * G < n; k += 4 * G) {
@@ -815,12 +844,10 @@ __global__ __launch_bounds__(256) void tm_stage2_kernel(TmParams p) {
   if (t < E) {
     double tot = 0.0;
     for (int q = 0; q < G; ++q) tot += red[q * E + t];
-    const int a = t / w2, b = t - (t / w2) * w2;
-    p.S[(int64_t)(c1 + a) * p.M + (c2 + b)] = tot;
+    const int a = t / d.w2, b = t - a * d.w2;
+    p.S[(int64_t)(d.c1 + a) * p.M + (d.c2 + b)] = tot;
   }
 }
-
-// Stage 3: trace of S (its diagonal) with a fixed-shape tree reduction.
 __global__ __launch_bounds__(256) void tm_trace_kernel(TmParams p) {
   __shared__ double red[256];
   const int t = threadIdx.x;
@@ -1133,8 +1160,19 @@ int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t
 
 int launch_tmmult(const TmParams& p, void* stream) {
   hipStream_t st = (hipStream_t)stream;
-  if (p.nunits > 0) {
-    hipLaunchKernelGGL(tm_stage1_kernel, dim3((unsigned)p.nunits), dim3(64), 0, st, p);
+  const int64_t* ce = p.class_end;
+  if (ce[0] > 0)
+    hipLaunchKernelGGL(tm_stage1_kernel<0>, dim3((unsigned)ce[0]), dim3(64), 0, st, p, (int64_t)0);
+  if (ce[1] > ce[0])
+    hipLaunchKernelGGL(tm_stage1_kernel<1>, dim3((unsigned)(ce[1] - ce[0])), dim3(64), 0, st, p,
+                       ce[0]);
+  if (ce[2] > ce[1])
+    hipLaunchKernelGGL((tm_stage1_mfma_kernel<1, 2>), dim3((unsigned)(ce[2] - ce[1])), dim3(64), 0,
+                       st, p, ce[1]);
+  if (ce[3] > ce[2])
+    hipLaunchKernelGGL((tm_stage1_mfma_kernel<4, 2>), dim3((unsigned)(ce[3] - ce[2])), dim3(256), 0,
+                       st, p, ce[2]);
+  {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
   }

@@ -37,12 +37,14 @@ struct TmParams {
   const double* Y;
   const TmUnit* units;
   int64_t nunits;
+  int64_t class_end[4];      // cumulative unit counts of the four stage-1 kernel classes
   double* part;
   const int32_t* pair_tab;   // [ncb*ncb]
   const int32_t* pair_ptr;   // [npairs+1] prefix counts of partial products per pair
   const int64_t* pair_list;  // [npairs] offset of each pair's contiguous partials
   const int32_t* cb_of_col;  // [M]
   const int32_t* cb_start;   // [ncb+1]
+  const S2Desc* s2;          // [ncb*ncb] blocks of S for the second stage
   int32_t M, ncb;
   double* S;
   double* trace;

@@ -573,6 +573,30 @@ void plan_mv(MvPlan& mv, const MeshPlan& m, int M, const double* centers, const 
         mv.units.push_back(u);
       }
   }
+  mv.s2.assign((size_t)ncb * ncb, S2Desc{0, 0, 0, 0, 0, 0, 0});
+  for (int C1 = 0; C1 < ncb; ++C1)
+    for (int C2 = 0; C2 < ncb; ++C2) {
+      S2Desc& d = mv.s2[(size_t)C1 * ncb + C2];
+      const int32_t pid = mv.pair_tab[(size_t)C1 * ncb + C2];
+      d.base = pid >= 0 ? mv.pair_list[pid] : 0;
+      d.n = pid >= 0 ? mv.pair_ptr[pid + 1] - mv.pair_ptr[pid] : 0;
+      d.c1 = mv.cb_start[C1];
+      d.c2 = mv.cb_start[C2];
+      d.w1 = w[C1];
+      d.w2 = w[C2];
+    }
+  // one overlap kernel per class, each with its own thread count and
+  // register budget
+  auto tm_class = [](const TmUnit& u) {
+    const bool shortb = u.rows <= 128;
+    if (u.w1 == 8 && u.w2 == 8 && (shortb || ((u.off1 | u.off2) & 1) == 0)) return shortb ? 0 : 1;
+    return shortb ? 2 : 3;
+  };
+  std::stable_sort(mv.units.begin(), mv.units.end(),
+                   [&](const TmUnit& x, const TmUnit& y) { return tm_class(x) < tm_class(y); });
+  mv.tm_class_end.fill(0);
+  for (const TmUnit& u : mv.units)
+    for (int c = tm_class(u); c < 4; ++c) ++mv.tm_class_end[c];
 }
 
 }  // namespace mfb

@@ -4,6 +4,7 @@
 // device memory by the bind calls and read by the kernels in kernels.hip.
 #pragma once
 
+#include <array>
 #include <cstdint>
 #include <stdexcept>
 #include <string>
@@ -93,6 +94,14 @@ struct TmUnit {
 };
 static_assert(sizeof(TmUnit) == 40, "TmUnit layout");
 
+// One block of S for the second overlap stage: its pair's n partial
+// products start at part[base] (n = 0: the block is outside the pattern).
+struct S2Desc {
+  int64_t base;
+  int32_t n, c1, c2, w1, w2, pad;
+};
+static_assert(sizeof(S2Desc) == 32, "S2Desc layout");
+
 struct MvPlan {
   const MeshPlan* mesh = nullptr;
   int M = 0, ncb = 0;
@@ -109,7 +118,11 @@ struct MvPlan {
   std::vector<int32_t> shell_ptr;    // [nshell+1] CSR over the shell items' present rows
   std::vector<int32_t> shell_ro;     // present row offsets of the shell items
   int64_t apply_pairs = 0, apply_pairs_own = 0;
-  std::vector<TmUnit> units;
+  std::vector<TmUnit> units;         // Alg. 8 block products, sorted by kernel class:
+  // 0: 8x8 blocks of at most 128 rows, 1: longer 8x8 blocks with even
+  // offsets, 2: other blocks of at most 128 rows, 3: the rest
+  std::array<int64_t, 4> tm_class_end{};  // cumulative unit counts per class
+  std::vector<S2Desc> s2;            // [ncb*ncb] blocks of S
   int64_t part_doubles = 0;
   std::vector<int32_t> pair_tab;     // ncb*ncb -> pair id or -1
   std::vector<int32_t> pair_ptr;     // npairs + 1: prefix count of partial products per pair

@@ -139,6 +139,7 @@ def test_uneven_blocks_640_orbitals_sampled(mesh_index):
     sel_orbs = np.concatenate([op.block_orbitals(C) for C in blocks])
     sel = np.isin(orb, sel_orbs)
     Yo = oracle_Y_at(op, node[sel], orb[sel], blocks)
+    import scipy.sparse as sp
     import torch
     for prec, tol in ((FP64, 1e-12), (FP32_MFMA, 1e-5)):
         dp.apply(prec)
@@ -147,3 +148,21 @@ def test_uneven_blocks_640_orbitals_sampled(mesh_index):
         e = rel_fro(Yg[sel], Yo)
         say(f"640 orbitals mesh {mesh_index} prec={prec}: relY(sampled) {e:.2e}")
         assert e <= tol
+    # S = X^T Y over the stored entries (Alg. 8), against a sparse product of
+    # the same device values: every block class of the overlap kernels
+    dp.overlap()
+    torch.cuda.synchronize()
+    S = dp.S_original_order()
+    tr = float(dp.trace.cpu()[0])
+    Xg = dp.X.cpu().numpy()[:dp.nvalues]
+    shape = (int(node.max()) + 1, wl.M)
+    Xs = sp.csc_matrix((Xg, (node, orb)), shape=shape)
+    Ys = sp.csc_matrix((Yg, (node, orb)), shape=shape)
+    Sr = (Xs.T @ Ys).toarray()
+    eS = rel_fro(S, Sr)
+    et = abs(tr - np.trace(Sr)) / abs(np.trace(Sr))
+    say(f"640 orbitals mesh {mesh_index}: relS {eS:.2e} relTr {et:.2e}")
+    assert eS <= 1e-12 and et <= 1e-12
+    Sa = dp.S.cpu().numpy().copy()
+    dp.overlap()
+    assert np.array_equal(Sa, dp.S.cpu().numpy())
