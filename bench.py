@@ -263,7 +263,7 @@ def main(argv=None):
         roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": gbs / HBM_PEAK_GBS}
     roof.update({"traffic": measured_traffic(wl.name, args.prec),
-                 "kernel": "apply_H (fill_zero_kernel + apply_grid_kernel<BatchProc> + apply_shell_kernel)",
+                 "kernel": "apply_H launch (fill_zero_kernel + apply_fused_kernel)",
                  "algorithmic_bytes": alg["bytes"], "algorithmic_flops": alg["flops"],
                  "avg_launch_s": t_ap, "hbm_frac": gbs / HBM_PEAK_GBS,
                  "alu_frac": tfl / peak_f})
