@@ -97,7 +97,8 @@ class Server:
         self.max_slots = int(max_slots)
 
     def run(self, requests: Sequence[Request], realtime: bool = True,
-            poll_s: float = 0.0005) -> ServeReport:
+            poll_s: float = 0.0005, progress=None) -> ServeReport:
+        """progress: optional callable, given (finished, total) after each request."""
         rep = ServeReport()
         queue = sorted(requests, key=lambda r: r.arrival)
         arrived: List[Tuple[Request, Future]] = []
@@ -143,6 +144,8 @@ class Server:
                     rep.results[s.req.rid] = res
                     in_use -= self.ex.footprint(s.handle)
                     self.ex.release(s.handle)
+                    if progress is not None:
+                        progress(len(rep.results), len(queue))
                 else:
                     still.append(s)
             active = still
