@@ -99,10 +99,15 @@ def measured_traffic(workload: str, prec: str):
     return rec.get("apply_H_bytes_per_launch")
 
 
-def build_problem(cfg: int, mesh_index: int = 0):
+def build_problem(cfg: int, mesh_index: int = 0, radius: float = 0.0):
+    """The seeded workload of configuration `cfg` on the GPU; radius > 0 replaces the
+    support radius (same centres, potential and blocks; a different workload)."""
+    import dataclasses
     import synth
     from paper_1907_01005_amd.problem import DeviceProblem
     wl = synth.make_workload(cfg)
+    if radius > 0:
+        wl = dataclasses.replace(wl, radius=float(radius), name=f"{wl.name}-r{radius:g}")
     ms = wl.meshes[mesh_index]
     dp = DeviceProblem((ms.nx, ms.ny, ms.nz), ms.L, ms.degree, ms.dirichlet, wl.centres,
                        wl.radius, wl.colblock_sizes, lambda P: synth.potential_at(wl, P))
@@ -243,6 +248,9 @@ def main(argv=None):
     ap.add_argument("--prec", default="fp64", choices=sorted(PRECS))
     ap.add_argument("--config", type=int, default=2, choices=[2, 3])
     ap.add_argument("--kernel", type=int, default=0, choices=[0, 1])
+    ap.add_argument("--radius", type=float, default=0.0,
+                    help="replace the support radius (e.g. 16: the paper's density, ~575 MB "
+                         "of X at config 2; not the baseline workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--config4", action="store_true",
@@ -264,7 +272,7 @@ def main(argv=None):
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     print(f"[bench] building config {args.config}", file=sys.stderr, flush=True)
-    wl, dp = build_problem(args.config)
+    wl, dp = build_problem(args.config, radius=args.radius)
     degree = wl.mesh.degree
     prec = PRECS[args.prec]
     alg = algorithmic(dp, degree)

@@ -694,9 +694,11 @@ __device__ __forceinline__ double shfl_xor_d(double v, int m) {
 }
 
 template <int CLASS>
-__global__ __launch_bounds__(64) void tm_stage1_kernel(TmParams p, int64_t first) {
+__global__ __launch_bounds__(64) void tm_stage1_kernel(TmParams p, int64_t first, int64_t count) {
   const int lane = threadIdx.x;
-  const TmUnit U = p.units[first + blockIdx.x];
+  const int64_t u = xcd_item(blockIdx.x, gridDim.x);
+  if (u >= count) return;
+  const TmUnit U = p.units[first + u];
   const double* __restrict__ X = p.X + U.off1;
   const double* __restrict__ Y = p.Y + U.off2;
   if constexpr (CLASS == 0) {
@@ -769,9 +771,12 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // g = w, w + NW, ... dealt round robin to NACC accumulators; accumulators and
 // waves are summed in a fixed order.
 template <int NW, int NACC>
-__global__ __launch_bounds__(64 * NW) void tm_stage1_mfma_kernel(TmParams p, int64_t first) {
+__global__ __launch_bounds__(64 * NW) void tm_stage1_mfma_kernel(TmParams p, int64_t first,
+                                                               int64_t count) {
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, col = l & 15, kr = l >> 4;
-  const TmUnit U = p.units[first + blockIdx.x];
+  const int64_t u = xcd_item(blockIdx.x, gridDim.x);
+  if (u >= count) return;
+  const TmUnit U = p.units[first + u];
   const int w1 = U.w1, w2 = U.w2, rows = U.rows;
   const bool okx = col < w1, oky = col < w2;
   const double* __restrict__ X = p.X + U.off1 + (okx ? col : 0);
@@ -1160,18 +1165,19 @@ int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t
 
 int launch_tmmult(const TmParams& p, void* stream) {
   hipStream_t st = (hipStream_t)stream;
+  // units in XCD-contiguous ranges (xcd_item): the products of one row block
+  // run on one XCD, close in time, and share its L2 for the X and Y blocks
   const int64_t* ce = p.class_end;
-  if (ce[0] > 0)
-    hipLaunchKernelGGL(tm_stage1_kernel<0>, dim3((unsigned)ce[0]), dim3(64), 0, st, p, (int64_t)0);
-  if (ce[1] > ce[0])
-    hipLaunchKernelGGL(tm_stage1_kernel<1>, dim3((unsigned)(ce[1] - ce[0])), dim3(64), 0, st, p,
-                       ce[0]);
-  if (ce[2] > ce[1])
-    hipLaunchKernelGGL((tm_stage1_mfma_kernel<1, 2>), dim3((unsigned)(ce[2] - ce[1])), dim3(64), 0,
-                       st, p, ce[1]);
-  if (ce[3] > ce[2])
-    hipLaunchKernelGGL((tm_stage1_mfma_kernel<4, 2>), dim3((unsigned)(ce[3] - ce[2])), dim3(256), 0,
-                       st, p, ce[2]);
+  auto launch = [&](auto kernel, int c, int threads) {
+    const int64_t lo = c ? ce[c - 1] : 0, n = ce[c] - lo;
+    if (n <= 0) return;
+    const int64_t nwg = ((n + 7) / 8) * 8;
+    hipLaunchKernelGGL(kernel, dim3((unsigned)nwg), dim3(threads), 0, st, p, lo, n);
+  };
+  launch(tm_stage1_kernel<0>, 0, 64);
+  launch(tm_stage1_kernel<1>, 1, 64);
+  launch(tm_stage1_mfma_kernel<1, 2>, 2, 64);
+  launch(tm_stage1_mfma_kernel<4, 2>, 3, 256);
   {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
