@@ -15,6 +15,10 @@ only reaches stored blocks; the destination here has the pattern of X):
 
 Overlap (Alg. 8 / eq. inner2): S = X^T Y, and its trace sum_a X_a . Y_a
 (eq. G_ops4 with D = X, G = Y).
+
+With the closure pattern (``oracle.pattern.closure_pattern``) as the
+destination, nothing of H X or M X is dropped, so X^T (H X) and X^T (M X) are
+the projected matrices Hbar and Mbar of eq. energy, and the energy follows.
 """
 
 from __future__ import annotations
@@ -27,14 +31,21 @@ from .mesh import BoxMesh
 from .pattern import Pattern
 
 
+def element_masses(mesh: BoxMesh, cells: np.ndarray) -> np.ndarray:
+    """M_K for the listed cells (the same on every cell of a uniform box)."""
+    Mk = mass_matrix(mesh.p, mesh.h)
+    return np.broadcast_to(Mk, (len(cells),) + Mk.shape)
+
+
 def element_hamiltonians(mesh: BoxMesh, v_qp: np.ndarray, cells: np.ndarray) -> np.ndarray:
     """H_K for the listed cells (indices into the lexicographic cell order)."""
     return hamiltonian_matrices(mesh.p, mesh.h, np.asarray(v_qp)[cells])
 
 
 def apply_hamiltonian(mesh: BoxMesh, v_qp: np.ndarray, Xg: np.ndarray,
-                      chunk: int = 4096) -> np.ndarray:
-    """Y = H X on the non-Dirichlet nodes for a dense (N, m) block of columns."""
+                      chunk: int = 4096, op: str = "H") -> np.ndarray:
+    """Y = H X (op "H") or Y = M X (op "M", the mass matrix of eq. fe_matrices)
+    on the non-Dirichlet nodes for a dense (N, m) block of columns."""
     Xg = np.asarray(Xg, dtype=np.float64)
     if Xg.ndim == 1:
         Xg = Xg[:, None]
@@ -48,7 +59,7 @@ def apply_hamiltonian(mesh: BoxMesh, v_qp: np.ndarray, Xg: np.ndarray,
     m = X.shape[1]
     for s in range(0, len(active), chunk):
         cells = active[s:s + chunk]
-        H = element_hamiltonians(mesh, v_qp, cells)    # (c, n3, n3)
+        H = element_hamiltonians(mesh, v_qp, cells) if op == "H" else element_masses(mesh, cells)
         idx = dofs[cells]                              # (c, n3)
         Yk = H @ X[idx]                                # (c, n3, m)
         np.add.at(Y, idx.ravel(), Yk.reshape(-1, m))
@@ -62,9 +73,10 @@ def block_mask(pat: Pattern, orbs) -> np.ndarray:
     return pat.stored[pat.node_rb[:, None], pat.orb_cb[orbs][None, :]]
 
 
-def masked_apply(pat: Pattern, v_qp: np.ndarray, Xg: np.ndarray, orbs) -> np.ndarray:
-    """Y = mask_P(H X) for the columns ``orbs`` of X (dense (N, len(orbs)))."""
-    Y = apply_hamiltonian(pat.mesh, v_qp, Xg)
+def masked_apply(pat: Pattern, v_qp: np.ndarray, Xg: np.ndarray, orbs, op: str = "H") -> np.ndarray:
+    """Y = mask_P(H X) (or mask_P(M X)) for the columns ``orbs`` of X (dense
+    (N, len(orbs))); ``pat`` is the destination pattern."""
+    Y = apply_hamiltonian(pat.mesh, v_qp, Xg, op=op)
     return np.where(block_mask(pat, orbs), Y, 0.0)
 
 
@@ -87,6 +99,11 @@ def overlap(X: sp.spmatrix, Y: sp.spmatrix) -> np.ndarray:
 
 def trace(S: np.ndarray) -> float:
     return float(np.trace(S))
+
+
+def energy(Mbar: np.ndarray, Hbar: np.ndarray) -> float:
+    """eq. energy: E = tr((2 I - Mbar) Hbar) with Mbar = X^T M X, Hbar = X^T H X."""
+    return float(np.trace((2.0 * np.eye(len(Mbar)) - Mbar) @ Hbar))
 
 
 def assemble(mesh: BoxMesh, v_qp: np.ndarray | None = None, which: str = "H") -> np.ndarray:

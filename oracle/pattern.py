@@ -177,6 +177,34 @@ def build_pattern(mesh: BoxMesh, centres, radius, colblock_sizes,
                    cb_start, orb_cb, rowptr, cc.astype(np.int64), block_offset, stored)
 
 
+def closure_pattern(pat: Pattern) -> Pattern:
+    """Destination pattern that holds H X and M X entirely.
+
+    Alg. 6 writes through the destination's accessor, and the text notes that
+    the operator's result has a larger support than its argument.  This
+    pattern is the support of that result: block (r, C) is stored iff some
+    non-Dirichlet node of row block r shares a cell with a non-Dirichlet node
+    whose block (r', C) is stored in ``pat``.  Rows, columns and column blocks
+    are those of ``pat``; the stored blocks of ``pat`` are a subset.
+    """
+    mesh = pat.mesh
+    dofs = mesh.cell_dofs()                          # (ncells, n^3)
+    free = ~mesh.dirichlet_mask()[dofs]              # (ncells, n^3)
+    rb = pat.node_rb[dofs]                           # row block of every cell node
+    stored = np.zeros_like(pat.stored)
+    for C in range(pat.ncb):
+        touches = (pat.stored[rb, C] & free).any(axis=1)   # cells with a stored free node
+        reached = rb[touches][free[touches]]
+        stored[np.unique(reached), C] = True
+    rowptr = np.concatenate([[0], np.cumsum(stored.sum(axis=1))]).astype(np.int64)
+    rr, cc = np.nonzero(stored)
+    rows_r = np.diff(pat.rb_start)
+    sizes = np.diff(pat.cb_start)
+    block_offset = np.concatenate([[0], np.cumsum(rows_r[rr] * sizes[cc])]).astype(np.int64)
+    return dataclasses.replace(pat, rowptr=rowptr, colidx=cc.astype(np.int64),
+                               block_offset=block_offset, stored=stored)
+
+
 def entry_coords(pat: Pattern):
     """For every stored value position: (global node id, original orbital id)."""
     nodes = np.empty(pat.nvalues, dtype=np.int64)

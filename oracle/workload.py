@@ -12,9 +12,9 @@ import scipy.sparse as sp
 
 import synth
 
-from .apply import block_mask, dense_columns, masked_apply, overlap, trace
+from .apply import block_mask, dense_columns, energy, masked_apply, overlap, trace
 from .mesh import BoxMesh
-from .pattern import build_pattern, entry_coords
+from .pattern import build_pattern, closure_pattern, entry_coords
 
 
 class OracleProblem:
@@ -49,19 +49,28 @@ class OracleProblem:
     def X_columns(self, orbs) -> np.ndarray:
         return dense_columns(self.mesh.ndofs, self.node, self.orb, self.val, orbs)
 
-    def Y_columns(self, orbs) -> np.ndarray:
-        return masked_apply(self.pattern, self.v_qp, self.X_columns(orbs), orbs)
+    def closure(self):
+        """Destination pattern that holds H X and M X entirely."""
+        if not hasattr(self, "_closure"):
+            self._closure = closure_pattern(self.pattern)
+        return self._closure
+
+    def Y_columns(self, orbs, op: str = "H", dest: str = "x") -> np.ndarray:
+        """H X (op "H") or M X (op "M") for the columns ``orbs``, kept on the
+        pattern of X (dest "x") or on its closure (dest "closure")."""
+        pat = self.pattern if dest == "x" else self.closure()
+        return masked_apply(pat, self.v_qp, self.X_columns(orbs), orbs, op=op)
 
     def Y_blocks(self, blocks):
         """{C: (orbs, dense Y (N, |C|))} for the listed column blocks."""
         return {C: (self.block_orbitals(C), self.Y_columns(self.block_orbitals(C))) for C in blocks}
 
-    def Y_all_sparse(self) -> sp.csc_matrix:
+    def Y_all_sparse(self, op: str = "H", dest: str = "x") -> sp.csc_matrix:
         """Y for every column as a sparse N x M matrix (original orbital order)."""
         rows, cols, vals = [], [], []
         for C in range(self.pattern.ncb):
             orbs = self.block_orbitals(C)
-            Y = self.Y_columns(orbs)
+            Y = self.Y_columns(orbs, op, dest)
             r, c = np.nonzero(Y)
             rows.append(r)
             cols.append(orbs[c])
@@ -76,3 +85,10 @@ class OracleProblem:
         Y = self.Y_all_sparse() if Y is None else Y
         S = overlap(self.X_sparse(), Y)
         return S, trace(S)
+
+    def projected(self):
+        """(Mbar, Hbar, E): X^T M X and X^T H X through the closure destination,
+        and the energy of eq. energy (original orbital order)."""
+        Hbar = overlap(self.X_sparse(), self.Y_all_sparse("H", "closure"))
+        Mbar = overlap(self.X_sparse(), self.Y_all_sparse("M", "closure"))
+        return Mbar, Hbar, energy(Mbar, Hbar)

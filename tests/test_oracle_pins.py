@@ -281,3 +281,100 @@ def test_row_block_spread_at_paper_density():
     sizes = np.diff(rb_start)
     assert abs(sizes.mean() - 66.1226) < 1e-3
     assert 8.0 < sizes.std() < 30.0
+
+
+# ---------------------------------------------------------------- closure and energy
+def _dense_free(m, which, v=None):
+    """Dense assembled matrix restricted to the non-Dirichlet nodes (zero rows
+    and columns on the Dirichlet faces)."""
+    A = oapply.assemble(m, v, which=which)
+    free = (~m.dirichlet_mask()).astype(float)
+    return A * free[:, None] * free[None, :]
+
+
+@pytest.mark.parametrize("p,cells,radius", [(2, (4, 4, 2), 1.6), (4, (6, 4, 2), 1.6)])
+def test_closure_holds_operator_results_brute_force(p, cells, radius):
+    """Dense H X and M X vanish outside the closure blocks, and the cell-wise
+    applies onto the closure equal them: X^T H X and X^T M X by brute force."""
+    from oracle.pattern import closure_pattern, entry_coords
+    m = BoxMesh(*cells, tuple(float(c) for c in cells), p, 0x3F)
+    rng = np.random.default_rng(3)
+    M = 6
+    centres = rng.uniform(0, 1, (M, 3)) * np.array(m.L)
+    pat = build_pattern(m, centres, radius, [2, 3, 1])
+    clo = closure_pattern(pat)
+    assert (clo.stored | ~pat.stored).all() and clo.nvalues > pat.nvalues
+    node, orb = entry_coords(pat)
+    keep = ~m.dirichlet_mask()[node]
+    X = np.zeros((m.ndofs, M))
+    X[node[keep], orb[keep]] = rng.standard_normal(keep.sum())
+    v = rng.uniform(-1, 1, (m.ncells, (p + 1) ** 3))
+    orbs = np.arange(M)
+    inside = oapply.block_mask(clo, orbs)
+    for which, op in (("H", "H"), ("M", "M")):
+        A = _dense_free(m, which, v if which == "H" else None)
+        Yd = A @ X
+        assert not np.any(Yd[~inside])
+        Yo = oapply.masked_apply(clo, v, X, orbs, op=op)
+        assert np.abs(Yo - Yd).max() <= 1e-13 * np.abs(Yd).max()
+        S = X.T @ Yo
+        assert np.abs(S - X.T @ A @ X).max() <= 1e-12 * np.abs(S).max()
+        assert np.abs(S - S.T).max() <= 1e-12 * np.abs(S).max()
+    # on the pattern of X itself some of H X is dropped (the reading of the text)
+    Yx = oapply.masked_apply(pat, v, X, orbs)
+    assert np.abs(X.T @ Yx - X.T @ _dense_free(m, "H", v) @ X).max() > 1e-6
+
+
+def _full_support_problem(p, cells, M):
+    m = BoxMesh(*cells, tuple(float(c) for c in cells), p, 0x3F)
+    centres = np.full((M, 3), 0.5) * np.array(m.L)
+    pat = build_pattern(m, centres, 1e3, [M // 2, M - M // 2])
+    assert pat.stored.all()
+    return m, pat
+
+
+@pytest.mark.parametrize("p", [2, 4])
+def test_energy_at_generalized_eigenvectors(p):
+    """Phi = the M lowest M-orthonormal eigenvectors of H u = lambda M u:
+    Mbar = I, Hbar = diag(lambda), E = tr((2I - Mbar) Hbar) = sum lambda."""
+    from oracle.pattern import closure_pattern
+    m, pat = _full_support_problem(p, (4, 2, 2), 4)
+    v = np.random.default_rng(1).uniform(0, 2, (m.ncells, (p + 1) ** 3))
+    free = ~m.dirichlet_mask()
+    H = oapply.assemble(m, v, which="H")[np.ix_(free, free)]
+    Mm = oapply.assemble(m, which="M")[np.ix_(free, free)]
+    lam, U = sla.eigh(H, Mm)
+    X = np.zeros((m.ndofs, 4))
+    X[free] = U[:, :4]
+    clo = closure_pattern(pat)
+    orbs = np.arange(4)
+    Hbar = X.T @ oapply.masked_apply(clo, v, X, orbs, op="H")
+    Mbar = X.T @ oapply.masked_apply(clo, v, X, orbs, op="M")
+    assert np.abs(Mbar - np.eye(4)).max() <= 1e-11
+    assert np.abs(Hbar - np.diag(lam[:4])).max() <= 1e-10 * lam[3]
+    assert abs(oapply.energy(Mbar, Hbar) - lam[:4].sum()) <= 1e-10 * lam[:4].sum()
+
+
+def test_energy_invariant_under_orthogonal_mixing():
+    """E(Phi Q) = E(Phi) for orthogonal Q (eq. energy is a trace of products
+    of projected matrices); a transposed or dropped factor breaks it."""
+    from oracle.pattern import closure_pattern
+    m, pat = _full_support_problem(2, (4, 4, 2), 6)
+    rng = np.random.default_rng(7)
+    v = rng.uniform(-1, 1, (m.ncells, 27))
+    free = ~m.dirichlet_mask()
+    X = np.zeros((m.ndofs, 6))
+    X[free] = 0.05 * rng.standard_normal((free.sum(), 6))
+    Q, _ = np.linalg.qr(rng.standard_normal((6, 6)))
+    clo = closure_pattern(pat)
+    orbs = np.arange(6)
+
+    def E(Xc):
+        Hbar = Xc.T @ oapply.masked_apply(clo, v, Xc, orbs, op="H")
+        Mbar = Xc.T @ oapply.masked_apply(clo, v, Xc, orbs, op="M")
+        return oapply.energy(Mbar, Hbar), Mbar, Hbar
+
+    e1, Mb, Hb = E(X)
+    e2, _, _ = E(X @ Q)
+    assert abs(e1 - e2) <= 1e-12 * abs(e1)
+    assert abs(e1 - (2 * np.trace(Hb) - np.sum(Mb * Hb.T))) <= 1e-12 * abs(e1)
