@@ -83,6 +83,12 @@ typedef enum {
   MFB_FP32 = 3        /* float32 on the vector ALUs (comparison form)          */
 } mfb_prec;
 
+/* Operator of mfb_apply_op (eq. fe_matrices). */
+typedef enum {
+  MFB_OP_H = 0,  /* Hamiltonian: 1/2 grad N_i . grad N_j + N_i V N_j        */
+  MFB_OP_M = 1   /* mass matrix: N_i N_j                                     */
+} mfb_op;
+
 /* ------------------------------------------------------------------ mesh */
 
 /* Box [0,Lx]x[0,Ly]x[0,Lz] split into nx x ny x nz equal Q_p cells.
@@ -255,7 +261,38 @@ typedef struct {
 int mfb_apply_H_tuned(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X, double* d_Y,
                       const mfb_tune* tune, void* d_work, void* stream);
 
-/* S = X^T Y (Alg. 8) and t = tr S, float64.  X and Y share the layout mv.
+/* Closure destination layout of x, so that the operator's full result can
+ * be kept (the result of Alg. 6 has a larger support than its argument):
+ * block (r, C) is stored iff a non-Dirichlet node of row block r shares a cell
+ * with a non-Dirichlet node whose block (r', C) is stored in x.  H X and M X
+ * are zero outside it, so X^T (H X) through mfb_tmmult on this layout is the
+ * projected Hamiltonian of eq. energy exactly (symmetric up to rounding).
+ * Same rows, columns and column blocks as x; x's stored blocks are a subset.
+ * The new layout refers to x: destroy it before x.  It is a destination only
+ * (mfb_apply_H, mfb_apply_H_tuned and mfb_mv_update reject it).  Bind it with
+ * mfb_mv_bind like any layout (info.meta_bytes); info.work_bytes is the
+ * workspace of mfb_tmmult on it.  Errors: EINVAL (closure of a closure),
+ * EUNSUPPORTED (2^31 or more stored values).                                */
+int mfb_create_closure(const mfb_mv* x, mfb_mv** out);
+
+/* Y = mask_y(op X) with op = H or M (MFB_OP_H / MFB_OP_M, eq. fe_matrices),
+ * the same cell loop as mfb_apply_H.  d_X: layout x (info.nvalues of x);
+ * d_Y: layout y, which is x itself (the result is kept on the pattern of X,
+ * as mfb_apply_H does) or the closure of x (nothing is dropped).  d_Y is
+ * overwritten and must not alias d_X.  prec as for mfb_apply_H; the mass
+ * form scales with JxW in float64.  Errors: EPATTERN (y is neither x nor its
+ * closure, or another mesh), ESTATE (not bound), EINVAL, EUNSUPPORTED, EHIP. */
+int mfb_apply_op(const mfb_mesh* mesh, const mfb_mv* x, const mfb_mv* y, int op,
+                 const double* d_X, double* d_Y, int prec, void* stream);
+
+/* Energy of eq. energy, E = tr((2 I - Mbar) Hbar), float64, summed in a
+ * fixed order (bitwise repeatable).  d_Mbar, d_Hbar: M x M row-major device
+ * arrays (X^T M X and X^T H X, e.g. from mfb_tmmult on a closure layout, in
+ * the same column order); d_E: one double.  Errors: EINVAL, EHIP.          */
+int mfb_energy(int32_t M, const double* d_Mbar, const double* d_Hbar, double* d_E, void* stream);
+
+/* S = X^T Y (Alg. 8) and t = tr S, float64.  X and Y share the layout mv, or
+ * mv is a closure layout: then X is in mv's source layout and Y in mv.
  * d_S: M*M doubles, fully written (entries outside the product pattern are
  * exactly 0); d_trace: one double; d_work: info.work_bytes of scratch for the
  * per-row-block partial products, which are summed in a fixed order (the

@@ -10,11 +10,15 @@ from .api import (  # noqa: F401
     FP32_MFMA,
     FP64,
     FP64_MFMA,
+    OP_H,
+    OP_M,
     PREC_NAMES,
     Layout,
     Mesh,
     apply_H,
     apply_H_tuned,
+    apply_op,
+    energy,
     mv_update,
     tmmult,
 )

@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(HERE, "libmfbcsr.so")
 MFB_OK, MFB_EINVAL, MFB_EUNSUPPORTED, MFB_EPATTERN, MFB_ENOMEM, MFB_EHIP, MFB_ESTATE = \
     0, -1, -2, -3, -4, -5, -6
 MFB_FP64, MFB_FP64_MFMA, MFB_FP32_MFMA, MFB_FP32 = 0, 1, 2, 3
+MFB_OP_H, MFB_OP_M = 0, 1
 STATUS_NAMES = {0: "MFB_OK", -1: "MFB_EINVAL", -2: "MFB_EUNSUPPORTED", -3: "MFB_EPATTERN",
                 -4: "MFB_ENOMEM", -5: "MFB_EHIP", -6: "MFB_ESTATE"}
 
@@ -89,6 +90,9 @@ SIGNATURES = {
     "mfb_apply_H_tuned": (C.c_int, [VP, VP, VP, VP, C.POINTER(Tune), VP, VP]),
     "mfb_tmmult": (C.c_int, [VP, VP, VP, VP, VP, VP, VP]),
     "mfb_mv_update": (C.c_int, [VP, VP, VP, VP, VP, C.c_double, VP]),
+    "mfb_create_closure": (C.c_int, [VP, C.POINTER(VP)]),
+    "mfb_apply_op": (C.c_int, [VP, VP, VP, C.c_int, VP, VP, C.c_int, VP]),
+    "mfb_energy": (C.c_int, [C.c_int32, VP, VP, VP, VP]),
 }
 
 

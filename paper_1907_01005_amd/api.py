@@ -15,6 +15,7 @@ from . import _native as N
 from ._native import check, lib
 
 FP64, FP64_MFMA, FP32_MFMA, FP32 = N.MFB_FP64, N.MFB_FP64_MFMA, N.MFB_FP32_MFMA, N.MFB_FP32
+OP_H, OP_M = N.MFB_OP_H, N.MFB_OP_M
 PREC_NAMES = {FP64: "fp64", FP64_MFMA: "fp64-mfma", FP32_MFMA: "fp32-mfma", FP32: "fp32"}
 
 
@@ -106,8 +107,12 @@ class Layout:
                      None if sizes is None else _ptr(sizes, C.c_int32), B, col_order)
         h = C.c_void_p()
         check(lib().mfb_create_bcsr_multivector(mesh.handle, C.byref(d), C.byref(h)))
-        self._h = h
+        self.source = None
         self._keep = (cen, rad, sizes)
+        self._finish(h)
+
+    def _finish(self, h) -> None:
+        self._h = h
         info = N.MvInfo()
         check(lib().mfb_mv_get_info(h, C.byref(info)))
         self.info = {k: getattr(info, k) for k, _ in N.MvInfo._fields_}
@@ -116,6 +121,18 @@ class Layout:
         self.meta_bytes = info.meta_bytes
         self.work_bytes = info.work_bytes
         self._meta = None
+
+    def closure(self) -> "Layout":
+        """mfb_create_closure: the destination layout that holds H X and M X
+        entirely.  It keeps this layout alive."""
+        h = C.c_void_p()
+        check(lib().mfb_create_closure(self._h, C.byref(h)))
+        out = Layout.__new__(Layout)
+        out.mesh = self.mesh
+        out.source = self
+        out._keep = None
+        out._finish(h)
+        return out
 
     @property
     def handle(self):
@@ -209,3 +226,15 @@ def mv_update(layout: Layout, X, Y, S, S2, tau: float, stream=None) -> None:
     """mfb_mv_update: X <- X - tau (Y - X diag(S)/diag(S2)) on the stored entries."""
     check(lib().mfb_mv_update(layout.handle, _dev_ptr(X), _dev_ptr(Y), _dev_ptr(S), _dev_ptr(S2),
                               float(tau), _stream(stream)))
+
+
+def apply_op(mesh: Mesh, x: Layout, y: Layout, op: int, X, Y, prec: int = FP64,
+             stream=None) -> None:
+    """mfb_apply_op: Y = mask_y(op X), op = OP_H or OP_M; y is x or x.closure()."""
+    check(lib().mfb_apply_op(mesh.handle, x.handle, y.handle, int(op), _dev_ptr(X), _dev_ptr(Y),
+                             int(prec), _stream(stream)))
+
+
+def energy(M: int, Mbar, Hbar, E, stream=None) -> None:
+    """mfb_energy: E = tr((2 I - Mbar) Hbar) into the one-element tensor E."""
+    check(lib().mfb_energy(int(M), _dev_ptr(Mbar), _dev_ptr(Hbar), _dev_ptr(E), _stream(stream)))

@@ -29,30 +29,32 @@ MeshLayout mesh_layout(const mfb::MeshPlan& m) {
   L.off_gtab = 0;
   L.off_cv = align256(sizeof(int32_t) * nb3 * m.nbatch);
   L.off_wg = align256(L.off_cv + sizeof(double) * (size_t)m.ncells * n3);
-  L.bytes = align256(L.off_wg + sizeof(double) * 3 * n3);
+  L.bytes = align256(L.off_wg + sizeof(double) * 4 * n3);
   return L;
 }
 
 // Per-direction quadrature scaling of the gradient term of eq. fe_matrices on
-// a box cell: 1/2 JxW_q / h_d^2 with JxW_q = w_q1 w_q2 w_q3 hx hy hz.
+// a box cell, 1/2 JxW_q / h_d^2 with JxW_q = w_q1 w_q2 w_q3 hx hy hz, for
+// d = 0, 1, 2; then JxW_q itself (the mass term).
 std::vector<double> grad_scales(const mfb::MeshPlan& m) {
   const int n = m.n, n3 = n * n * n;
   const double det = m.h[0] * m.h[1] * m.h[2];
-  std::vector<double> wg(3 * n3);
-  for (int d = 0; d < 3; ++d)
-    for (int k = 0; k < n; ++k)
-      for (int j = 0; j < n; ++j)
-        for (int i = 0; i < n; ++i) {
-          const double jxw = m.basis.wq[i] * m.basis.wq[j] * m.basis.wq[k] * det;
-          wg[d * n3 + i + n * (j + n * k)] = 0.5 * jxw / (m.h[d] * m.h[d]);
-        }
+  std::vector<double> wg(4 * n3);
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        const double jxw = m.basis.wq[i] * m.basis.wq[j] * m.basis.wq[k] * det;
+        for (int d = 0; d < 3; ++d) wg[d * n3 + i + n * (j + n * k)] = 0.5 * jxw / (m.h[d] * m.h[d]);
+        wg[3 * n3 + i + n * (j + n * k)] = jxw;
+      }
   return wg;
 }
 
 struct MvLayout {
   size_t off_items = 0, off_units = 0, off_pair_tab = 0, off_pair_ptr = 0, off_pair_list = 0,
          off_cb_of_col = 0, off_cb_start = 0, off_blk_off = 0, off_blk_col0 = 0, off_blk_w = 0,
-         off_rowoff = 0, off_shell_ptr = 0, off_shell_ro = 0, off_s2 = 0, bytes = 0;
+         off_rowoff = 0, off_shell_ptr = 0, off_shell_ro = 0, off_s2 = 0, off_dest_rowoff = 0,
+         bytes = 0;
 };
 
 MvLayout mv_layout(const mfb::MvPlan& v) {
@@ -86,6 +88,8 @@ MvLayout mv_layout(const mfb::MvPlan& v) {
   o = align256(o + sizeof(int32_t) * v.shell_ro.size());
   L.off_s2 = o;
   o = align256(o + sizeof(mfb::S2Desc) * v.s2.size());
+  L.off_dest_rowoff = o;
+  o = align256(o + sizeof(int32_t) * v.dest_rowoff.size());
 
   L.bytes = std::max<size_t>(o, 256);
   return L;
@@ -111,6 +115,7 @@ struct mfb_mesh {
 struct mfb_mv {
   mfb::MvPlan plan;
   const mfb_mesh* mesh = nullptr;
+  const mfb_mv* source = nullptr;  // closure layouts: the layout they are the closure of
   MvLayout lay;
   size_t work_bytes = 0;
   void* d_meta = nullptr;
@@ -280,7 +285,7 @@ int mfb_query_stats(const mfb_mv* mv, mfb_stats* out) {
   for (int r = 0; r < m.nbatch; ++r) rows[r] = (double)(m.rb_start[r + 1] - m.rb_start[r]);
   for (int C = 0; C < p.ncb; ++C) cols[C] = p.cb_start[C + 1] - p.cb_start[C];
   int64_t sum = 0;
-  for (int64_t c = 0; c < m.ncells; ++c) {
+  for (int64_t c = 0; c < m.ncells && !p.cell_colblocks.empty(); ++c) {
     cells[c] = p.cell_colblocks[c];
     sum += p.cell_colblocks[c];
   }
@@ -379,6 +384,7 @@ int mfb_mv_bind(mfb_mv* mv, void* d_meta, void* stream) {
   put(L.off_shell_ptr, p.shell_ptr.data(), sizeof(int32_t) * p.shell_ptr.size());
   put(L.off_shell_ro, p.shell_ro.data(), sizeof(int32_t) * p.shell_ro.size());
   put(L.off_s2, p.s2.data(), sizeof(mfb::S2Desc) * p.s2.size());
+  put(L.off_dest_rowoff, p.dest_rowoff.data(), sizeof(int32_t) * p.dest_rowoff.size());
 
   {
     std::vector<int32_t> col0(p.colidx.size()), wid(p.colidx.size());
@@ -420,6 +426,8 @@ static void fill_apply_params(const mfb_mesh* mesh, const mfb_mv* mv, const doub
   a.gtab = (const int32_t*)(gb + mesh->lay.off_gtab);
   a.cV = (const double*)(gb + mesh->lay.off_cv);
   a.Wg = (const double*)(gb + mesh->lay.off_wg);
+  a.jxw = a.Wg + 3 * m.n * m.n * m.n;
+  a.rowoff_out = a.rowoff;
   const int n = m.n;
   for (int i = 0; i < n * n; ++i) {
     a.S[i] = b.S[i];
@@ -432,6 +440,7 @@ static void fill_apply_params(const mfb_mesh* mesh, const mfb_mv* mv, const doub
 static void check_apply_args(const mfb_mesh* mesh, const mfb_mv* mv, const double* X, const double* Y) {
   if (!mesh || !mv || !X || !Y) fail(MFB_EINVAL, "null argument");
   if (mv->mesh != mesh) fail(MFB_EPATTERN, "layout was planned on another mesh");
+  if (mv->source) fail(MFB_EINVAL, "a closure layout is a destination only");
   if (!mesh->bound) fail(MFB_ESTATE, "mesh metadata not bound");
   if (!mv->bound) fail(MFB_ESTATE, "layout metadata not bound");
   if (X == Y) fail(MFB_EINVAL, "X and Y must not alias");
@@ -476,6 +485,57 @@ int mfb_apply_H_tuned(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X,
   MFB_CATCH
 }
 
+int mfb_create_closure(const mfb_mv* x, mfb_mv** out) {
+  MFB_TRY
+  if (!x || !out) fail(MFB_EINVAL, "null argument");
+  *out = nullptr;
+  if (x->source) fail(MFB_EINVAL, "the closure of a closure layout is not supported");
+  auto* v = new mfb_mv();
+  try {
+    mfb::plan_closure(v->plan, x->plan, x->mesh->plan);
+    v->mesh = x->mesh;
+    v->source = x;
+    v->lay = mv_layout(v->plan);
+    v->work_bytes = kCounterBytes + sizeof(double) * (size_t)v->plan.part_doubles;
+  } catch (...) {
+    delete v;
+    throw;
+  }
+  *out = v;
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_apply_op(const mfb_mesh* mesh, const mfb_mv* x, const mfb_mv* y, int op, const double* d_X,
+                 double* d_Y, int prec, void* stream) {
+  MFB_TRY
+  check_apply_args(mesh, x, d_X, d_Y);
+  if (!y) fail(MFB_EINVAL, "null argument");
+  if (y != x && y->source != x) fail(MFB_EPATTERN, "y must be x or the closure of x");
+  if (!y->bound) fail(MFB_ESTATE, "destination layout metadata not bound");
+  if (op != MFB_OP_H && op != MFB_OP_M) fail(MFB_EINVAL, "unknown operator");
+  if (prec < 0 || prec > 3) fail(MFB_EINVAL, "unknown precision");
+  mfb::gpu::ApplyParams a;
+  fill_apply_params(mesh, x, d_X, d_Y, a);
+  if (y != x) a.rowoff_out = (const int32_t*)((const char*)y->d_meta + y->lay.off_dest_rowoff);
+  const int rc = mfb::gpu::launch_apply_op(a, mesh->plan.p, prec, op, y->plan.block_offset.back(),
+                                           stream);
+  if (rc == -2) fail(MFB_EUNSUPPORTED, "precision not implemented in this build");
+  if (rc != 0) fail(MFB_EHIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)rc));
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_energy(int32_t M, const double* d_Mbar, const double* d_Hbar, double* d_E, void* stream) {
+  MFB_TRY
+  if (!d_Mbar || !d_Hbar || !d_E) fail(MFB_EINVAL, "null argument");
+  if (M <= 0) fail(MFB_EINVAL, "M must be positive");
+  const int rc = mfb::gpu::launch_energy(M, d_Mbar, d_Hbar, d_E, stream);
+  if (rc != 0) fail(MFB_EHIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)rc));
+  return MFB_OK;
+  MFB_CATCH
+}
+
 int mfb_tmmult(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d_S, double* d_trace,
                void* d_work, void* stream) {
   MFB_TRY
@@ -512,6 +572,7 @@ int mfb_mv_update(const mfb_mv* mv, double* d_X, const double* d_Y, const double
                   const double* d_S2, double tau, void* stream) {
   MFB_TRY
   if (!mv || !d_X || !d_Y || !d_S || !d_S2) fail(MFB_EINVAL, "null argument");
+  if (mv->source) fail(MFB_EINVAL, "the update works on X's own layout, not a closure");
   if (!mv->bound) fail(MFB_ESTATE, "layout metadata not bound");
   if (!std::isfinite(tau)) fail(MFB_EINVAL, "tau must be finite");
   const char* mb = (const char*)mv->d_meta;

@@ -321,6 +321,59 @@ __device__ __forceinline__ void plane_operator(const Ctr& ctr, R* __restrict__ T
   ctr.template c<0, true, 0>(B, out);
 }
 
+// Mass operator on planes (eq. fe_matrices, the N_i N_j term): interpolate
+// to the quadrature points, scale by JxW (float64), integrate back; the same
+// layouts and calling convention as plane_operator, two layout switches.
+template <typename R, int P, class Ctr, class Hook>
+__device__ __forceinline__ void plane_mass(const Ctr& ctr, R* __restrict__ Tc, int pl,
+                                           const double* __restrict__ jxw, bool act,
+                                           const R (&u)[P + 1][P + 1], R (&out)[P + 1][P + 1],
+                                           Hook after_first_barrier) {
+  using D = Dims<P>;
+  constexpr int n = D::n, n2 = D::n2;
+  R A[n][n], B[n][n];
+  ctr.template c<0, false, 0>(u, A);
+  ctr.template c<1, false, 0>(A, B);
+  if (act) {
+#pragma unroll
+    for (int j = 0; j < n; ++j)
+#pragma unroll
+      for (int i = 0; i < n; ++i) Tc[i + n * j + n2 * pl] = B[i][j];
+  }
+  __syncthreads();
+  after_first_barrier();
+  // layout B: plane y = pl; interpolate along z, scale, integrate back along z
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < n; ++k)
+#pragma unroll
+      for (int i = 0; i < n; ++i) A[i][k] = Tc[i + n * pl + n2 * k];
+  }
+  ctr.template c<1, false, 0>(A, B);
+#pragma unroll
+  for (int i = 0; i < n; ++i)
+#pragma unroll
+    for (int k = 0; k < n; ++k) B[i][k] = (R)((double)B[i][k] * jxw[i + n * pl + n2 * k]);
+  ctr.template c<1, true, 0>(B, A);
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < n; ++k)
+#pragma unroll
+      for (int i = 0; i < n; ++i) Tc[i + n * pl + n2 * k] = A[i][k];
+  }
+  __syncthreads();
+  // layout A: integrate back along y and x
+  if (act) {
+#pragma unroll
+    for (int j = 0; j < n; ++j)
+#pragma unroll
+      for (int i = 0; i < n; ++i) A[i][j] = Tc[i + n * j + n2 * pl];
+  }
+  ctr.template c<1, true, 0>(A, B);
+  ctr.template c<0, true, 0>(B, out);
+}
+
 // Sum the 8 cell results of a batch per batch node (T holds cell-column
 // tensors at T[(e*8 + col)*n^3 + local]) and add them into stored rows of Y.
 template <typename R, int P, int NT>
@@ -378,7 +431,7 @@ __device__ __forceinline__ Contractor<R, P, MF> make_ctr(const ApplyParams& a) {
   return c;
 }
 
-template <typename R, int P, bool MF = false>
+template <typename R, int P, bool MF = false, int OP = 0>
 struct BatchProc {
   using D = Dims<P>;
   static constexpr int NT = 64 * D::n, UPI = 1;
@@ -419,9 +472,11 @@ struct BatchProc {
       xv[k] = ro[k] >= 0 ? a.X[(int64_t)ro[k] + ((t + k * NT) & 7)] : 0.0;
   }
   // Everything after the gather: returns without work when all values are 0.
-  static __device__ __forceinline__ void compute(const ApplyParams& a, int rank, int t,
-                                                 const int32_t (&ro)[K], const double (&xv)[K],
-                                                 Smem& sm) {
+  // OP 0: Hamiltonian, 1: mass.  The sums go to the rows rowoff_out gives
+  // (the pattern of X, or its closure).
+  static __device__ __forceinline__ void compute(const ApplyParams& a, int64_t idx, int rank,
+                                                 int t, const int32_t (&ro)[K],
+                                                 const double (&xv)[K], Smem& sm) {
     constexpr int n = D::n, NB = D::NB;
     const int c = t & 7, e = (t >> 3) & 7;
     const int pl = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -449,27 +504,44 @@ struct BatchProc {
     R out[n][n];
     const double* cv = a.cV + ((int64_t)rank * 8 + e) * D::n3;
     const double* wg = a.Wg;
+    auto op = [&](auto hook) {
+      if constexpr (OP == 0)
+        plane_operator<R, P>(make_ctr<R, P, MF>(a), sm.b.T + (t & 63) * D::n3, pl, cv, wg, true,
+                             u, out, hook);
+      else
+        plane_mass<R, P>(make_ctr<R, P, MF>(a), sm.b.T + (t & 63) * D::n3, pl, a.jxw, true, u,
+                         out, hook);
+    };
     if constexpr (ALIAS) {
       __syncthreads();
-      plane_operator<R, P>(make_ctr<R, P, MF>(a), sm.b.T + (t & 63) * D::n3, pl, cv, wg, true, u,
-                           out, []() {});
+      op([]() {});
       __syncthreads();
       zero_sums();
       __syncthreads();
     } else {
       // every thread has read its plane by the first barrier: reuse G for the sums
-      plane_operator<R, P>(make_ctr<R, P, MF>(a), sm.b.T + (t & 63) * D::n3, pl, cv, wg, true, u,
-                           out, zero_sums);
+      op(zero_sums);
     }
 #pragma unroll
     for (int j = 0; j < n; ++j)
 #pragma unroll
       for (int i = 0; i < n; ++i) unsafeAtomicAdd(&G[base + (i + NB * j) * 8], (double)out[i][j]);
     __syncthreads();
+    if (a.rowoff_out == a.rowoff) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      if (ro[k] < 0) continue;
-      unsafeAtomicAdd(a.Y + (int64_t)ro[k] + ((t + k * NT) & 7), G[t + k * NT]);
+      for (int k = 0; k < K; ++k) {
+        if (ro[k] < 0) continue;
+        unsafeAtomicAdd(a.Y + (int64_t)ro[k] + ((t + k * NT) & 7), G[t + k * NT]);
+      }
+    } else {
+      const int32_t* __restrict__ r2 = a.rowoff_out + idx * D::NB3;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int e2 = t + k * NT;
+        if (e2 >= NV || (e2 & 7) >= a.items[idx].nc) continue;
+        const int32_t o = r2[e2 >> 3];
+        if (o >= 0) unsafeAtomicAdd(a.Y + (int64_t)o + (e2 & 7), G[e2]);
+      }
     }
   }
   static __device__ __forceinline__ void run(const ApplyParams& a, int64_t idx, int, Smem& sm) {
@@ -478,7 +550,7 @@ struct BatchProc {
     double xv[K];
     load(a, idx, t, ro);
     fetch(a, t, ro, xv);
-    compute(a, a.items[idx].rank, t, ro, xv, sm);
+    compute(a, idx, a.items[idx].rank, t, ro, xv, sm);
   }
 };
 
@@ -918,9 +990,9 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-template <typename R, int P, bool MF>
+template <typename R, int P, bool MF, int OP = 0>
 __global__ __launch_bounds__(64 * (P + 1)) void apply_fused_kernel(ApplyParams a, int spw) {
-  using Proc = BatchProc<R, P, MF>;
+  using Proc = BatchProc<R, P, MF, OP>;
   constexpr int NW = Proc::NT / 64;
   __shared__ typename Proc::Smem sm;
   __shared__ uint64_t s_hit[NW];
@@ -1024,7 +1096,7 @@ __global__ __launch_bounds__(64 * (P + 1)) void apply_pipe_kernel(ApplyParams a)
     for (int k = 0; k < K; ++k) xcur[k] = xv[k];
     if (j + 1 < total) Proc::fetch(a, t, ro_n, xv);
     if (j + 2 < total) Proc::load(a, item_of(j + 2), t, ro_nn);
-    Proc::compute(a, rank, t, ro_c, xcur, sm);
+    Proc::compute(a, cur, rank, t, ro_c, xcur, sm);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       ro_c[k] = ro_n[k];
@@ -1072,6 +1144,21 @@ hipError_t launch_pipe(const ApplyParams& p, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Own and shell items in one grid; spw = shell items checked per wave (a
+// power of two up to 64; 0 = 2).
+template <typename R, int P, bool MF, int OP>
+hipError_t launch_fused(const ApplyParams& p, int spw, hipStream_t st) {
+  using Proc = BatchProc<R, P, MF, OP>;
+  if (spw <= 0) spw = 2;
+  if (spw > 64 || (spw & (spw - 1)) != 0) return hipErrorInvalidValue;
+  const int64_t G = (Proc::NT / 64) * spw;
+  const int64_t po = (p.nitems + 7) >> 3, pg = ((p.nshell + G - 1) / G + 7) >> 3;
+  if (po + pg == 0) return hipSuccess;
+  hipLaunchKernelGGL((apply_fused_kernel<R, P, MF, OP>), dim3((unsigned)(8 * (po + pg))),
+                     dim3(Proc::NT), 0, st, p, spw);
+  return hipGetLastError();
+}
+
 template <typename R, int P, bool MF = false>
 hipError_t launch_apply_t(const ApplyParams& p, int kernel, hipStream_t st) {
   if (kernel == 6) return launch_pipe<R, P, MF>(p, st);
@@ -1081,19 +1168,7 @@ hipError_t launch_apply_t(const ApplyParams& p, int kernel, hipStream_t st) {
   // for p = 4)
   const int proc = kernel >> 1;
   const bool batch = proc <= 1;
-  if (batch && !queue) {
-    // own and shell items in one grid; p.grid = shell items checked per wave
-    // (a power of two up to 64; 0 = 2)
-    using Proc = BatchProc<R, P, MF>;
-    int spw = p.grid > 0 ? p.grid : 2;
-    if (spw > 64 || (spw & (spw - 1)) != 0) return hipErrorInvalidValue;
-    const int64_t G = (Proc::NT / 64) * spw;
-    const int64_t po = (p.nitems + 7) >> 3, pg = ((p.nshell + G - 1) / G + 7) >> 3;
-    if (po + pg == 0) return hipSuccess;
-    hipLaunchKernelGGL((apply_fused_kernel<R, P, MF>), dim3((unsigned)(8 * (po + pg))),
-                       dim3(Proc::NT), 0, st, p, spw);
-    return hipGetLastError();
-  }
+  if (batch && !queue) return launch_fused<R, P, MF, 0>(p, p.grid, st);
   hipError_t e;
   if (batch) {
     e = launch_proc<BatchProc<R, P, MF>>(p, queue, st);
@@ -1107,6 +1182,30 @@ hipError_t launch_apply_t(const ApplyParams& p, int kernel, hipStream_t st) {
   const int64_t nwg = ((p.nshell + 8 * spw - 1) / (8 * spw)) * 8;
   hipLaunchKernelGGL((apply_shell_kernel<R, P, MF>), dim3((unsigned)nwg), dim3(64), 0, st, p);
   return hipGetLastError();
+}
+
+// -------------------------------------------------------------- energy
+// E = tr((2 I - Mbar) Hbar) = 2 tr Hbar - sum_ab Mbar_ab Hbar_ba (eq. energy),
+// one workgroup, fixed-order strided sums and tree.
+__global__ __launch_bounds__(1024) void energy_kernel(int M, const double* __restrict__ Mb,
+                                                      const double* __restrict__ Hb,
+                                                      double* __restrict__ E) {
+  __shared__ double red[1024];
+  const int t = threadIdx.x;
+  double tr = 0.0, mh = 0.0;
+  for (int a = t; a < M; a += 1024) tr += Hb[(int64_t)a * M + a];
+  const int64_t MM = (int64_t)M * M;
+  for (int64_t q = t; q < MM; q += 1024) {
+    const int64_t a = q / M, b = q - a * M;
+    mh = __builtin_fma(Mb[q], Hb[b * M + a], mh);
+  }
+  red[t] = 2.0 * tr - mh;
+  __syncthreads();
+  for (int h = 512; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
+  }
+  if (t == 0) *E = red[0];
 }
 
 // -------------------------------------------------------------- update
@@ -1161,6 +1260,37 @@ int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t
     return -2;
   }
   return (int)e;
+}
+
+int launch_apply_op(const ApplyParams& p, int degree, int prec, int op, int64_t nvalues,
+                    void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  {
+    const int64_t blocks = std::min<int64_t>(4096, std::max<int64_t>(1, (nvalues / 2 + 255) / 256));
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p.Y, nvalues,
+                       nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return (int)e;
+  }
+  hipError_t e;
+  const bool q2 = degree == 2;
+  if (prec == 0)
+    e = op == 0 ? (q2 ? launch_fused<double, 2, false, 0>(p, 0, st) : launch_fused<double, 4, false, 0>(p, 0, st))
+                : (q2 ? launch_fused<double, 2, false, 1>(p, 0, st) : launch_fused<double, 4, false, 1>(p, 0, st));
+  else if (prec == 2)
+    e = op == 0 ? (q2 ? launch_fused<float, 2, true, 0>(p, 0, st) : launch_fused<float, 4, true, 0>(p, 0, st))
+                : (q2 ? launch_fused<float, 2, true, 1>(p, 0, st) : launch_fused<float, 4, true, 1>(p, 0, st));
+  else if (prec == 3)
+    e = op == 0 ? (q2 ? launch_fused<float, 2, false, 0>(p, 0, st) : launch_fused<float, 4, false, 0>(p, 0, st))
+                : (q2 ? launch_fused<float, 2, false, 1>(p, 0, st) : launch_fused<float, 4, false, 1>(p, 0, st));
+  else
+    return -2;
+  return (int)e;
+}
+
+int launch_energy(int M, const double* Mbar, const double* Hbar, double* E, void* stream) {
+  hipLaunchKernelGGL(energy_kernel, dim3(1), dim3(1024), 0, (hipStream_t)stream, M, Mbar, Hbar, E);
+  return (int)hipGetLastError();
 }
 
 int launch_tmmult(const TmParams& p, void* stream) {

@@ -30,6 +30,8 @@ struct ApplyParams {
   float Sf[25];          // float copies of S and Dco for the float contractions
   float Df[25];
   const double* Wg;      // [3][ (p+1)^3 ]: 1/2 JxW_q / h_d^2 per direction d
+  const double* jxw;     // [ (p+1)^3 ]: JxW_q (mass operator)
+  const int32_t* rowoff_out;  // destination offsets per item and node (rowoff, or a closure's)
 };
 
 struct TmParams {
@@ -57,6 +59,10 @@ struct TmParams {
 int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t nvalues,
                  void* stream);
 int launch_tmmult(const TmParams& p, void* stream);
+// op: 0 Hamiltonian, 1 mass; default kernel; destination nvalues for the fill.
+int launch_apply_op(const ApplyParams& p, int degree, int prec, int op, int64_t nvalues,
+                    void* stream);
+int launch_energy(int M, const double* Mbar, const double* Hbar, double* E, void* stream);
 
 // X <- X - tau (Y - X d), d_c = S[c][c] / S2[c][c], one workgroup per stored block.
 struct UpdateParams {

@@ -310,6 +310,90 @@ int64_t MvPlan::block_index(int r, int C) const {
   return -1;
 }
 
+// Overlap products of Alg. 8 for S = A^T B (A and B have the same rows and
+// columns): every pair of a stored block of A and a stored block of B in the
+// same row block.  Partial products are stored pair by pair (row-block order
+// within a pair), so that the second stage streams one contiguous run per
+// block of S.  The plan goes into `mv`.
+void plan_overlap(MvPlan& mv, const MvPlan& A, const MvPlan& B, const MeshPlan& m) {
+  const int nbt = m.nbatch, ncb = A.ncb;
+  std::vector<int32_t> w(ncb);
+  for (int C = 0; C < ncb; ++C) w[C] = A.cb_start[C + 1] - A.cb_start[C];
+  mv.units.clear();
+  mv.pair_tab.assign((size_t)ncb * ncb, -1);
+  std::vector<int64_t> pair_count;
+  for (int r = 0; r < nbt; ++r)
+    for (int64_t k1 = A.rowptr[r]; k1 < A.rowptr[r + 1]; ++k1)
+      for (int64_t k2 = B.rowptr[r]; k2 < B.rowptr[r + 1]; ++k2) {
+        int32_t& pid = mv.pair_tab[(size_t)A.colidx[k1] * ncb + B.colidx[k2]];
+        if (pid < 0) {
+          pid = (int32_t)pair_count.size();
+          pair_count.push_back(0);
+        }
+        ++pair_count[pid];
+      }
+  const int npairs = (int)pair_count.size();
+  std::vector<int32_t> pair_c1(npairs), pair_c2(npairs);
+  for (int C1 = 0; C1 < ncb; ++C1)
+    for (int C2 = 0; C2 < ncb; ++C2) {
+      const int32_t pid = mv.pair_tab[(size_t)C1 * ncb + C2];
+      if (pid >= 0) { pair_c1[pid] = C1; pair_c2[pid] = C2; }
+    }
+  // pair_ptr: first unit slot of each pair; pair_list[pid] = partial base
+  mv.pair_ptr.assign(npairs + 1, 0);
+  mv.pair_list.assign(npairs, 0);
+  int64_t part = 0;
+  for (int pid = 0; pid < npairs; ++pid) {
+    mv.pair_ptr[pid + 1] = mv.pair_ptr[pid] + (int32_t)pair_count[pid];
+    mv.pair_list[pid] = part;
+    part += pair_count[pid] * (int64_t)w[pair_c1[pid]] * w[pair_c2[pid]];
+  }
+  mv.part_doubles = part;
+  std::vector<int64_t> fill(npairs, 0);
+  for (int r = 0; r < nbt; ++r) {
+    const int64_t rows = m.rb_start[r + 1] - m.rb_start[r];
+    for (int64_t k1 = A.rowptr[r]; k1 < A.rowptr[r + 1]; ++k1)
+      for (int64_t k2 = B.rowptr[r]; k2 < B.rowptr[r + 1]; ++k2) {
+        const int C1 = A.colidx[k1], C2 = B.colidx[k2];
+        const int32_t pid = mv.pair_tab[(size_t)C1 * ncb + C2];
+        const int64_t E = (int64_t)w[C1] * w[C2];
+        TmUnit u;
+        u.off1 = A.block_offset[k1];
+        u.off2 = B.block_offset[k2];
+        u.part = mv.pair_list[pid] + fill[pid]++ * E;
+        u.rows = (int32_t)rows;
+        u.w1 = w[C1];
+        u.w2 = w[C2];
+        u.pad = 0;
+        mv.units.push_back(u);
+      }
+  }
+  mv.s2.assign((size_t)ncb * ncb, S2Desc{0, 0, 0, 0, 0, 0, 0});
+  for (int C1 = 0; C1 < ncb; ++C1)
+    for (int C2 = 0; C2 < ncb; ++C2) {
+      S2Desc& d = mv.s2[(size_t)C1 * ncb + C2];
+      const int32_t pid = mv.pair_tab[(size_t)C1 * ncb + C2];
+      d.base = pid >= 0 ? mv.pair_list[pid] : 0;
+      d.n = pid >= 0 ? mv.pair_ptr[pid + 1] - mv.pair_ptr[pid] : 0;
+      d.c1 = A.cb_start[C1];
+      d.c2 = A.cb_start[C2];
+      d.w1 = w[C1];
+      d.w2 = w[C2];
+    }
+  // one overlap kernel per class, each with its own thread count and
+  // register budget
+  auto tm_class = [](const TmUnit& u) {
+    const bool shortb = u.rows <= 128;
+    if (u.w1 == 8 && u.w2 == 8 && (shortb || ((u.off1 | u.off2) & 1) == 0)) return shortb ? 0 : 1;
+    return shortb ? 2 : 3;
+  };
+  std::stable_sort(mv.units.begin(), mv.units.end(),
+                   [&](const TmUnit& x, const TmUnit& y) { return tm_class(x) < tm_class(y); });
+  mv.tm_class_end.fill(0);
+  for (const TmUnit& u : mv.units)
+    for (int c = tm_class(u); c < 4; ++c) ++mv.tm_class_end[c];
+}
+
 void plan_mv(MvPlan& mv, const MeshPlan& m, int M, const double* centers, const double* radius,
              int radius_count, int ncolblocks, const int32_t* sizes, int B, int col_order) {
   if (M <= 0) throw Error(-1, "M must be positive");
@@ -423,7 +507,9 @@ void plan_mv(MvPlan& mv, const MeshPlan& m, int M, const double* centers, const 
   // non-Dirichlet node of the batch; one item per 8-column chunk of C.
   const int NB = m.NB, NB3 = NB * NB * NB, n = m.n;
   mv.items.clear();
+  mv.item_cb.clear();
   std::vector<ApplyItem> shell;  // batches whose own block is not stored for C
+  std::vector<int32_t> shell_cb;
   mv.apply_pairs = mv.apply_pairs_own = 0;
   mv.cell_colblocks.assign(m.ncells, 0);
   std::vector<int> mark(ncb, 0), list;
@@ -467,6 +553,7 @@ void plan_mv(MvPlan& mv, const MeshPlan& m, int M, const double* centers, const 
         it.c0 = c0;
         it.nc = std::min(8, w[C] - c0);
         (own ? mv.items : shell).push_back(it);
+        (own ? mv.item_cb : shell_cb).push_back(C);
       }
     }
     // non-empty column blocks per cell (Table 1, last row)
@@ -493,6 +580,7 @@ void plan_mv(MvPlan& mv, const MeshPlan& m, int M, const double* centers, const 
   // own items first, then the shell items (processed by a separate kernel)
   mv.n_own_items = (int64_t)mv.items.size();
   mv.items.insert(mv.items.end(), shell.begin(), shell.end());
+  mv.item_cb.insert(mv.item_cb.end(), shell_cb.begin(), shell_cb.end());
 
   // per item, the value offset of every batch node's row in its block of C,
   // at the item's first column (-1 when the node is on a Dirichlet face or
@@ -521,82 +609,100 @@ void plan_mv(MvPlan& mv, const MeshPlan& m, int M, const double* centers, const 
     mv.shell_ptr.push_back((int32_t)mv.shell_ro.size());
   }
 
-  // overlap products (Alg. 8): every pair of stored blocks of a row block.
-  // Partial products are stored pair by pair (row-block order within a
-  // pair), so that the second stage streams one contiguous run per block of S.
-  mv.units.clear();
-  mv.pair_tab.assign((size_t)ncb * ncb, -1);
-  std::vector<int64_t> pair_count;
-  for (int r = 0; r < nbt; ++r)
-    for (int64_t k1 = mv.rowptr[r]; k1 < mv.rowptr[r + 1]; ++k1)
-      for (int64_t k2 = mv.rowptr[r]; k2 < mv.rowptr[r + 1]; ++k2) {
-        int32_t& pid = mv.pair_tab[(size_t)mv.colidx[k1] * ncb + mv.colidx[k2]];
-        if (pid < 0) {
-          pid = (int32_t)pair_count.size();
-          pair_count.push_back(0);
-        }
-        ++pair_count[pid];
+  plan_overlap(mv, mv, mv, m);
+}
+
+void plan_closure(MvPlan& y, const MvPlan& x, const MeshPlan& m) {
+  if (x.source) throw Error(-1, "the closure of a closure layout is not supported");
+  y = MvPlan();
+  y.mesh = &m;
+  y.source = &x;
+  y.M = x.M;
+  y.ncb = x.ncb;
+  y.col_perm = x.col_perm;
+  y.col_pos = x.col_pos;
+  y.cb_start = x.cb_start;
+  y.cb_of_col = x.cb_of_col;
+  const int nbt = m.nbatch, ncb = x.ncb, NB = m.NB, NB3 = NB * NB * NB, n = m.n;
+  std::vector<int32_t> w(ncb);
+  for (int C = 0; C < ncb; ++C) w[C] = x.cb_start[C + 1] - x.cb_start[C];
+
+  // owner rank of each neighbour slot of every batch
+  std::vector<std::array<int, 27>> owners(nbt);
+  for (int r = 0; r < nbt; ++r) {
+    owners[r].fill(-1);
+    const int32_t* g = m.gtab.data() + (size_t)r * NB3;
+    int bx, by, bz;
+    m.batch_coords(m.batch_order[r], bx, by, bz);
+    for (int v = 0; v < NB3; ++v)
+      if (g[v] >= 0) {
+        const int s = g[v] >> 24;
+        const int ox = bx + (s % 3) - 1, oy = by + ((s / 3) % 3) - 1, oz = bz + (s / 9) - 1;
+        owners[r][s] = m.batch_rank[ox + m.nb[0] * (oy + m.nb[1] * oz)];
       }
-  const int npairs = (int)pair_count.size();
-  std::vector<int32_t> pair_c1(npairs), pair_c2(npairs);
-  for (int C1 = 0; C1 < ncb; ++C1)
-    for (int C2 = 0; C2 < ncb; ++C2) {
-      const int32_t pid = mv.pair_tab[(size_t)C1 * ncb + C2];
-      if (pid >= 0) { pair_c1[pid] = C1; pair_c2[pid] = C2; }
-    }
-  // pair_ptr: first unit slot of each pair; pair_list[pid] = partial base
-  mv.pair_ptr.assign(npairs + 1, 0);
-  mv.pair_list.assign(npairs, 0);
-  int64_t part = 0;
-  for (int pid = 0; pid < npairs; ++pid) {
-    mv.pair_ptr[pid + 1] = mv.pair_ptr[pid] + (int32_t)pair_count[pid];
-    mv.pair_list[pid] = part;
-    part += pair_count[pid] * (int64_t)w[pair_c1[pid]] * w[pair_c2[pid]];
   }
-  mv.part_doubles = part;
-  std::vector<int64_t> fill(npairs, 0);
+  // cell by cell: the column blocks stored for any free node of the cell
+  // reach the row blocks of all free nodes of the cell
+  std::vector<uint8_t> stored((size_t)nbt * ncb, 0);
+  std::vector<int> mark(ncb, 0), list;
+  for (int r = 0; r < nbt; ++r) {
+    const int32_t* g = m.gtab.data() + (size_t)r * NB3;
+    for (int e = 0; e < 8; ++e) {
+      const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
+      uint32_t slots = 0;
+      for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+          for (int i = 0; i < n; ++i) {
+            const int v = (ex * m.p + i) + NB * ((ey * m.p + j) + NB * (ez * m.p + k));
+            if (g[v] >= 0) slots |= 1u << (g[v] >> 24);
+          }
+      list.clear();
+      for (int s = 0; s < 27; ++s) {
+        if (!((slots >> s) & 1u)) continue;
+        const int o = owners[r][s];
+        for (int64_t kb = x.rowptr[o]; kb < x.rowptr[o + 1]; ++kb) {
+          const int C = x.colidx[kb];
+          if (!mark[C]) { mark[C] = 1; list.push_back(C); }
+        }
+      }
+      for (int C : list) {
+        mark[C] = 0;
+        for (int s = 0; s < 27; ++s)
+          if ((slots >> s) & 1u) stored[(size_t)owners[r][s] * ncb + C] = 1;
+      }
+    }
+  }
+  y.rowptr.assign(nbt + 1, 0);
+  for (int r = 0; r < nbt; ++r) {
+    for (int C = 0; C < ncb; ++C)
+      if (stored[(size_t)r * ncb + C]) y.colidx.push_back(C);
+    y.rowptr[r + 1] = (int64_t)y.colidx.size();
+  }
+  const int64_t nblocks = (int64_t)y.colidx.size();
+  y.block_offset.assign(nblocks + 1, 0);
   for (int r = 0; r < nbt; ++r) {
     const int64_t rows = m.rb_start[r + 1] - m.rb_start[r];
-    for (int64_t k1 = mv.rowptr[r]; k1 < mv.rowptr[r + 1]; ++k1)
-      for (int64_t k2 = mv.rowptr[r]; k2 < mv.rowptr[r + 1]; ++k2) {
-        const int C1 = mv.colidx[k1], C2 = mv.colidx[k2];
-        const int32_t pid = mv.pair_tab[(size_t)C1 * ncb + C2];
-        const int64_t E = (int64_t)w[C1] * w[C2];
-        TmUnit u;
-        u.off1 = mv.block_offset[k1];
-        u.off2 = mv.block_offset[k2];
-        u.part = mv.pair_list[pid] + fill[pid]++ * E;
-        u.rows = (int32_t)rows;
-        u.w1 = w[C1];
-        u.w2 = w[C2];
-        u.pad = 0;
-        mv.units.push_back(u);
-      }
+    for (int64_t k = y.rowptr[r]; k < y.rowptr[r + 1]; ++k)
+      y.block_offset[k + 1] = y.block_offset[k] + rows * w[y.colidx[k]];
   }
-  mv.s2.assign((size_t)ncb * ncb, S2Desc{0, 0, 0, 0, 0, 0, 0});
-  for (int C1 = 0; C1 < ncb; ++C1)
-    for (int C2 = 0; C2 < ncb; ++C2) {
-      S2Desc& d = mv.s2[(size_t)C1 * ncb + C2];
-      const int32_t pid = mv.pair_tab[(size_t)C1 * ncb + C2];
-      d.base = pid >= 0 ? mv.pair_list[pid] : 0;
-      d.n = pid >= 0 ? mv.pair_ptr[pid + 1] - mv.pair_ptr[pid] : 0;
-      d.c1 = mv.cb_start[C1];
-      d.c2 = mv.cb_start[C2];
-      d.w1 = w[C1];
-      d.w2 = w[C2];
+  if (y.block_offset.back() >= ((int64_t)1 << 31))
+    throw Error(-2, "multivectors of 2^31 or more stored values are not supported");
+
+  // destination row offsets of x's apply items
+  y.dest_rowoff.assign(x.items.size() * (size_t)NB3, -1);
+  for (size_t q = 0; q < x.items.size(); ++q) {
+    const ApplyItem& it = x.items[q];
+    const int32_t* g = m.gtab.data() + (size_t)it.rank * NB3;
+    const int CC = x.item_cb[q];
+    int32_t* ro = y.dest_rowoff.data() + q * NB3;
+    for (int v = 0; v < NB3; ++v) {
+      if (g[v] < 0) continue;
+      const int64_t k = y.block_index(owners[it.rank][g[v] >> 24], CC);
+      if (k < 0) continue;
+      ro[v] = (int32_t)(y.block_offset[k] + (int64_t)(g[v] & 0xFFFFFF) * it.ld + it.c0);
     }
-  // one overlap kernel per class, each with its own thread count and
-  // register budget
-  auto tm_class = [](const TmUnit& u) {
-    const bool shortb = u.rows <= 128;
-    if (u.w1 == 8 && u.w2 == 8 && (shortb || ((u.off1 | u.off2) & 1) == 0)) return shortb ? 0 : 1;
-    return shortb ? 2 : 3;
-  };
-  std::stable_sort(mv.units.begin(), mv.units.end(),
-                   [&](const TmUnit& x, const TmUnit& y) { return tm_class(x) < tm_class(y); });
-  mv.tm_class_end.fill(0);
-  for (const TmUnit& u : mv.units)
-    for (int c = tm_class(u); c < 4; ++c) ++mv.tm_class_end[c];
+  }
+  plan_overlap(y, x, y, m);
 }
 
 }  // namespace mfb

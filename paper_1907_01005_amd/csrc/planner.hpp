@@ -113,6 +113,7 @@ struct MvPlan {
   std::vector<int32_t> colidx;
   std::vector<int64_t> block_offset; // nblocks + 1
   std::vector<ApplyItem> items;      // own items (batch's own block stored) then shell items
+  std::vector<int32_t> item_cb;      // column block of each item (host only)
   int64_t n_own_items = 0;
   std::vector<int32_t> rowoff;       // [item][(2p+1)^3] value offset of each node's row at the item's first column, or -1
   std::vector<int32_t> shell_ptr;    // [nshell+1] CSR over the shell items' present rows
@@ -127,6 +128,11 @@ struct MvPlan {
   std::vector<int32_t> pair_tab;     // ncb*ncb -> pair id or -1
   std::vector<int32_t> pair_ptr;     // npairs + 1: prefix count of partial products per pair
   std::vector<int64_t> pair_list;    // npairs: offset of the pair's contiguous partials
+  // closure layouts only: the layout whose operator results this one holds,
+  // and for every apply item of that layout the offset of each batch node's
+  // row here (at the item's first column), or -1
+  const MvPlan* source = nullptr;
+  std::vector<int32_t> dest_rowoff;
   // cell statistics
   std::vector<int32_t> cell_colblocks; // per library cell: non-empty column blocks
   int64_t block_index(int r, int C) const;  // -1 if (r, C) not stored
@@ -134,5 +140,16 @@ struct MvPlan {
 
 void plan_mv(MvPlan& mv, const MeshPlan& m, int M, const double* centers, const double* radius,
              int radius_count, int ncolblocks, const int32_t* sizes, int B, int col_order);
+
+// Overlap plan (units, pairs, S-block descriptors) of S = A^T B into mv.
+void plan_overlap(MvPlan& mv, const MvPlan& A, const MvPlan& B, const MeshPlan& m);
+
+// Closure destination of x: block (r, C) is stored iff a non-Dirichlet node of
+// row block r shares a cell with a non-Dirichlet node whose block (r', C) is
+// stored in x, so H X and M X lie in it entirely.  Same rows and columns as
+// x; x's stored blocks are a subset.  Also plans the destination row offsets
+// of x's apply items and the overlap X^T Y (X in x, Y here).  No apply items
+// of its own: a closure layout is a destination only.
+void plan_closure(MvPlan& y, const MvPlan& x, const MeshPlan& m);
 
 }  // namespace mfb

@@ -11,7 +11,8 @@ from typing import Callable, Optional, Sequence
 
 import numpy as np
 
-from .api import FP64, Layout, Mesh, apply_H, apply_H_tuned, mv_update, tmmult
+from .api import (FP64, OP_H, OP_M, Layout, Mesh, apply_H, apply_H_tuned, apply_op, energy,
+                  mv_update, tmmult)
 
 
 class DeviceProblem:
@@ -62,6 +63,41 @@ class DeviceProblem:
 
     def update(self, S, S2, tau: float, stream=None) -> None:
         mv_update(self.layout, self.X, self.Y, S, S2, tau, stream)
+
+    def enable_closure(self) -> None:
+        """Closure layout and its buffers: H X and M X kept entirely, the
+        projected matrices Hbar = X^T H X, Mbar = X^T M X and the energy."""
+        import torch
+        if getattr(self, "closure", None) is not None:
+            return
+        self.closure = self.layout.closure()
+        self.closure.bind(self.device)
+        self.YH = self.closure.new_values(self.device)
+        self.YM = self.closure.new_values(self.device)
+        self.work_c = self.closure.new_work(self.device)
+        self.Hbar = torch.zeros((self.M, self.M), dtype=torch.float64, device=self.device)
+        self.Mbar = torch.zeros_like(self.Hbar)
+        self.tr_c = torch.zeros(2, dtype=torch.float64, device=self.device)
+        self.E = torch.zeros(1, dtype=torch.float64, device=self.device)
+
+    def energy(self, prec: int = FP64, stream=None) -> None:
+        """E(X) of eq. energy: H X and M X onto the closure, the two
+        projected matrices, then E = tr((2 I - Mbar) Hbar); all on the GPU."""
+        self.enable_closure()
+        c = self.closure
+        apply_op(self.mesh, self.layout, c, OP_H, self.X, self.YH, prec, stream)
+        apply_op(self.mesh, self.layout, c, OP_M, self.X, self.YM, prec, stream)
+        tmmult(c, self.X, self.YH, self.Hbar, self.tr_c[0:1], self.work_c, stream)
+        tmmult(c, self.X, self.YM, self.Mbar, self.tr_c[1:2], self.work_c, stream)
+        energy(self.M, self.Mbar, self.Hbar, self.E, stream)
+
+    def original_order(self, S) -> np.ndarray:
+        """An M x M device matrix in library column order, permuted back."""
+        S = S.cpu().numpy()
+        perm = self.layout.pattern()["col_perm"]
+        out = np.empty_like(S)
+        out[np.ix_(perm, perm)] = S
+        return out
 
     def S_original_order(self) -> np.ndarray:
         """S permuted back to original orbital ids."""

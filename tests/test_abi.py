@@ -96,3 +96,27 @@ def test_compute_calls_reject_unbound_handles():
     assert rc == N.MFB_ESTATE                         # no potential yet
     rc = lib().mfb_mv_bind(lay.handle, C.c_void_p(4097), None)
     assert rc == N.MFB_EINVAL                         # misaligned
+
+
+def test_closure_and_operator_argument_checks():
+    """Closure layouts are destinations only; mfb_apply_op checks the pairing
+    of source and destination; mfb_energy checks its size (no GPU call)."""
+    m = Mesh(4, 4, 4, (4, 4, 4), 2)
+    lay = Layout(m, np.full((8, 3), 1.0), 0.5)       # only the corner batch is stored
+    clo = lay.closure()
+    assert clo.nvalues > lay.nvalues and clo.info["apply_items"] == 0
+    h = C.c_void_p()
+    assert lib().mfb_create_closure(clo.handle, C.byref(h)) == N.MFB_EINVAL   # closure of a closure
+    assert lib().mfb_create_closure(None, C.byref(h)) == N.MFB_EINVAL
+    fake, fake2 = C.c_void_p(4096), C.c_void_p(8192)
+    # a closure is never a source
+    assert lib().mfb_apply_H(m.handle, clo.handle, fake, fake2, 0, None) == N.MFB_EINVAL
+    assert lib().mfb_apply_op(m.handle, clo.handle, clo.handle, 0, fake, fake2, 0, None) == N.MFB_EINVAL
+    assert lib().mfb_mv_update(clo.handle, fake, fake2, fake, fake, 0.1, None) == N.MFB_EINVAL
+    # unbound handles, then a destination that is neither x nor its closure
+    assert lib().mfb_apply_op(m.handle, lay.handle, clo.handle, 0, fake, fake2, 0, None) == N.MFB_ESTATE
+    other = Layout(m, np.full((8, 3), 1.0), 0.5)
+    rc = lib().mfb_apply_op(m.handle, lay.handle, other.handle, 0, fake, fake2, 0, None)
+    assert rc in (N.MFB_ESTATE, N.MFB_EPATTERN)
+    assert lib().mfb_energy(0, fake, fake, fake, None) == N.MFB_EINVAL
+    assert lib().mfb_energy(4, None, fake, fake, None) == N.MFB_EINVAL

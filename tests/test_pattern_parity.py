@@ -95,3 +95,29 @@ def test_table1_statistics_plausible():
         st = lay.stats()
         assert abs(st["rows_mean"] - rows_mean) < 1e-3
         assert 0.5 * colsum < st["colblocks_per_cell_sum"] < 2.0 * colsum
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_closure_patterns_bit_exact(cfg):
+    """mfb_create_closure against the oracle's closure pattern."""
+    from oracle.pattern import closure_pattern
+    wl = synth.make_workload(cfg)
+    _, lay, op = _both(wl)
+    _assert_same(lay.closure(), closure_pattern(op))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_closure_random_small_meshes(seed):
+    from oracle.pattern import closure_pattern
+    rng = np.random.default_rng(100 + seed)
+    cells = tuple(int(2 * rng.integers(1, 5)) for _ in range(3))
+    degree = int(rng.choice([2, 4]))
+    L = tuple(float(c) * float(rng.uniform(0.5, 1.5)) for c in cells)
+    ms = synth.MeshSpec(*cells, L, degree, int(rng.integers(0, 64)))
+    M = int(rng.integers(1, 30))
+    wl = synth.custom_workload(ms, M, float(rng.uniform(0.5, 3.0)), seed, B=int(rng.integers(1, 9)),
+                               uneven=bool(rng.integers(0, 2)))
+    _, lay, op = _both(wl, order=int(rng.integers(0, 2)))
+    clo = lay.closure()
+    _assert_same(clo, closure_pattern(op))
+    assert clo.info["apply_items"] == 0 and clo.nvalues >= lay.nvalues
