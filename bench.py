@@ -138,6 +138,30 @@ def graph_form(dp, prec: int, n: int = 20, reps: int = 5):
             "gdofcols_s": dp.nvalues / it / 1e9, "iterations_per_graph": n}
 
 
+def energy_form(dp, reps: int = 20):
+    """One evaluation of eq. energy: H X and M X onto the closure of X's
+    pattern, Hbar = X^T H X and Mbar = X^T M X, E = tr((2 I - Mbar) Hbar)."""
+    import torch
+    out = {}
+    for name, prec in (("fp64", PRECS["fp64"]), ("fp32-mfma", PRECS["fp32-mfma"])):
+        for _ in range(3):
+            dp.energy(prec)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(reps)]
+        for a, b in evs:
+            a.record()
+            dp.energy(prec)
+            b.record()
+        torch.cuda.synchronize()
+        t = float(np.median([a.elapsed_time(b) for a, b in evs])) * 1e-3
+        out[name] = {"ms": t * 1e3, "E": float(dp.E.cpu()[0])}
+    out["closure_entries"] = dp.closure.nvalues
+    out["x_entries"] = dp.nvalues
+    out["rel_diff_E_fp32_vs_fp64"] = abs(out["fp32-mfma"]["E"] - out["fp64"]["E"]) / abs(out["fp64"]["E"])
+    return out
+
+
 def config4_forms():
     """640 orbitals in uneven column blocks on the 1686177-DoF Q2 and Q4 meshes:
     autotuned kernels, hipGraph of 20 iterations, fp32-MFMA operator with fp64
@@ -342,6 +366,7 @@ def main(argv=None):
                 forms[name] = {"error": str(e)}
         _, ta, _ = time_path(dp, prec, 50, 5, kernel=1)
         forms["queue-kernel"] = {"apply_ms_mean": float(np.mean(ta) * 1e3)}
+        forms["energy"] = energy_form(dp)
         forms["graph20-" + args.prec] = graph_form(dp, prec)
         forms["graph20-fp32-mfma"] = graph_form(dp, PRECS["fp32-mfma"])
         out["forms"] = forms

@@ -288,8 +288,11 @@ int mfb_apply_op(const mfb_mesh* mesh, const mfb_mv* x, const mfb_mv* y, int op,
 /* Energy of eq. energy, E = tr((2 I - Mbar) Hbar), float64, summed in a
  * fixed order (bitwise repeatable).  d_Mbar, d_Hbar: M x M row-major device
  * arrays (X^T M X and X^T H X, e.g. from mfb_tmmult on a closure layout, in
- * the same column order); d_E: one double.  Errors: EINVAL, EHIP.          */
-int mfb_energy(int32_t M, const double* d_Mbar, const double* d_Hbar, double* d_E, void* stream);
+ * the same column order); d_E: one double; d_work: device scratch of
+ * 8 ceil(M/32)^2 bytes (one partial sum per 32x32 tile), 8-byte aligned.
+ * Errors: EINVAL, EHIP.                                                     */
+int mfb_energy(int32_t M, const double* d_Mbar, const double* d_Hbar, double* d_E, void* d_work,
+               void* stream);
 
 /* S = X^T Y (Alg. 8) and t = tr S, float64.  X and Y share the layout mv, or
  * mv is a closure layout: then X is in mv's source layout and Y in mv.

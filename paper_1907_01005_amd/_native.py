@@ -92,7 +92,7 @@ SIGNATURES = {
     "mfb_mv_update": (C.c_int, [VP, VP, VP, VP, VP, C.c_double, VP]),
     "mfb_create_closure": (C.c_int, [VP, C.POINTER(VP)]),
     "mfb_apply_op": (C.c_int, [VP, VP, VP, C.c_int, VP, VP, C.c_int, VP]),
-    "mfb_energy": (C.c_int, [C.c_int32, VP, VP, VP, VP]),
+    "mfb_energy": (C.c_int, [C.c_int32, VP, VP, VP, VP, VP]),
 }
 
 

@@ -235,6 +235,13 @@ def apply_op(mesh: Mesh, x: Layout, y: Layout, op: int, X, Y, prec: int = FP64,
                              int(prec), _stream(stream)))
 
 
-def energy(M: int, Mbar, Hbar, E, stream=None) -> None:
+def energy_work_bytes(M: int) -> int:
+    """Scratch of mfb_energy: one double per 32x32 tile of the M x M matrices."""
+    t = (int(M) + 31) // 32
+    return 8 * t * t
+
+
+def energy(M: int, Mbar, Hbar, E, work, stream=None) -> None:
     """mfb_energy: E = tr((2 I - Mbar) Hbar) into the one-element tensor E."""
-    check(lib().mfb_energy(int(M), _dev_ptr(Mbar), _dev_ptr(Hbar), _dev_ptr(E), _stream(stream)))
+    check(lib().mfb_energy(int(M), _dev_ptr(Mbar), _dev_ptr(Hbar), _dev_ptr(E), _dev_ptr(work),
+                           _stream(stream)))

@@ -526,11 +526,13 @@ int mfb_apply_op(const mfb_mesh* mesh, const mfb_mv* x, const mfb_mv* y, int op,
   MFB_CATCH
 }
 
-int mfb_energy(int32_t M, const double* d_Mbar, const double* d_Hbar, double* d_E, void* stream) {
+int mfb_energy(int32_t M, const double* d_Mbar, const double* d_Hbar, double* d_E, void* d_work,
+               void* stream) {
   MFB_TRY
-  if (!d_Mbar || !d_Hbar || !d_E) fail(MFB_EINVAL, "null argument");
+  if (!d_Mbar || !d_Hbar || !d_E || !d_work) fail(MFB_EINVAL, "null argument");
   if (M <= 0) fail(MFB_EINVAL, "M must be positive");
-  const int rc = mfb::gpu::launch_energy(M, d_Mbar, d_Hbar, d_E, stream);
+  if (((uintptr_t)d_work & 7) != 0) fail(MFB_EINVAL, "d_work must be 8-byte aligned");
+  const int rc = mfb::gpu::launch_energy(M, d_Mbar, d_Hbar, d_E, (double*)d_work, stream);
   if (rc != 0) fail(MFB_EHIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)rc));
   return MFB_OK;
   MFB_CATCH

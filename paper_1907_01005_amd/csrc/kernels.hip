@@ -1185,20 +1185,48 @@ hipError_t launch_apply_t(const ApplyParams& p, int kernel, hipStream_t st) {
 }
 
 // -------------------------------------------------------------- energy
-// E = tr((2 I - Mbar) Hbar) = 2 tr Hbar - sum_ab Mbar_ab Hbar_ba (eq. energy),
-// one workgroup, fixed-order strided sums and tree.
-__global__ __launch_bounds__(1024) void energy_kernel(int M, const double* __restrict__ Mb,
-                                                      const double* __restrict__ Hb,
-                                                      double* __restrict__ E) {
+// E = tr((2 I - Mbar) Hbar) = 2 tr Hbar - sum_ab Mbar_ab Hbar_ba (eq. energy).
+// Stage 1: one workgroup per 32x32 tile (a, b) sums Mbar_ab Hbar_ba, the tile
+// of Hbar^T staged through LDS so that both reads are coalesced; stage 2 adds
+// the tile sums and the trace.  Both in a fixed order.
+__global__ __launch_bounds__(256) void energy_tile_kernel(int M, const double* __restrict__ Mb,
+                                                          const double* __restrict__ Hb,
+                                                          double* __restrict__ part) {
+  __shared__ double ht[32][33];
+  __shared__ double red[256];
+  const int nt = (M + 31) / 32;
+  const int ta = blockIdx.x / nt, tb = blockIdx.x - ta * nt;
+  const int t = threadIdx.x, tx = t & 31, ty = t >> 5;
+  const int a0 = ta * 32, b0 = tb * 32;
+  // ht[i][j] = Hbar[b0 + i][a0 + j]
+  for (int i = ty; i < 32; i += 8) {
+    const int b = b0 + i, a = a0 + tx;
+    ht[i][tx] = (b < M && a < M) ? Hb[(int64_t)b * M + a] : 0.0;
+  }
+  __syncthreads();
+  double s = 0.0;
+  for (int i = ty; i < 32; i += 8) {
+    const int a = a0 + i, b = b0 + tx;
+    if (a < M && b < M) s = __builtin_fma(Mb[(int64_t)a * M + b], ht[tx][i], s);
+  }
+  red[t] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
+  }
+  if (t == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(1024) void energy_sum_kernel(int M, int ntiles,
+                                                         const double* __restrict__ Hb,
+                                                         const double* __restrict__ part,
+                                                         double* __restrict__ E) {
   __shared__ double red[1024];
   const int t = threadIdx.x;
   double tr = 0.0, mh = 0.0;
   for (int a = t; a < M; a += 1024) tr += Hb[(int64_t)a * M + a];
-  const int64_t MM = (int64_t)M * M;
-  for (int64_t q = t; q < MM; q += 1024) {
-    const int64_t a = q / M, b = q - a * M;
-    mh = __builtin_fma(Mb[q], Hb[b * M + a], mh);
-  }
+  for (int q = t; q < ntiles; q += 1024) mh += part[q];
   red[t] = 2.0 * tr - mh;
   __syncthreads();
   for (int h = 512; h > 0; h >>= 1) {
@@ -1288,8 +1316,15 @@ int launch_apply_op(const ApplyParams& p, int degree, int prec, int op, int64_t 
   return (int)e;
 }
 
-int launch_energy(int M, const double* Mbar, const double* Hbar, double* E, void* stream) {
-  hipLaunchKernelGGL(energy_kernel, dim3(1), dim3(1024), 0, (hipStream_t)stream, M, Mbar, Hbar, E);
+int launch_energy(int M, const double* Mbar, const double* Hbar, double* E, double* work,
+                  void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const int nt = (M + 31) / 32;
+  hipLaunchKernelGGL(energy_tile_kernel, dim3((unsigned)(nt * nt)), dim3(256), 0, st, M, Mbar,
+                     Hbar, work);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return (int)e;
+  hipLaunchKernelGGL(energy_sum_kernel, dim3(1), dim3(1024), 0, st, M, nt * nt, Hbar, work, E);
   return (int)hipGetLastError();
 }
 

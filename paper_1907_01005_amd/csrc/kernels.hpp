@@ -62,7 +62,8 @@ int launch_tmmult(const TmParams& p, void* stream);
 // op: 0 Hamiltonian, 1 mass; default kernel; destination nvalues for the fill.
 int launch_apply_op(const ApplyParams& p, int degree, int prec, int op, int64_t nvalues,
                     void* stream);
-int launch_energy(int M, const double* Mbar, const double* Hbar, double* E, void* stream);
+int launch_energy(int M, const double* Mbar, const double* Hbar, double* E, double* work,
+                  void* stream);
 
 // X <- X - tau (Y - X d), d_c = S[c][c] / S2[c][c], one workgroup per stored block.
 struct UpdateParams {

@@ -12,7 +12,7 @@ from typing import Callable, Optional, Sequence
 import numpy as np
 
 from .api import (FP64, OP_H, OP_M, Layout, Mesh, apply_H, apply_H_tuned, apply_op, energy,
-                  mv_update, tmmult)
+                  energy_work_bytes, mv_update, tmmult)
 
 
 class DeviceProblem:
@@ -79,6 +79,8 @@ class DeviceProblem:
         self.Mbar = torch.zeros_like(self.Hbar)
         self.tr_c = torch.zeros(2, dtype=torch.float64, device=self.device)
         self.E = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self.work_e = torch.zeros(energy_work_bytes(self.M) // 8, dtype=torch.float64,
+                                  device=self.device)
 
     def energy(self, prec: int = FP64, stream=None) -> None:
         """E(X) of eq. energy: H X and M X onto the closure, the two
@@ -89,7 +91,7 @@ class DeviceProblem:
         apply_op(self.mesh, self.layout, c, OP_M, self.X, self.YM, prec, stream)
         tmmult(c, self.X, self.YH, self.Hbar, self.tr_c[0:1], self.work_c, stream)
         tmmult(c, self.X, self.YM, self.Mbar, self.tr_c[1:2], self.work_c, stream)
-        energy(self.M, self.Mbar, self.Hbar, self.E, stream)
+        energy(self.M, self.Mbar, self.Hbar, self.E, self.work_e, stream)
 
     def original_order(self, S) -> np.ndarray:
         """An M x M device matrix in library column order, permuted back."""

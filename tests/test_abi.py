@@ -118,5 +118,6 @@ def test_closure_and_operator_argument_checks():
     other = Layout(m, np.full((8, 3), 1.0), 0.5)
     rc = lib().mfb_apply_op(m.handle, lay.handle, other.handle, 0, fake, fake2, 0, None)
     assert rc in (N.MFB_ESTATE, N.MFB_EPATTERN)
-    assert lib().mfb_energy(0, fake, fake, fake, None) == N.MFB_EINVAL
-    assert lib().mfb_energy(4, None, fake, fake, None) == N.MFB_EINVAL
+    assert lib().mfb_energy(0, fake, fake, fake, fake, None) == N.MFB_EINVAL
+    assert lib().mfb_energy(4, None, fake, fake, fake, None) == N.MFB_EINVAL
+    assert lib().mfb_energy(4, fake, fake, fake, None, None) == N.MFB_EINVAL

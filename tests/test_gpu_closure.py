@@ -147,3 +147,9 @@ def test_paper_scale_closure_energy(cfg):
     tmmult(dp.closure, dp.X, Y1, dp.Hbar, dp.tr_c[0:1], dp.work_c)
     torch.cuda.synchronize()
     assert np.array_equal(Ha, dp.Hbar.cpu().numpy())
+    from paper_1907_01005_amd import energy
+    E1 = dp.E.clone()
+    energy(dp.M, dp.Mbar, dp.Hbar, dp.E, dp.work_e)
+    e1 = float(dp.E.cpu()[0])
+    energy(dp.M, dp.Mbar, dp.Hbar, dp.E, dp.work_e)
+    assert e1 == float(dp.E.cpu()[0]) and np.isfinite(float(E1.cpu()[0]))
