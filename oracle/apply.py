@@ -125,3 +125,18 @@ def assemble(mesh: BoxMesh, v_qp: np.ndarray | None = None, which: str = "H") ->
         idx = dofs[c]
         A[np.ix_(idx, idx)] += Ke[c]
     return A
+
+
+def mmult(A: np.ndarray, B: np.ndarray, dest_mask: np.ndarray) -> np.ndarray:
+    """Alg. 7 with truncation: C = A B (A dense N x M, B dense M x M), kept
+    only where the destination pattern stores an entry (``dest_mask``,
+    N x M bool); the rest of the product is discarded."""
+    return np.where(dest_mask, A @ B, 0.0)
+
+
+def gradient(MX: np.ndarray, HX: np.ndarray, Mbar: np.ndarray, Hbar: np.ndarray,
+             dest_mask: np.ndarray) -> np.ndarray:
+    """eq. gradient on the pattern of X: G = -2 M X Hbar + 2 H X (2 I - Mbar),
+    each product by Alg. 7 truncated to the destination pattern."""
+    two_minus = 2.0 * np.eye(len(Mbar)) - Mbar
+    return mmult(MX, -2.0 * Hbar, dest_mask) + mmult(HX, 2.0 * two_minus, dest_mask)

@@ -12,7 +12,7 @@ import scipy.sparse as sp
 
 import synth
 
-from .apply import block_mask, dense_columns, energy, masked_apply, overlap, trace
+from .apply import block_mask, dense_columns, energy, gradient, masked_apply, overlap, trace
 from .mesh import BoxMesh
 from .pattern import build_pattern, closure_pattern, entry_coords
 
@@ -92,3 +92,14 @@ class OracleProblem:
         Hbar = overlap(self.X_sparse(), self.Y_all_sparse("H", "closure"))
         Mbar = overlap(self.X_sparse(), self.Y_all_sparse("M", "closure"))
         return Mbar, Hbar, energy(Mbar, Hbar)
+
+    def gradient_dense(self):
+        """(G, E): eq. gradient on the pattern of X as a dense N x M array
+        (original orbital order), and the energy; for small problems."""
+        orbs = np.arange(self.M)
+        X = self.X_columns(orbs)
+        HX = self.Y_columns(orbs, "H", "closure")
+        MX = self.Y_columns(orbs, "M", "closure")
+        Hbar, Mbar = X.T @ HX, X.T @ MX
+        G = gradient(MX, HX, Mbar, Hbar, block_mask(self.pattern, orbs))
+        return G, energy(Mbar, Hbar)

@@ -378,3 +378,48 @@ def test_energy_invariant_under_orthogonal_mixing():
     e2, _, _ = E(X @ Q)
     assert abs(e1 - e2) <= 1e-12 * abs(e1)
     assert abs(e1 - (2 * np.trace(Hb) - np.sum(Mb * Hb.T))) <= 1e-12 * abs(e1)
+
+
+# ---------------------------------------------------------------- gradient (eq. gradient) and Alg. 7
+def test_gradient_matches_central_differences_of_the_energy():
+    """tr(D^T G) = dE(X + eps D)/d eps for D on the pattern of X (the line-search
+    derivative of the text), by central differences of the closure energy."""
+    import synth
+    from oracle.apply import block_mask
+    from oracle.workload import OracleProblem
+    ms = synth.MeshSpec(4, 4, 2, (4.0, 4.0, 2.0), 2)
+    wl = synth.custom_workload(ms, 6, 1.8, 2, potential="wells", B=3)
+    op = OracleProblem(wl, values="generic", value_seed=4)
+    op.val = 0.05 * op.val
+    G, E0 = op.gradient_dense()
+    rng = np.random.default_rng(9)
+    mask = block_mask(op.pattern, np.arange(op.M)) & ~op.mesh.dirichlet_mask()[:, None]
+    D = np.where(mask, rng.standard_normal(mask.shape), 0.0)
+    node, orb = np.nonzero(mask)
+
+    def E_at(eps):
+        X = op.X_columns(np.arange(op.M)) + eps * D
+        q = OracleProblem.__new__(OracleProblem)
+        q.__dict__.update(op.__dict__)
+        q.node, q.orb, q.val = node, orb.astype(np.int32), X[node, orb]
+        return q.gradient_dense()[1]
+
+    h = 1e-4
+    fd = (E_at(h) - E_at(-h)) / (2 * h)
+    an = float(np.sum(D * G))
+    assert abs(fd - an) <= 1e-6 * max(abs(an), 1.0), (fd, an)
+    assert abs(E_at(0.0) - E0) <= 1e-12 * abs(E0)
+
+
+def test_mmult_truncation_brute_force():
+    """Alg. 7: entries outside the destination pattern are discarded, entries
+    inside equal the full product, element by element."""
+    rng = np.random.default_rng(2)
+    A = rng.standard_normal((40, 9))
+    B = rng.standard_normal((9, 9))
+    mask = rng.random((40, 9)) < 0.4
+    C = oapply.mmult(A, B, mask)
+    for i in range(40):
+        for j in range(9):
+            ref = sum(A[i, k] * B[k, j] for k in range(9)) if mask[i, j] else 0.0
+            assert abs(C[i, j] - ref) <= 1e-12 * (1 + abs(ref))
