@@ -294,6 +294,31 @@ int mfb_apply_op(const mfb_mesh* mesh, const mfb_mv* x, const mfb_mv* y, int op,
 int mfb_energy(int32_t M, const double* d_Mbar, const double* d_Hbar, double* d_E, void* d_work,
                void* stream);
 
+/* Alg. 7 with truncation: C = mask_c(A (alpha B + beta I)), or C += that
+ * when accumulate != 0.  A lives in layout a, C in layout c; a and c share
+ * rows and columns (equal, or one the closure of the other).  Entries of the
+ * product outside c's stored blocks are discarded (the destination's pattern
+ * decides, as the gradient is denser than X).  d_B: M x M row-major device
+ * array in library column order (e.g. Hbar, Mbar from mfb_tmmult), treated
+ * as dense.  Each block of C is summed over the blocks of A's row block in a
+ * fixed order (bitwise repeatable); d_C must not alias d_A.  With A = M X,
+ * H X on the closure and C on X's pattern, two calls give the gradient of
+ * eq. gradient: alpha = -2, beta = 0 with B = Hbar, then alpha = -2, beta = 4
+ * with B = Mbar, accumulated.  Errors: EPATTERN, ESTATE, EINVAL, EHIP.       */
+int mfb_mmult(const mfb_mv* a, const mfb_mv* c, const double* d_A, const double* d_B, double alpha,
+              double beta, double* d_C, int accumulate, void* stream);
+
+/* Y += alpha X over the info.nvalues stored values of layout mv (a descent
+ * step X <- X - tau G with alpha = -tau).  Errors: EINVAL, EHIP.            */
+int mfb_mv_axpy(const mfb_mv* mv, double alpha, const double* d_X, double* d_Y, void* stream);
+
+/* tr(X^T Y) = sum over stored entries of X . Y (eq. G_ops4: the directional
+ * derivative tr(D^T G) of a line search), float64, fixed order.  d_out: one
+ * double; d_work: 8 KiB of device scratch (1024 partial sums), 8-byte
+ * aligned.  Errors: EINVAL, EHIP.                                           */
+int mfb_mv_dot(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d_out, void* d_work,
+               void* stream);
+
 /* S = X^T Y (Alg. 8) and t = tr S, float64.  X and Y share the layout mv, or
  * mv is a closure layout: then X is in mv's source layout and Y in mv.
  * d_S: M*M doubles, fully written (entries outside the product pattern are

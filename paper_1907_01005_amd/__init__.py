@@ -19,6 +19,9 @@ from .api import (  # noqa: F401
     apply_H_tuned,
     apply_op,
     energy,
+    mmult,
+    mv_axpy,
+    mv_dot,
     mv_update,
     tmmult,
 )

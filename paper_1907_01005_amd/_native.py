@@ -93,6 +93,9 @@ SIGNATURES = {
     "mfb_create_closure": (C.c_int, [VP, C.POINTER(VP)]),
     "mfb_apply_op": (C.c_int, [VP, VP, VP, C.c_int, VP, VP, C.c_int, VP]),
     "mfb_energy": (C.c_int, [C.c_int32, VP, VP, VP, VP, VP]),
+    "mfb_mmult": (C.c_int, [VP, VP, VP, VP, C.c_double, C.c_double, VP, C.c_int, VP]),
+    "mfb_mv_axpy": (C.c_int, [VP, C.c_double, VP, VP, VP]),
+    "mfb_mv_dot": (C.c_int, [VP, VP, VP, VP, VP, VP]),
 }
 
 

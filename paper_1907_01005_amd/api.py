@@ -245,3 +245,24 @@ def energy(M: int, Mbar, Hbar, E, work, stream=None) -> None:
     """mfb_energy: E = tr((2 I - Mbar) Hbar) into the one-element tensor E."""
     check(lib().mfb_energy(int(M), _dev_ptr(Mbar), _dev_ptr(Hbar), _dev_ptr(E), _dev_ptr(work),
                            _stream(stream)))
+
+
+def mmult(a: Layout, c: Layout, A, B, alpha: float, beta: float, Cv, accumulate: bool = False,
+          stream=None) -> None:
+    """mfb_mmult (Alg. 7 with truncation): Cv = [Cv +] mask_c(A (alpha B + beta I))."""
+    check(lib().mfb_mmult(a.handle, c.handle, _dev_ptr(A), _dev_ptr(B), float(alpha), float(beta),
+                          _dev_ptr(Cv), int(bool(accumulate)), _stream(stream)))
+
+
+def mv_axpy(layout: Layout, alpha: float, X, Y, stream=None) -> None:
+    """mfb_mv_axpy: Y += alpha X over the stored values."""
+    check(lib().mfb_mv_axpy(layout.handle, float(alpha), _dev_ptr(X), _dev_ptr(Y), _stream(stream)))
+
+
+DOT_WORK_DOUBLES = 1024
+
+
+def mv_dot(layout: Layout, X, Y, out, work, stream=None) -> None:
+    """mfb_mv_dot: out = tr(X^T Y) over the stored entries (fixed order)."""
+    check(lib().mfb_mv_dot(layout.handle, _dev_ptr(X), _dev_ptr(Y), _dev_ptr(out), _dev_ptr(work),
+                           _stream(stream)))

@@ -54,7 +54,7 @@ struct MvLayout {
   size_t off_items = 0, off_units = 0, off_pair_tab = 0, off_pair_ptr = 0, off_pair_list = 0,
          off_cb_of_col = 0, off_cb_start = 0, off_blk_off = 0, off_blk_col0 = 0, off_blk_w = 0,
          off_rowoff = 0, off_shell_ptr = 0, off_shell_ro = 0, off_s2 = 0, off_dest_rowoff = 0,
-         bytes = 0;
+         off_rowptr = 0, off_blk_row = 0, bytes = 0;
 };
 
 MvLayout mv_layout(const mfb::MvPlan& v) {
@@ -90,6 +90,10 @@ MvLayout mv_layout(const mfb::MvPlan& v) {
   o = align256(o + sizeof(mfb::S2Desc) * v.s2.size());
   L.off_dest_rowoff = o;
   o = align256(o + sizeof(int32_t) * v.dest_rowoff.size());
+  L.off_rowptr = o;
+  o = align256(o + sizeof(int64_t) * v.rowptr.size());
+  L.off_blk_row = o;
+  o = align256(o + sizeof(int32_t) * v.colidx.size());
 
   L.bytes = std::max<size_t>(o, 256);
   return L;
@@ -385,6 +389,13 @@ int mfb_mv_bind(mfb_mv* mv, void* d_meta, void* stream) {
   put(L.off_shell_ro, p.shell_ro.data(), sizeof(int32_t) * p.shell_ro.size());
   put(L.off_s2, p.s2.data(), sizeof(mfb::S2Desc) * p.s2.size());
   put(L.off_dest_rowoff, p.dest_rowoff.data(), sizeof(int32_t) * p.dest_rowoff.size());
+  put(L.off_rowptr, p.rowptr.data(), sizeof(int64_t) * p.rowptr.size());
+  {
+    std::vector<int32_t> brow(p.colidx.size());
+    for (size_t r = 0; r + 1 < p.rowptr.size(); ++r)
+      for (int64_t k = p.rowptr[r]; k < p.rowptr[r + 1]; ++k) brow[k] = (int32_t)r;
+    put(L.off_blk_row, brow.data(), sizeof(int32_t) * brow.size());
+  }
 
   {
     std::vector<int32_t> col0(p.colidx.size()), wid(p.colidx.size());
@@ -533,6 +544,69 @@ int mfb_energy(int32_t M, const double* d_Mbar, const double* d_Hbar, double* d_
   if (M <= 0) fail(MFB_EINVAL, "M must be positive");
   if (((uintptr_t)d_work & 7) != 0) fail(MFB_EINVAL, "d_work must be 8-byte aligned");
   const int rc = mfb::gpu::launch_energy(M, d_Mbar, d_Hbar, d_E, (double*)d_work, stream);
+  if (rc != 0) fail(MFB_EHIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)rc));
+  return MFB_OK;
+  MFB_CATCH
+}
+
+// Two layouts with the same rows and columns: equal, or one the closure of the other.
+static bool same_rows_and_columns(const mfb_mv* a, const mfb_mv* b) {
+  return a == b || a->source == b || b->source == a;
+}
+
+static mfb::gpu::BlockView block_view(const mfb_mv* v) {
+  const char* mb = (const char*)v->d_meta;
+  mfb::gpu::BlockView b;
+  b.rowptr = (const int64_t*)(mb + v->lay.off_rowptr);
+  b.blk_off = (const int64_t*)(mb + v->lay.off_blk_off);
+  b.blk_col0 = (const int32_t*)(mb + v->lay.off_blk_col0);
+  b.blk_w = (const int32_t*)(mb + v->lay.off_blk_w);
+  b.blk_row = (const int32_t*)(mb + v->lay.off_blk_row);
+  b.nblocks = (int64_t)v->plan.colidx.size();
+  return b;
+}
+
+int mfb_mmult(const mfb_mv* a, const mfb_mv* c, const double* d_A, const double* d_B, double alpha,
+              double beta, double* d_C, int accumulate, void* stream) {
+  MFB_TRY
+  if (!a || !c || !d_A || !d_B || !d_C) fail(MFB_EINVAL, "null argument");
+  if (!same_rows_and_columns(a, c)) fail(MFB_EPATTERN, "a and c must share rows and columns");
+  if (!a->bound || !c->bound) fail(MFB_ESTATE, "layout metadata not bound");
+  if (d_A == d_C) fail(MFB_EINVAL, "A and C must not alias");
+  if (!std::isfinite(alpha) || !std::isfinite(beta)) fail(MFB_EINVAL, "alpha and beta must be finite");
+  mfb::gpu::MmultParams q;
+  q.A = d_A;
+  q.B = d_B;
+  q.C = d_C;
+  q.a = block_view(a);
+  q.c = block_view(c);
+  q.M = a->plan.M;
+  q.alpha = alpha;
+  q.beta = beta;
+  q.accumulate = accumulate ? 1 : 0;
+  const int rc = mfb::gpu::launch_mmult(q, stream);
+  if (rc != 0) fail(MFB_EHIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)rc));
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_mv_axpy(const mfb_mv* mv, double alpha, const double* d_X, double* d_Y, void* stream) {
+  MFB_TRY
+  if (!mv || !d_X || !d_Y) fail(MFB_EINVAL, "null argument");
+  if (!std::isfinite(alpha)) fail(MFB_EINVAL, "alpha must be finite");
+  const int rc = mfb::gpu::launch_axpy(mv->plan.block_offset.back(), alpha, d_X, d_Y, stream);
+  if (rc != 0) fail(MFB_EHIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)rc));
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_mv_dot(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d_out, void* d_work,
+               void* stream) {
+  MFB_TRY
+  if (!mv || !d_X || !d_Y || !d_out || !d_work) fail(MFB_EINVAL, "null argument");
+  if (((uintptr_t)d_work & 7) != 0) fail(MFB_EINVAL, "d_work must be 8-byte aligned");
+  const int rc = mfb::gpu::launch_dot(mv->plan.block_offset.back(), d_X, d_Y, d_out,
+                                      (double*)d_work, stream);
   if (rc != 0) fail(MFB_EHIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)rc));
   return MFB_OK;
   MFB_CATCH

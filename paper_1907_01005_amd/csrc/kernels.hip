@@ -1236,6 +1236,78 @@ __global__ __launch_bounds__(1024) void energy_sum_kernel(int M, int ntiles,
   if (t == 0) *E = red[0];
 }
 
+// -------------------------------------------------------------- Alg. 7
+// C = [C +] mask_c(A (alpha B + beta I)) with truncation: one workgroup per
+// stored block (i, j) of C sums A_{i,k} (alpha B_{k,j} + beta I_{k,j}) over the
+// stored blocks (i, k) of A's row block i, in a fixed order; entries of the
+// product outside C's blocks are never formed.  B is dense M x M row-major.
+__global__ __launch_bounds__(256) void mmult_kernel(MmultParams p) {
+  const int64_t q = blockIdx.x;
+  const int i = p.c.blk_row[q];
+  const int64_t dst = p.c.blk_off[q];
+  const int wj = p.c.blk_w[q], cj0 = p.c.blk_col0[q];
+  const int64_t n = p.c.blk_off[q + 1] - dst;  // rows x wj
+  const int64_t k0 = p.a.rowptr[i], k1 = p.a.rowptr[i + 1];
+  for (int64_t e = threadIdx.x; e < n; e += 256) {
+    const int64_t r = e / wj;
+    const int b = (int)(e - r * wj);
+    double s = 0.0;
+    for (int64_t kb = k0; kb < k1; ++kb) {
+      const int ck0 = p.a.blk_col0[kb], wk = p.a.blk_w[kb];
+      const double* __restrict__ arow = p.A + p.a.blk_off[kb] + r * wk;
+      const double* __restrict__ bcol = p.B + (int64_t)ck0 * p.M + cj0 + b;
+      double t = 0.0;
+      for (int x = 0; x < wk; ++x) t = __builtin_fma(arow[x], bcol[(int64_t)x * p.M], t);
+      s = __builtin_fma(p.alpha, t, s);
+      if (ck0 == cj0) s = __builtin_fma(p.beta, arow[b], s);
+    }
+    p.C[dst + e] = p.accumulate ? p.C[dst + e] + s : s;
+  }
+}
+
+// -------------------------------------------------------------- vectors
+__global__ __launch_bounds__(256) void axpy_kernel(int64_t n, double alpha,
+                                                   const double* __restrict__ X,
+                                                   double* __restrict__ Y) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    Y[i] = __builtin_fma(alpha, X[i], Y[i]);
+}
+
+// tr(X^T Y) = sum of X . Y over the stored entries (the column-wise inner
+// product of eq. G_ops4): workgroup g sums its contiguous chunk, then one
+// workgroup sums the partials; both in a fixed order.
+__global__ __launch_bounds__(256) void dot_chunk_kernel(int64_t n, const double* __restrict__ X,
+                                                        const double* __restrict__ Y,
+                                                        double* __restrict__ part) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(n, lo + chunk);
+  double s = 0.0;
+  for (int64_t i = lo + t; i < hi; i += 256) s = __builtin_fma(X[i], Y[i], s);
+  red[t] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
+  }
+  if (t == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(1024) void dot_sum_kernel(int np, const double* __restrict__ part,
+                                                       double* __restrict__ out) {
+  __shared__ double red[1024];
+  const int t = threadIdx.x;
+  red[t] = t < np ? part[t] : 0.0;
+  __syncthreads();
+  for (int h = 512; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
+  }
+  if (t == 0) *out = red[0];
+}
+
 // -------------------------------------------------------------- update
 __global__ __launch_bounds__(256) void update_kernel(UpdateParams p) {
   const int64_t k = blockIdx.x;
@@ -1314,6 +1386,32 @@ int launch_apply_op(const ApplyParams& p, int degree, int prec, int op, int64_t 
   else
     return -2;
   return (int)e;
+}
+
+int launch_mmult(const MmultParams& p, void* stream) {
+  if (p.c.nblocks == 0) return 0;
+  hipLaunchKernelGGL(mmult_kernel, dim3((unsigned)p.c.nblocks), dim3(256), 0, (hipStream_t)stream,
+                     p);
+  return (int)hipGetLastError();
+}
+
+int launch_axpy(int64_t n, double alpha, const double* X, double* Y, void* stream) {
+  if (n == 0) return 0;
+  const int64_t blocks = std::min<int64_t>(4096, (n + 255) / 256);
+  hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, n,
+                     alpha, X, Y);
+  return (int)hipGetLastError();
+}
+
+int launch_dot(int64_t n, const double* X, const double* Y, double* out, double* work,
+               void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const int np = (int)std::max<int64_t>(1, std::min<int64_t>(kDotPartials, (n + 2047) / 2048));
+  hipLaunchKernelGGL(dot_chunk_kernel, dim3((unsigned)np), dim3(256), 0, st, n, X, Y, work);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return (int)e;
+  hipLaunchKernelGGL(dot_sum_kernel, dim3(1), dim3(1024), 0, st, np, work, out);
+  return (int)hipGetLastError();
 }
 
 int launch_energy(int M, const double* Mbar, const double* Hbar, double* E, double* work,

@@ -79,6 +79,32 @@ struct UpdateParams {
   double tau;
 };
 int launch_update(const UpdateParams& p, void* stream);
+
+// Device view of a layout's stored blocks (CSR over row blocks).
+struct BlockView {
+  const int64_t* rowptr;    // [nrowblocks+1]
+  const int64_t* blk_off;   // [nblocks+1] value offset of each block
+  const int32_t* blk_col0;  // [nblocks] first column of the block's column block
+  const int32_t* blk_w;     // [nblocks] its width
+  const int32_t* blk_row;   // [nblocks] its row block
+  int64_t nblocks;
+};
+
+// Alg. 7: C = [C +] mask_c(A (alpha B + beta I)), B dense M x M row-major.
+struct MmultParams {
+  const double* A;
+  const double* B;
+  double* C;
+  BlockView a, c;
+  int32_t M;
+  int32_t accumulate;
+  double alpha, beta;
+};
+int launch_mmult(const MmultParams& p, void* stream);
+int launch_axpy(int64_t n, double alpha, const double* X, double* Y, void* stream);
+// fixed-order dot product; work: kDotPartials doubles
+constexpr int kDotPartials = 1024;
+int launch_dot(int64_t n, const double* X, const double* Y, double* out, double* work, void* stream);
 int device_cu_count();
 
 }  // namespace gpu

@@ -11,8 +11,8 @@ from typing import Callable, Optional, Sequence
 
 import numpy as np
 
-from .api import (FP64, OP_H, OP_M, Layout, Mesh, apply_H, apply_H_tuned, apply_op, energy,
-                  energy_work_bytes, mv_update, tmmult)
+from .api import (DOT_WORK_DOUBLES, FP64, OP_H, OP_M, Layout, Mesh, apply_H, apply_H_tuned,
+                  apply_op, energy, energy_work_bytes, mmult, mv_axpy, mv_dot, mv_update, tmmult)
 
 
 class DeviceProblem:
@@ -92,6 +92,28 @@ class DeviceProblem:
         tmmult(c, self.X, self.YH, self.Hbar, self.tr_c[0:1], self.work_c, stream)
         tmmult(c, self.X, self.YM, self.Mbar, self.tr_c[1:2], self.work_c, stream)
         energy(self.M, self.Mbar, self.Hbar, self.E, self.work_e, stream)
+
+    def gradient(self, prec: int = FP64, stream=None) -> None:
+        """Energy, then the gradient of eq. gradient on the pattern of X into
+        self.G: -2 (M X) Hbar + (H X)(4 I - 2 Mbar), two Alg. 7 products from
+        the closure onto X's pattern."""
+        import torch
+        self.energy(prec, stream)
+        if getattr(self, "G", None) is None:
+            self.G = self.layout.new_values(self.device)
+            self.dots = torch.zeros(2, dtype=torch.float64, device=self.device)
+            self.work_d = torch.zeros(DOT_WORK_DOUBLES, dtype=torch.float64, device=self.device)
+        c = self.closure
+        mmult(c, self.layout, self.YM, self.Hbar, -2.0, 0.0, self.G, False, stream)
+        mmult(c, self.layout, self.YH, self.Mbar, -2.0, 4.0, self.G, True, stream)
+
+    def descent_step(self, tau: float, prec: int = FP64, stream=None) -> None:
+        """One steepest-descent step of the orbital minimisation: E and G at X,
+        dots[0] = tr(G^T G) (minus the directional derivative along -G), then
+        X <- X - tau G on X's pattern."""
+        self.gradient(prec, stream)
+        mv_dot(self.layout, self.G, self.G, self.dots[0:1], self.work_d, stream)
+        mv_axpy(self.layout, -float(tau), self.G, self.X, stream)
 
     def original_order(self, S) -> np.ndarray:
         """An M x M device matrix in library column order, permuted back."""
