@@ -312,6 +312,11 @@ int mfb_mmult(const mfb_mv* a, const mfb_mv* c, const double* d_A, const double*
  * step X <- X - tau G with alpha = -tau).  Errors: EINVAL, EHIP.            */
 int mfb_mv_axpy(const mfb_mv* mv, double alpha, const double* d_X, double* d_Y, void* stream);
 
+/* X[:, c] *= scale[c] for every column c (library column order) over the
+ * stored values of layout mv, e.g. to normalise columns to X^T M X = 1 on the
+ * diagonal.  d_scale: M device doubles.  Errors: EINVAL, ESTATE, EHIP.      */
+int mfb_mv_scale_columns(const mfb_mv* mv, const double* d_scale, double* d_X, void* stream);
+
 /* tr(X^T Y) = sum over stored entries of X . Y (eq. G_ops4: the directional
  * derivative tr(D^T G) of a line search), float64, fixed order.  d_out: one
  * double; d_work: 8 KiB of device scratch (1024 partial sums), 8-byte

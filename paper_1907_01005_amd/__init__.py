@@ -22,6 +22,7 @@ from .api import (  # noqa: F401
     mmult,
     mv_axpy,
     mv_dot,
+    mv_scale_columns,
     mv_update,
     tmmult,
 )

@@ -96,6 +96,7 @@ SIGNATURES = {
     "mfb_mmult": (C.c_int, [VP, VP, VP, VP, C.c_double, C.c_double, VP, C.c_int, VP]),
     "mfb_mv_axpy": (C.c_int, [VP, C.c_double, VP, VP, VP]),
     "mfb_mv_dot": (C.c_int, [VP, VP, VP, VP, VP, VP]),
+    "mfb_mv_scale_columns": (C.c_int, [VP, VP, VP, VP]),
 }
 
 

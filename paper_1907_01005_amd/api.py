@@ -266,3 +266,8 @@ def mv_dot(layout: Layout, X, Y, out, work, stream=None) -> None:
     """mfb_mv_dot: out = tr(X^T Y) over the stored entries (fixed order)."""
     check(lib().mfb_mv_dot(layout.handle, _dev_ptr(X), _dev_ptr(Y), _dev_ptr(out), _dev_ptr(work),
                            _stream(stream)))
+
+
+def mv_scale_columns(layout: Layout, scale, X, stream=None) -> None:
+    """mfb_mv_scale_columns: X[:, c] *= scale[c] (library column order)."""
+    check(lib().mfb_mv_scale_columns(layout.handle, _dev_ptr(scale), _dev_ptr(X), _stream(stream)))

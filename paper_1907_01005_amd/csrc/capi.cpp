@@ -600,6 +600,16 @@ int mfb_mv_axpy(const mfb_mv* mv, double alpha, const double* d_X, double* d_Y, 
   MFB_CATCH
 }
 
+int mfb_mv_scale_columns(const mfb_mv* mv, const double* d_scale, double* d_X, void* stream) {
+  MFB_TRY
+  if (!mv || !d_scale || !d_X) fail(MFB_EINVAL, "null argument");
+  if (!mv->bound) fail(MFB_ESTATE, "layout metadata not bound");
+  const int rc = mfb::gpu::launch_scale_columns(block_view(mv), d_scale, d_X, stream);
+  if (rc != 0) fail(MFB_EHIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)rc));
+  return MFB_OK;
+  MFB_CATCH
+}
+
 int mfb_mv_dot(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d_out, void* d_work,
                void* stream) {
   MFB_TRY

@@ -1308,6 +1308,16 @@ __global__ __launch_bounds__(1024) void dot_sum_kernel(int np, const double* __r
   if (t == 0) *out = red[0];
 }
 
+// X[:, c] *= scale[c] over the stored blocks (library column order).
+__global__ __launch_bounds__(256) void scale_columns_kernel(BlockView v, const double* __restrict__ sc,
+                                                            double* __restrict__ X) {
+  const int64_t k = blockIdx.x;
+  const int64_t o0 = v.blk_off[k], o1 = v.blk_off[k + 1];
+  const int c0 = v.blk_col0[k], w = v.blk_w[k];
+  for (int64_t e = o0 + threadIdx.x; e < o1; e += blockDim.x)
+    X[e] *= sc[c0 + (int)((e - o0) % w)];
+}
+
 // -------------------------------------------------------------- update
 __global__ __launch_bounds__(256) void update_kernel(UpdateParams p) {
   const int64_t k = blockIdx.x;
@@ -1392,6 +1402,13 @@ int launch_mmult(const MmultParams& p, void* stream) {
   if (p.c.nblocks == 0) return 0;
   hipLaunchKernelGGL(mmult_kernel, dim3((unsigned)p.c.nblocks), dim3(256), 0, (hipStream_t)stream,
                      p);
+  return (int)hipGetLastError();
+}
+
+int launch_scale_columns(const BlockView& v, const double* scale, double* X, void* stream) {
+  if (v.nblocks == 0) return 0;
+  hipLaunchKernelGGL(scale_columns_kernel, dim3((unsigned)v.nblocks), dim3(256), 0,
+                     (hipStream_t)stream, v, scale, X);
   return (int)hipGetLastError();
 }
 

@@ -102,6 +102,7 @@ struct MmultParams {
 };
 int launch_mmult(const MmultParams& p, void* stream);
 int launch_axpy(int64_t n, double alpha, const double* X, double* Y, void* stream);
+int launch_scale_columns(const BlockView& v, const double* scale, double* X, void* stream);
 // fixed-order dot product; work: kDotPartials doubles
 constexpr int kDotPartials = 1024;
 int launch_dot(int64_t n, const double* X, const double* Y, double* out, double* work, void* stream);

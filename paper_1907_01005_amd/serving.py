@@ -1,12 +1,25 @@
 """Continuous-batching request loop over device-resident BCSR multivectors.
 
-A request is a small minimisation run on its own mesh: ``iters`` iterations
-of
+A request is a small minimisation run on its own mesh, ``iters`` iterations
+of one of two methods on the pattern of X:
 
-    Y = H X;  S = X^T Y;  S2 = X^T X;  X <- X - tau (Y - X diag(S)/diag(S2))
+* "rayleigh":  Y = H X;  S = X^T Y;  S2 = X^T X;
+               X <- X - tau (Y - X diag(S)/diag(S2))
+  (a column-wise Rayleigh-quotient step over the required operations);
+* "om": steepest descent on the energy of eq. energy: H X and M X onto the
+  closure of X's pattern, Hbar, Mbar and E, the gradient of eq. gradient by
+  Alg. 7 truncated to X's pattern, X <- X - tau G.  The functional is
+  bounded below only where H is negative on the growing directions, so H is
+  shifted by -shift M (the potential V - shift; H - shift M is exactly that
+  operator) and the columns are first scaled to diag(X^T M X) = 1/4, inside
+  the basin where components along positive directions decay.  Every step
+  takes a backtracking (Armijo) line search: tau is doubled from the last
+  accepted value and halved until E(X - tau G) <= E(X) - tau tr(G^T G) / 2
+  (eq. G_ops4 gives the directional derivative).  The searches read E back,
+  so an "om" request runs its loop in a host thread of its own; the
+  scheduler keeps polling the other requests meanwhile.
 
-on the pattern of X (the required operations of Sec. 2 with a column-wise
-Rayleigh-quotient step standing in for the paper's minimiser).  Requests
+Requests
 arrive over time; the server admits a waiting request as soon as a slot is
 free and its device footprint (BCSR values, metadata, workspace, S) fits in
 the byte budget, so requests that arrive while others run are started at
@@ -49,11 +62,13 @@ class Request:
     prec: int
     iters: int
     seed: int
+    method: str = "rayleigh"       # "rayleigh" or "om" (see the module docstring)
+    shift: float = 2.0             # "om": the spectral shift (potential V - shift)
 
 
 def request_stream(n: int = 96, rate: float = 40.0, seed: int = 5, meshes=MESHES,
                    m_range=(32, 640), r_range=(3.0, 5.0), precs=(FP32_MFMA, FP64),
-                   degrees=(2, 4), iters: int = 10) -> List[Request]:
+                   degrees=(2, 4), iters: int = 10, method: str = "rayleigh") -> List[Request]:
     """Poisson arrivals; mesh uniform over `meshes`; degree and precision 50/50;
     M log-uniform in m_range; support radius uniform in r_range."""
     rng = np.random.default_rng(seed)
@@ -66,7 +81,7 @@ def request_stream(n: int = 96, rate: float = 40.0, seed: int = 5, meshes=MESHES
         M = int(round(math.exp(rng.uniform(math.log(m_range[0]), math.log(m_range[1])))))
         r = float(rng.uniform(*r_range))
         prec = int(precs[int(rng.integers(len(precs)))])
-        out.append(Request(i, t, cells, degree, M, r, prec, iters, seed * 1000 + i))
+        out.append(Request(i, t, cells, degree, M, r, prec, iters, seed * 1000 + i, method))
     return out
 
 
@@ -191,6 +206,7 @@ class _Plan:
     values: np.ndarray
     nbytes: int
     h: float
+    closure: Any = None
 
 
 class GpuExecutor:
@@ -213,14 +229,25 @@ class GpuExecutor:
         ms = synth.MeshSpec(*cells, L, req.degree)
         wl = synth.custom_workload(ms, req.M, req.radius, req.seed, potential="wells")
         mesh = Mesh(*cells, L, req.degree, ms.dirichlet)
-        mesh.set_potential(synth.potential_at(wl, mesh.qp_points().reshape(-1, 3)))
+        V = synth.potential_at(wl, mesh.qp_points().reshape(-1, 3))
+        mesh.set_potential(V - req.shift if req.method == "om" else V)
         layout = Layout(mesh, wl.centres, wl.radius, wl.colblock_sizes)
         node, orb, val = synth.orbital_values(wl)
         values = layout.pack(node, orb, val)
         M = layout.M
         nbytes = (2 * 8 * max(layout.nvalues, 1) + mesh.meta_bytes + layout.meta_bytes
                   + layout.work_bytes + 2 * 8 * M * M + 16)
-        return _Plan(req, mesh, layout, values, nbytes, 1.0)
+        closure = None
+        if req.method == "om":
+            from .api import energy_work_bytes
+            closure = layout.closure()
+            # X, G, trial X; H X and M X on the closure; its metadata and
+            # workspace; Hbar, Mbar; energy and dot scratch
+            nbytes = (3 * 8 * max(layout.nvalues, 1) + 2 * 8 * max(closure.nvalues, 1)
+                      + mesh.meta_bytes + layout.meta_bytes + closure.meta_bytes
+                      + closure.work_bytes + 2 * 8 * M * M + energy_work_bytes(M) + 8 * 1024
+                      + 8 * (req.iters + 8))
+        return _Plan(req, mesh, layout, values, nbytes, 1.0, closure)
 
     def prepare_async(self, req: Request) -> Future:
         return self.pool.submit(self._plan, req)
@@ -230,6 +257,8 @@ class GpuExecutor:
 
     # -- execution
     def start(self, plan: _Plan):
+        if plan.req.method == "om":
+            return self._start_om(plan)
         import torch
         from .api import mv_update, apply_H, tmmult
         stream = torch.cuda.Stream(device=self.device)
@@ -261,18 +290,117 @@ class GpuExecutor:
         return {"plan": plan, "stream": stream, "evs": evs, "end": end,
                 "bufs": (X, Y, work, S, S2, tr)}
 
+    def _start_om(self, plan: _Plan):
+        """Orbital-minimisation steps on the slot's stream, driven by a host
+        thread (see the module docstring)."""
+        import torch
+        tok = {"plan": plan, "evs": [], "tau": 0.0, "energies": [], "error": None}
+        tok["thread"] = threading.Thread(target=self._run_om, args=(tok,), daemon=True)
+        tok["thread"].start()
+        return tok
+
+    def _run_om(self, tok) -> None:
+        import torch
+        from .api import (DOT_WORK_DOUBLES, OP_H, OP_M, apply_op, energy, energy_work_bytes,
+                          mmult, mv_axpy, mv_dot, mv_scale_columns, tmmult)
+        try:
+            plan = tok["plan"]
+            dev, lay, clo, mesh, prec = (self.device, plan.layout, plan.closure, plan.mesh,
+                                         plan.req.prec)
+            stream = torch.cuda.Stream(device=dev)
+            tok["stream"] = stream
+            M = lay.M
+            with torch.cuda.stream(stream):
+                mesh.bind(dev, stream)
+                lay.bind(dev, stream)
+                clo.bind(dev, stream)
+                X = torch.from_numpy(plan.values).to(dev) if lay.nvalues else \
+                    torch.zeros(1, dtype=torch.float64, device=dev)
+                Xt, G = lay.new_values(dev), lay.new_values(dev)
+                YH, YM = clo.new_values(dev), clo.new_values(dev)
+                work = clo.new_work(dev)
+                Hb = torch.zeros((M, M), dtype=torch.float64, device=dev)
+                Mb = torch.zeros_like(Hb)
+                tr = torch.zeros(2, dtype=torch.float64, device=dev)
+                wE = torch.zeros(energy_work_bytes(M) // 8, dtype=torch.float64, device=dev)
+                wD = torch.zeros(DOT_WORK_DOUBLES, dtype=torch.float64, device=dev)
+                E = torch.zeros(1, dtype=torch.float64, device=dev)
+                gg = torch.zeros(1, dtype=torch.float64, device=dev)
+
+                def energy_at(Xv, timed=False) -> float:
+                    a = torch.cuda.Event(enable_timing=True)
+                    b = torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                    apply_op(mesh, lay, clo, OP_H, Xv, YH, prec, stream)
+                    b.record(stream)
+                    apply_op(mesh, lay, clo, OP_M, Xv, YM, prec, stream)
+                    tmmult(clo, Xv, YH, Hb, tr[0:1], work, stream)
+                    tmmult(clo, Xv, YM, Mb, tr[1:2], work, stream)
+                    energy(M, Mb, Hb, E, wE, stream)
+                    if timed:
+                        tok["evs"].append((a, b))
+                    stream.synchronize()
+                    return float(E.cpu()[0])
+
+                # columns to diag(X^T M X) = 1/4
+                energy_at(X)
+                d = torch.diagonal(Mb).cpu().numpy()
+                sc = np.where(d > 0, 0.5 / np.sqrt(np.where(d > 0, d, 1.0)), 1.0)
+                scale = torch.from_numpy(sc).to(dev)
+                mv_scale_columns(lay, scale, X, stream)
+                tau = 0.0
+                for k in range(plan.req.iters):
+                    e0 = energy_at(X, timed=True)
+                    tok["energies"].append(e0)
+                    mmult(clo, lay, YM, Hb, -2.0, 0.0, G, False, stream)
+                    mmult(clo, lay, YH, Mb, -2.0, 4.0, G, True, stream)
+                    mv_dot(lay, G, G, gg, wD, stream)
+                    stream.synchronize()
+                    g0 = float(gg.cpu()[0])
+                    if not g0 > 0.0:
+                        break
+                    tau = 2.0 * tau if tau > 0 else 0.5 * max(abs(e0), 1.0) / g0
+                    for _ in range(60):
+                        Xt.copy_(X)
+                        mv_axpy(lay, -tau, G, Xt, stream)
+                        if energy_at(Xt) <= e0 - 0.5 * tau * g0:
+                            break
+                        tau *= 0.5
+                    X.copy_(Xt)
+                tok["energies"].append(energy_at(X))
+                tok["tau"] = tau
+                tok["bufs"] = (X,)
+                tok["keep"] = (Xt, G, YH, YM, work, Hb, Mb, tr, wE, wD, E, gg, scale)
+                stream.synchronize()
+        except Exception as e:  # reported by finish()
+            tok["error"] = e
+
     def done(self, tok) -> bool:
+        if "thread" in tok:
+            return not tok["thread"].is_alive()
         return tok["end"].query()
 
     def finish(self, tok) -> dict:
-        tok["end"].synchronize()
-        X, Y, work, S, S2, tr = tok["bufs"]
         plan = tok["plan"]
+        if "thread" in tok:
+            tok["thread"].join()
+            if tok["error"] is not None:
+                raise tok["error"]
+        else:
+            tok["end"].synchronize()
         apply_s = [a.elapsed_time(b) * 1e-3 for a, b in tok["evs"]]
-        trs = tr.cpu().numpy()
-        out = {"apply_s": apply_s, "entries": plan.layout.nvalues, "trace": float(trs[0]),
-               "trace_xx": float(trs[1]), "x_norm2": float((X[:plan.layout.nvalues] ** 2).sum()),
-               "prec": plan.req.prec, "bytes": plan.nbytes}
+        if plan.req.method == "om":
+            X = tok["bufs"][0]
+            out = {"apply_s": apply_s, "entries": plan.layout.nvalues, "tau": tok["tau"],
+                   "energies": tok["energies"], "prec": plan.req.prec,
+                   "bytes": plan.nbytes, "method": "om"}
+        else:
+            X, Y, work, S, S2, tr = tok["bufs"]
+            trs = tr.cpu().numpy()
+            out = {"apply_s": apply_s, "entries": plan.layout.nvalues, "trace": float(trs[0]),
+                   "trace_xx": float(trs[1]),
+                   "x_norm2": float((X[:plan.layout.nvalues] ** 2).sum()),
+                   "prec": plan.req.prec, "bytes": plan.nbytes}
         if self.keep_X:
             out["X"] = X[:plan.layout.nvalues].cpu().numpy()
         return out
@@ -281,6 +409,8 @@ class GpuExecutor:
         # device buffers die with the token; drop the device copies of the metadata
         plan.mesh._meta = None
         plan.layout._meta = None
+        if plan.closure is not None:
+            plan.closure._meta = None
 
     def advance(self, now: float) -> float:
         return now

@@ -166,3 +166,33 @@ def test_uneven_blocks_640_orbitals_sampled(mesh_index):
     Sa = dp.S.cpu().numpy().copy()
     dp.overlap()
     assert np.array_equal(Sa, dp.S.cpu().numpy())
+
+
+def test_serving_orbital_minimisation_alone_and_in_mix():
+    """method "om": steepest descent on the energy inside the serving loop;
+    each request's X equal alone and in the mix, its energy decreasing."""
+    from paper_1907_01005_amd import FP32_MFMA, FP64
+    from paper_1907_01005_amd.serving import GpuExecutor, Request, Server, summarize
+    say("serving om")
+    shapes = [((8, 8, 8), 2), ((8, 6, 6), 4), ((10, 8, 6), 2), ((8, 8, 4), 4)]
+    reqs = [Request(i, 0.002 * i, cells, deg, 16 + 5 * i, 3.0, FP64 if i % 2 == 0 else FP32_MFMA,
+                    4, 300 + i, "om") for i, (cells, deg) in enumerate(shapes)]
+    ex = GpuExecutor(planner_threads=2, keep_X=True)
+    budget = 2 * max(ex.footprint(ex._plan(r)) for r in reqs)
+    mix = Server(ex, byte_budget=budget, max_slots=3).run(reqs)
+    s = summarize(mix)
+    say(f"om mix: {s}")
+    assert s["requests_done"] == len(reqs) and mix.max_concurrent >= 2
+    for r in reqs:
+        res = mix.results[r.rid]
+        en = res["energies"]
+        say(f"om request {r.rid}: tau {res['tau']:.3e} energies {en}")
+        assert res["tau"] > 0 and all(b < a for a, b in zip(en, en[1:]))
+        # bounded: shifted by 2, the energy of M normalised columns stays O(M)
+        assert en[-1] > -20.0 * r.M
+        alone = Server(GpuExecutor(planner_threads=1, keep_X=True), byte_budget=budget,
+                       max_slots=1).run([Request(r.rid, 0.0, r.cells, r.degree, r.M, r.radius,
+                                                 r.prec, r.iters, r.seed, "om")])
+        err = rel_fro(res["X"], alone.results[r.rid]["X"])
+        say(f"om request {r.rid}: alone-vs-mix rel {err:.2e}")
+        assert err <= (1e-12 if r.prec == FP64 else 1e-5)

@@ -168,3 +168,22 @@ def test_gradient_central_difference_full_size():
     fd = (ev[0] - ev[1]) / (2 * h)
     say(f"full size: tr(G^T G) {gg:.6e}, central difference {fd:.6e}")
     assert abs(fd - gg) <= 1e-5 * gg
+
+
+def test_scale_columns():
+    import torch
+    from paper_1907_01005_amd import mv_scale_columns
+    wl = _small(2)
+    say("scale columns")
+    op = OracleProblem(wl, values="generic", value_seed=1)
+    dp = device_problem(wl)
+    dp.set_X_coo(op.node, op.orb, op.val)
+    X0 = dp.X.cpu().numpy()[:dp.nvalues].copy()
+    sc = np.random.default_rng(3).uniform(0.5, 2.0, wl.M)          # library column order
+    mv_scale_columns(dp.layout, torch.from_numpy(sc).cuda(), dp.X)
+    torch.cuda.synchronize()
+    node, orb = dp.layout.entry_coords()
+    pos = dp.layout.pattern()["col_perm"]
+    col_of_orb = np.empty(wl.M, dtype=np.int64)
+    col_of_orb[pos] = np.arange(wl.M)
+    assert np.array_equal(dp.X.cpu().numpy()[:dp.nvalues], X0 * sc[col_of_orb[orb]])
