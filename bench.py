@@ -156,6 +156,14 @@ def energy_form(dp, reps: int = 20):
         torch.cuda.synchronize()
         t = float(np.median([a.elapsed_time(b) for a, b in evs])) * 1e-3
         out[name] = {"ms": t * 1e3, "E": float(dp.E.cpu()[0])}
+        # one orbital-minimisation step: E, the gradient (two Alg. 7 products),
+        # tr(G^T G) and X <- X - tau G (tau = 0 keeps X for the next form)
+        for a, b in evs:
+            a.record()
+            dp.descent_step(0.0, prec)
+            b.record()
+        torch.cuda.synchronize()
+        out[name]["om_step_ms"] = float(np.median([a.elapsed_time(b) for a, b in evs]))
     out["closure_entries"] = dp.closure.nvalues
     out["x_entries"] = dp.nvalues
     out["rel_diff_E_fp32_vs_fp64"] = abs(out["fp32-mfma"]["E"] - out["fp64"]["E"]) / abs(out["fp64"]["E"])
@@ -194,16 +202,19 @@ def config4_forms():
     return out
 
 
-def serving_form(n: int, budget_mb: int):
+def serving_form(n: int, budget_mb: int, method: str = "rayleigh"):
     from paper_1907_01005_amd.serving import GpuExecutor, Server, request_stream, summarize
-    reqs = request_stream(n=n)
+    reqs = request_stream(n=n, method=method)
     ex = GpuExecutor(planner_threads=8)
     def progress(k, total):
         if k % 8 == 0 or k == total:
             print(f"[bench] serving: {k}/{total} requests done", file=sys.stderr, flush=True)
     rep = Server(ex, byte_budget=budget_mb << 20, max_slots=8).run(reqs, progress=progress)
     s = summarize(rep)
-    s.update({"requests": n, "rate_per_s": 40.0, "byte_budget_mb": budget_mb})
+    s.update({"requests": n, "rate_per_s": 40.0, "byte_budget_mb": budget_mb, "method": method})
+    if method == "om":
+        done = [r for r in rep.results.values() if "energies" in r]
+        s["om_energy_decreased"] = sum(1 for r in done if r["energies"][-1] < r["energies"][0])
     return s
 
 
@@ -282,6 +293,8 @@ def main(argv=None):
     ap.add_argument("--serve", type=int, default=0, metavar="N",
                     help="also run the serving stream with N requests")
     ap.add_argument("--serve-budget-mb", type=int, default=1024)
+    ap.add_argument("--serve-method", default="rayleigh", choices=["rayleigh", "om"],
+                    help="request iterations: Rayleigh-quotient steps or orbital minimisation")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args(argv)
@@ -374,7 +387,7 @@ def main(argv=None):
         out["config4"] = config4_forms()
     if args.serve:
         print(f"[bench] serving {args.serve} requests", file=sys.stderr, flush=True)
-        out["serving"] = serving_form(args.serve, args.serve_budget_mb)
+        out["serving"] = serving_form(args.serve, args.serve_budget_mb, args.serve_method)
     if args.copy_calibration:
         src = torch.ones(args.copy_calibration << 17, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
