@@ -584,6 +584,9 @@ int mfb_mmult(const mfb_mv* a, const mfb_mv* c, const double* d_A, const double*
   q.alpha = alpha;
   q.beta = beta;
   q.accumulate = accumulate ? 1 : 0;
+  q.max_rows = 0;
+  const auto& rb = c->mesh->plan.rb_start;
+  for (size_t r = 0; r + 1 < rb.size(); ++r) q.max_rows = std::max<int64_t>(q.max_rows, rb[r + 1] - rb[r]);
   const int rc = mfb::gpu::launch_mmult(q, stream);
   if (rc != 0) fail(MFB_EHIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)rc));
   return MFB_OK;

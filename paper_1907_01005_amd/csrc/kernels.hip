@@ -1239,29 +1239,71 @@ __global__ __launch_bounds__(1024) void energy_sum_kernel(int M, int ntiles,
 // -------------------------------------------------------------- Alg. 7
 // C = [C +] mask_c(A (alpha B + beta I)) with truncation: one workgroup per
 // stored block (i, j) of C sums A_{i,k} (alpha B_{k,j} + beta I_{k,j}) over the
-// stored blocks (i, k) of A's row block i, in a fixed order; entries of the
-// product outside C's blocks are never formed.  B is dense M x M row-major.
-__global__ __launch_bounds__(256) void mmult_kernel(MmultParams p) {
+// stored blocks (i, k) of A's row block i; entries of the product outside C's
+// blocks are never formed.  B is dense M x M row-major.  The rows of B that
+// the blocks of A select (columns of block j only) are staged in LDS in
+// chunks of at most KMAX rows; thread t owns output rows t, t + NT, ... and
+// keeps the (up to 16) entries of its row in registers, so every value of A
+// it loads serves the whole row.  Fixed summation order throughout.
+template <int NT, int KMAX>
+__global__ __launch_bounds__(NT) void mmult_kernel(MmultParams p) {
+  __shared__ double bs[KMAX][17];
   const int64_t q = blockIdx.x;
   const int i = p.c.blk_row[q];
   const int64_t dst = p.c.blk_off[q];
   const int wj = p.c.blk_w[q], cj0 = p.c.blk_col0[q];
-  const int64_t n = p.c.blk_off[q + 1] - dst;  // rows x wj
+  const int64_t rows = (p.c.blk_off[q + 1] - dst) / wj;
   const int64_t k0 = p.a.rowptr[i], k1 = p.a.rowptr[i + 1];
-  for (int64_t e = threadIdx.x; e < n; e += 256) {
-    const int64_t r = e / wj;
-    const int b = (int)(e - r * wj);
-    double s = 0.0;
-    for (int64_t kb = k0; kb < k1; ++kb) {
-      const int ck0 = p.a.blk_col0[kb], wk = p.a.blk_w[kb];
-      const double* __restrict__ arow = p.A + p.a.blk_off[kb] + r * wk;
-      const double* __restrict__ bcol = p.B + (int64_t)ck0 * p.M + cj0 + b;
-      double t = 0.0;
-      for (int x = 0; x < wk; ++x) t = __builtin_fma(arow[x], bcol[(int64_t)x * p.M], t);
-      s = __builtin_fma(p.alpha, t, s);
-      if (ck0 == cj0) s = __builtin_fma(p.beta, arow[b], s);
+  const int t = threadIdx.x;
+  for (int64_t r0 = 0; r0 < rows; r0 += NT) {
+    const int64_t r = r0 + t;
+    double acc[16];
+#pragma unroll
+    for (int b = 0; b < 16; ++b) acc[b] = 0.0;
+    // chunks of A's blocks whose widths sum to at most KMAX
+    for (int64_t kc = k0; kc < k1;) {
+      int64_t ke = kc;
+      int width = 0;
+      while (ke < k1 && width + p.a.blk_w[ke] <= KMAX) width += p.a.blk_w[ke++];
+      __syncthreads();  // the previous chunk is done with bs
+      {
+        int x0 = 0;
+        for (int64_t kb = kc; kb < ke; ++kb) {
+          const int ck0 = p.a.blk_col0[kb], wk = p.a.blk_w[kb];
+          for (int e = t; e < wk * 16; e += NT) {
+            const int x = e >> 4, b = e & 15;
+            double v = 0.0;
+            if (b < wj) {
+              v = p.alpha * p.B[(int64_t)(ck0 + x) * p.M + cj0 + b];
+              if (ck0 == cj0 && x == b) v += p.beta;  // the identity term
+            }
+            bs[x0 + x][b] = v;
+          }
+          x0 += wk;
+        }
+      }
+      __syncthreads();
+      if (r < rows) {
+        int x0 = 0;
+        for (int64_t kb = kc; kb < ke; ++kb) {
+          const int wk = p.a.blk_w[kb];
+          const double* __restrict__ arow = p.A + p.a.blk_off[kb] + r * wk;
+          for (int x = 0; x < wk; ++x) {
+            const double av = arow[x];
+#pragma unroll
+            for (int b = 0; b < 16; ++b) acc[b] = __builtin_fma(av, bs[x0 + x][b], acc[b]);
+          }
+          x0 += wk;
+        }
+      }
+      kc = ke;
     }
-    p.C[dst + e] = p.accumulate ? p.C[dst + e] + s : s;
+    if (r < rows) {
+      double* __restrict__ crow = p.C + dst + r * wj;
+#pragma unroll
+      for (int b = 0; b < 16; ++b)
+        if (b < wj) crow[b] = p.accumulate ? crow[b] + acc[b] : acc[b];
+    }
   }
 }
 
@@ -1400,8 +1442,13 @@ int launch_apply_op(const ApplyParams& p, int degree, int prec, int op, int64_t 
 
 int launch_mmult(const MmultParams& p, void* stream) {
   if (p.c.nblocks == 0) return 0;
-  hipLaunchKernelGGL(mmult_kernel, dim3((unsigned)p.c.nblocks), dim3(256), 0, (hipStream_t)stream,
-                     p);
+  // short row blocks (p = 2): 128 threads and half the LDS, more workgroups per CU
+  if (p.max_rows <= 128)
+    hipLaunchKernelGGL((mmult_kernel<128, 128>), dim3((unsigned)p.c.nblocks), dim3(128), 0,
+                       (hipStream_t)stream, p);
+  else
+    hipLaunchKernelGGL((mmult_kernel<256, 256>), dim3((unsigned)p.c.nblocks), dim3(256), 0,
+                       (hipStream_t)stream, p);
   return (int)hipGetLastError();
 }
 

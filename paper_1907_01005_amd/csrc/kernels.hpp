@@ -99,6 +99,7 @@ struct MmultParams {
   int32_t M;
   int32_t accumulate;
   double alpha, beta;
+  int64_t max_rows;         // largest row block of c (picks the kernel shape)
 };
 int launch_mmult(const MmultParams& p, void* stream);
 int launch_axpy(int64_t n, double alpha, const double* X, double* Y, void* stream);
