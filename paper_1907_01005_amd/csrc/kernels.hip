@@ -431,7 +431,7 @@ __device__ __forceinline__ Contractor<R, P, MF> make_ctr(const ApplyParams& a) {
   return c;
 }
 
-template <typename R, int P, bool MF = false, int OP = 0>
+template <typename R, int P, bool MF = false, int OP = 0, bool DEST = false>
 struct BatchProc {
   using D = Dims<P>;
   static constexpr int NT = 64 * D::n, UPI = 1;
@@ -472,8 +472,8 @@ struct BatchProc {
       xv[k] = ro[k] >= 0 ? a.X[(int64_t)ro[k] + ((t + k * NT) & 7)] : 0.0;
   }
   // Everything after the gather: returns without work when all values are 0.
-  // OP 0: Hamiltonian, 1: mass.  The sums go to the rows rowoff_out gives
-  // (the pattern of X, or its closure).
+  // OP 0: Hamiltonian, 1: mass.  The sums go to the rows of X's own pattern
+  // (rowoff), or with DEST to the rows rowoff_out gives (a closure).
   static __device__ __forceinline__ void compute(const ApplyParams& a, int64_t idx, int rank,
                                                  int t, const int32_t (&ro)[K],
                                                  const double (&xv)[K], Smem& sm) {
@@ -527,7 +527,7 @@ struct BatchProc {
 #pragma unroll
       for (int i = 0; i < n; ++i) unsafeAtomicAdd(&G[base + (i + NB * j) * 8], (double)out[i][j]);
     __syncthreads();
-    if (a.rowoff_out == a.rowoff) {
+    if constexpr (!DEST) {
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         if (ro[k] < 0) continue;
@@ -990,9 +990,9 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-template <typename R, int P, bool MF, int OP = 0>
+template <typename R, int P, bool MF, int OP = 0, bool DEST = false>
 __global__ __launch_bounds__(64 * (P + 1)) void apply_fused_kernel(ApplyParams a, int spw) {
-  using Proc = BatchProc<R, P, MF, OP>;
+  using Proc = BatchProc<R, P, MF, OP, DEST>;
   constexpr int NW = Proc::NT / 64;
   __shared__ typename Proc::Smem sm;
   __shared__ uint64_t s_hit[NW];
@@ -1154,8 +1154,11 @@ hipError_t launch_fused(const ApplyParams& p, int spw, hipStream_t st) {
   const int64_t G = (Proc::NT / 64) * spw;
   const int64_t po = (p.nitems + 7) >> 3, pg = ((p.nshell + G - 1) / G + 7) >> 3;
   if (po + pg == 0) return hipSuccess;
-  hipLaunchKernelGGL((apply_fused_kernel<R, P, MF, OP>), dim3((unsigned)(8 * (po + pg))),
-                     dim3(Proc::NT), 0, st, p, spw);
+  const dim3 grid((unsigned)(8 * (po + pg))), block(Proc::NT);
+  if (p.rowoff_out == p.rowoff)
+    hipLaunchKernelGGL((apply_fused_kernel<R, P, MF, OP, false>), grid, block, 0, st, p, spw);
+  else
+    hipLaunchKernelGGL((apply_fused_kernel<R, P, MF, OP, true>), grid, block, 0, st, p, spw);
   return hipGetLastError();
 }
 
