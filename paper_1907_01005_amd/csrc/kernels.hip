@@ -902,19 +902,21 @@ __global__ __launch_bounds__(256) void tm_stage2_kernel(TmParams p) {
   const int g = t / E, e = t - g * E;
   double sum = 0.0;
   if (g < G) {
-    // the pair's n partial products lie back to back: part[base + k E + e]
+    // the pair's n partial products lie back to back: part[base + k E + e];
+    // thread group g takes k = g, g + G, ...: up to 16 loads are issued
+    // before the first add, then summed in order (fixed order overall)
     const int n = d.n;
     const double* __restrict__ src = p.part + d.base + e;
-    int k = g;
-    double s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    for (; k + 3 * G < n; k += 4 * G) {
-      sum += src[(int64_t)k * E];
-      s1 += src[(int64_t)(k + G) * E];
-      s2 += src[(int64_t)(k + 2 * G) * E];
-      s3 += src[(int64_t)(k + 3 * G) * E];
+    for (int k0 = g; k0 < n; k0 += 16 * G) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int k = k0 + u * G;
+        v[u] = k < n ? src[(int64_t)k * E] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) sum += v[u];
     }
-    for (; k < n; k += G) sum += src[(int64_t)k * E];
-    sum = (sum + s1) + (s2 + s3);
   }
   red[t] = sum;
   __syncthreads();
