@@ -247,6 +247,9 @@ int mfb_apply_H(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X, doubl
  * of C is not stored) in a second kernel.  kernel 6: persistent workgroups
  * of the batch mapping walking a static strided list, with the loads of the
  * next items issued before the current item is computed (no workspace).
+ * kernel 7 (p = 2; at p = 4 the same as kernel 0): persistent workgroups of
+ * p + 1 compute waves and one loader wave that gathers the next item into a
+ * second LDS stage while the current one is computed (no workspace).
  * grid: for kernels 0 and 2, the shell items checked per wave (a power of
  * two up to 64; 0 = 2); for the persistent kernels, the
  * number of workgroups (0 = as many as fit on the device); else unused.  d_work: the workspace (info.work_bytes);

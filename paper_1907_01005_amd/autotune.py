@@ -22,7 +22,8 @@ from typing import Dict, List, Optional
 from . import api
 
 KERNEL_NAMES = {0: "default-grid", 1: "default-queue", 2: "batch-grid", 3: "batch-queue",
-                4: "wave-grid", 5: "wave-queue", 6: "batch-pipelined"}
+                4: "wave-grid", 5: "wave-queue", 6: "batch-pipelined",
+                7: "loader-pipelined"}
 
 
 @dataclass(frozen=True)
@@ -54,10 +55,12 @@ def layout_signature(dp, prec: int) -> str:
 
 def candidates(cu_count: int) -> List[tuple]:
     # kernel 0: own and shell items in one grid, grid = shell items checked
-    # per wave; 4: one wave per unit; 6 and odd: persistent (grid = workgroups)
+    # per wave; 4: one wave per unit; 6, 7 and odd: persistent (grid = workgroups)
     out = [(0, spw) for spw in (0, 1, 4, 8)] + [(4, 0)]
     for per_cu in (0, 1, 2, 3):
         out.append((6, per_cu * cu_count))
+    for per_cu in (0, 2, 3):
+        out.append((7, per_cu * cu_count))
     for k in (1, 3, 5):
         for per_cu in (0, 1, 2, 4):
             out.append((k, per_cu * cu_count))

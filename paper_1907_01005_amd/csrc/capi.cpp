@@ -477,12 +477,12 @@ int mfb_apply_H_tuned(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X,
   check_apply_args(mesh, mv, d_X, d_Y);
   if (!tune) fail(MFB_EINVAL, "null tune");
   if (tune->prec < 0 || tune->prec > 3) fail(MFB_EINVAL, "unknown precision");
-  if (tune->kernel < 0 || tune->kernel > 6) fail(MFB_EINVAL, "kernel must be in 0..6");
+  if (tune->kernel < 0 || tune->kernel > 7) fail(MFB_EINVAL, "kernel must be in 0..7");
   if (tune->grid < 0) fail(MFB_EINVAL, "negative grid");
   if ((tune->kernel == 0 || tune->kernel == 2) &&
       (tune->grid > 64 || (tune->grid & (tune->grid - 1)) != 0))
     fail(MFB_EINVAL, "kernels 0 and 2 take grid = 0 or a power of two up to 64");
-  if ((tune->kernel & 1) && tune->kernel != 6 && !d_work)
+  if ((tune->kernel & 1) && tune->kernel != 7 && !d_work)
     fail(MFB_EINVAL, "the queue kernels need the workspace");
   mfb::gpu::ApplyParams a;
   fill_apply_params(mesh, mv, d_X, d_Y, a);

@@ -30,6 +30,10 @@ int device_cu_count();
 namespace {
 
 // -------------------------------------------------------------- helpers
+// Fused multiply-add in the contraction type (float operands stay float).
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // out[o0][o1] = sum_k M(o_AX, k) in[...k...]; M(o,k) = M[o*n+k], or M[k*n+o]
 // when TR (the transposed matrix).  AX = index of `in` that is contracted.
 template <int n, int AX, bool TR, typename R>
@@ -45,7 +49,7 @@ __device__ __forceinline__ void contract(const R* __restrict__ M, const R (&in)[
       for (int k = 0; k < n; ++k) {
         const R c = TR ? M[k * n + o] : M[o * n + k];
         const R x = AX == 0 ? in[k][o1] : in[o0][k];
-        s = __builtin_fma(c, x, s);
+        s = fma_r(c, x, s);
       }
       out[o0][o1] = s;
     }
@@ -64,7 +68,7 @@ __device__ __forceinline__ void contract_add(const R* __restrict__ M, const R (&
       for (int k = 0; k < n; ++k) {
         const R c = TR ? M[k * n + o] : M[o * n + k];
         const R x = AX == 0 ? in[k][o1] : in[o0][k];
-        s = __builtin_fma(c, x, s);
+        s = fma_r(c, x, s);
       }
       acc[o0][o1] = s;
     }
@@ -602,7 +606,7 @@ __device__ __forceinline__ void sweep(R (&u)[n * n * n], const R* __restrict__ M
     for (int o = 0; o < n; ++o) {
       R s = 0;
 #pragma unroll
-      for (int k = 0; k < n; ++k) s = __builtin_fma(TR ? M[k * n + o] : M[o * n + k], u[base + k * S], s);
+      for (int k = 0; k < n; ++k) s = fma_r(TR ? M[k * n + o] : M[o * n + k], u[base + k * S], s);
       tmp[o] = s;
     }
 #pragma unroll
@@ -623,14 +627,14 @@ __device__ __forceinline__ void grad_pass(const R (&uq)[n * n * n], R (&w)[n * n
     for (int o = 0; o < n; ++o) {
       R s = 0;
 #pragma unroll
-      for (int k = 0; k < n; ++k) s = __builtin_fma(Dm[o * n + k], uq[base + k * S], s);
+      for (int k = 0; k < n; ++k) s = fma_r(Dm[o * n + k], uq[base + k * S], s);
       gq[o] = (R)((double)s * wg[base + o * S]);
     }
 #pragma unroll
     for (int o = 0; o < n; ++o) {
       R s = w[base + o * S];
 #pragma unroll
-      for (int k = 0; k < n; ++k) s = __builtin_fma(Dm[k * n + o], gq[k], s);
+      for (int k = 0; k < n; ++k) s = fma_r(Dm[k * n + o], gq[k], s);
       w[base + o * S] = s;
     }
   }
@@ -1058,6 +1062,258 @@ __global__ __launch_bounds__(64 * (P + 1)) void apply_fused_kernel(ApplyParams a
   }
 }
 
+// Loader-wave pipeline (p = 2).  A workgroup holds p + 1 compute waves (one
+// per plane, as in BatchProc) and one loader wave.  It walks a strided list
+// of the own items of its XCD's contiguous range, then those of its shell
+// items that hold a non-zero value (the compute waves check them while the
+// loader stages the first item).  While the compute waves work on item k out
+// of one LDS stage, the loader gathers item k + 1 into the other (values,
+// destination row offsets, JxW V of the cells) and already holds the row
+// offsets of item k + 2, so the compute waves never wait on global memory.
+// The loader passes the same barriers as the compute waves: the operator's
+// own (7 for H, 3 for M), the one before the flush and the one that ends
+// the item.
+template <int P>
+struct Stage {
+  using D = Dims<P>;
+  double G[D::NB3 * 8];  // gathered values [node][column], then the node sums
+  double cv[8 * D::n3];  // JxW V of the batch's eight cells
+  int32_t ro[D::NB3];    // destination row offset of each node at the item's first column, or -1
+  int32_t nc, nz;
+};
+
+template <typename R, int P, bool MF, int OP, bool DEST>
+struct LoaderPipe {
+  using D = Dims<P>;
+  static constexpr int n = D::n, n3 = D::n3, NB = D::NB, NB3 = D::NB3;
+  static constexpr int NWC = n;                    // compute waves
+  static constexpr int NTC = 64 * NWC, NT = NTC + 64;
+  static constexpr int NV = NB3 * 8;
+  static constexpr int KV = (NV + 63) / 64;        // values per loader lane
+  static constexpr int KC = (8 * n3 + 63) / 64;    // JxW V entries per loader lane
+  static constexpr int KR = (NB3 + 63) / 64;       // destination row offsets per loader lane
+  static constexpr int KS = (NV + NTC - 1) / NTC;  // node sums per compute thread
+  static constexpr int kOpBarriers = OP == 0 ? 7 : 3;
+  static constexpr int kListMax = 256;
+  struct Smem {
+    Stage<P> st[2];
+    R T[64 * n3];
+    double wg[4 * n3];  // the mesh's gradient scales and JxW (the same for every cell)
+    int32_t list[kListMax];
+    int32_t nlist;
+  };
+  // Row offsets of every value slot of item idx and its record (lane 4m + f
+  // holds field f: rank, c0, nc, ld).
+  struct Ahead {
+    int32_t rv[KV];
+    int32_t meta;
+  };
+  struct Vals {
+    double v[KV];
+    double cv[KC];
+    int32_t ro[KR];
+    int nc;
+  };
+  static __device__ __forceinline__ void rows(const ApplyParams& a, int64_t idx, int l, Ahead& h) {
+    const int32_t* __restrict__ r = a.rowoff + idx * NB3;
+#pragma unroll
+    for (int q = 0; q < KV; ++q) {
+      const int e = l + 64 * q;
+      h.rv[q] = e < NV ? r[e >> 3] : -1;
+    }
+    h.meta = reinterpret_cast<const int32_t*>(a.items + idx)[l & 3];
+  }
+  static __device__ __forceinline__ void issue(const ApplyParams& a, int64_t idx, int l,
+                                               const Ahead& h, Vals& s) {
+    s.nc = __builtin_amdgcn_readlane(h.meta, 2);
+    const int rank = __builtin_amdgcn_readlane(h.meta, 0);
+#pragma unroll
+    for (int q = 0; q < KV; ++q) {
+      const int col = (l + 64 * q) & 7;
+      s.v[q] = (h.rv[q] >= 0 && col < s.nc) ? a.X[(int64_t)h.rv[q] + col] : 0.0;
+    }
+    const double* __restrict__ cvp = a.cV + (int64_t)rank * 8 * n3;
+#pragma unroll
+    for (int j = 0; j < KC; ++j) {
+      const int e = l + 64 * j;
+      s.cv[j] = e < 8 * n3 ? cvp[e] : 0.0;
+    }
+    const int32_t* __restrict__ r2 = (DEST ? a.rowoff_out : a.rowoff) + idx * NB3;
+#pragma unroll
+    for (int j = 0; j < KR; ++j) {
+      const int e = l + 64 * j;
+      s.ro[j] = e < NB3 ? r2[e] : -1;
+    }
+  }
+  // Writes the staged item; returns (wave-uniform) whether any value is non-zero.
+  static __device__ __forceinline__ bool store(Stage<P>& st, int l, const Vals& s) {
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < KV; ++q) {
+      const int e = l + 64 * q;
+      if (e < NV) st.G[e] = s.v[q];
+      any |= (s.v[q] != 0.0);
+    }
+#pragma unroll
+    for (int j = 0; j < KC; ++j) {
+      const int e = l + 64 * j;
+      if (e < 8 * n3) st.cv[e] = s.cv[j];
+    }
+#pragma unroll
+    for (int j = 0; j < KR; ++j) {
+      const int e = l + 64 * j;
+      if (e < NB3) st.ro[e] = s.ro[j];
+    }
+    const bool nz = __ballot(any) != 0;
+    if (l == 0) {
+      st.nc = s.nc;
+      st.nz = nz ? 1 : 0;
+    }
+    return nz;
+  }
+  // One staged item on the compute waves (thread t < NTC).
+  static __device__ __forceinline__ void compute(const ApplyParams& a, Stage<P>& cur, R* T,
+                                                 const double* wg, int t, int pl) {
+    const int c = t & 7, e = (t >> 3) & 7;
+    const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
+    double* __restrict__ G = cur.G;
+    R u[n][n];
+    const int base = ((ex * P) + NB * ((ey * P) + NB * (ez * P + pl))) * 8 + c;
+#pragma unroll
+    for (int j = 0; j < n; ++j)
+#pragma unroll
+      for (int i = 0; i < n; ++i) u[i][j] = (R)G[base + (i + NB * j) * 8];
+    auto zero_sums = [&]() {
+#pragma unroll
+      for (int k = 0; k < KS; ++k)
+        if (t + k * NTC < NV) G[t + k * NTC] = 0.0;
+    };
+    R out[n][n];
+    if constexpr (OP == 0)
+      plane_operator<R, P>(make_ctr<R, P, MF>(a), T + (t & 63) * n3, pl, cur.cv + e * n3, wg,
+                           true, u, out, zero_sums);
+    else
+      plane_mass<R, P>(make_ctr<R, P, MF>(a), T + (t & 63) * n3, pl, wg + 3 * n3, true, u, out,
+                       zero_sums);
+#pragma unroll
+    for (int j = 0; j < n; ++j)
+#pragma unroll
+      for (int i = 0; i < n; ++i) unsafeAtomicAdd(&G[base + (i + NB * j) * 8], (double)out[i][j]);
+    __syncthreads();
+    // all LDS reads of the flush first, then the atomics
+    const int nc = cur.nc;
+    int32_t o[KS];
+    double v[KS];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const int e2 = t + k * NTC;
+      o[k] = e2 < NV ? cur.ro[e2 >> 3] : -1;
+      v[k] = e2 < NV ? G[e2] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const int e2 = t + k * NTC;
+      if (o[k] >= 0 && (e2 & 7) < nc) unsafeAtomicAdd(a.Y + (int64_t)o[k] + (e2 & 7), v[k]);
+    }
+  }
+};
+
+// Two stages, the tiles and the scales take 35 KB of LDS at p = 2: four
+// workgroups per CU, which leaves each wave up to 128 VGPRs.
+template <typename R, int P, bool MF, int OP, bool DEST>
+__global__ __launch_bounds__(64 * (P + 2)) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void apply_ws_kernel(ApplyParams a) {
+  using L = LoaderPipe<R, P, MF, OP, DEST>;
+  __shared__ typename L::Smem sm;
+  const int64_t W = gridDim.x >> 3;
+  const int x = blockIdx.x & 7;
+  const int64_t w = blockIdx.x >> 3;
+  const int t = threadIdx.x;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+  const bool loader = wv == L::NWC;
+  const int l = t & 63;
+  const int64_t po = (a.nitems + 7) >> 3, ps = (a.nshell + 7) >> 3;
+  const int64_t o0 = x * po + w, o1 = min(a.nitems, (x + 1) * po);
+  const int64_t s0 = x * ps + w, s1 = min(a.nshell, (x + 1) * ps);
+  const int n_own = o0 < o1 ? (int)((o1 - o0 + W - 1) / W) : 0;
+  const int n_sh = s0 < s1 ? (int)((s1 - s0 + W - 1) / W) : 0;
+  if (n_own + n_sh == 0) return;
+  if (t == 0) sm.nlist = 0;
+  for (int i = t; i < 4 * L::n3; i += L::NT) sm.wg[i] = a.Wg[i];
+  __syncthreads();
+  // item k of this workgroup's sequence
+  auto seq = [&](int k) -> int64_t {
+    if (k < n_own) return o0 + (int64_t)k * W;
+    return a.nitems + __builtin_amdgcn_readfirstlane(sm.list[k - n_own]);
+  };
+  // The loader and the compute waves run separate loops (their registers are
+  // not live in each other's) with the same barrier sequence.
+  if (loader) {
+    typename L::Ahead h;
+    typename L::Vals s;
+    bool nz_cur = false;
+    if (n_own > 0) {
+      L::rows(a, seq(0), l, h);
+      L::issue(a, seq(0), l, h, s);
+      if (n_own > 1) L::rows(a, seq(1), l, h);
+      nz_cur = L::store(sm.st[0], l, s);
+    }
+    __syncthreads();
+    const int nk = n_own + min(__builtin_amdgcn_readfirstlane(sm.nlist), L::kListMax);
+    if (nk == 0) return;
+    if (n_own == 0) {
+      L::rows(a, seq(0), l, h);
+      L::issue(a, seq(0), l, h, s);
+      if (nk > 1) L::rows(a, seq(1), l, h);
+      nz_cur = L::store(sm.st[0], l, s);
+      __syncthreads();
+    } else if (n_own == 1 && nk > 1) {
+      L::rows(a, seq(1), l, h);
+    }
+    for (int k = 0; k < nk; ++k) {
+      const bool more = k + 1 < nk;
+      if (more) {
+        L::issue(a, seq(k + 1), l, h, s);
+        if (k + 2 < nk) L::rows(a, seq(k + 2), l, h);
+      }
+      if (nz_cur)
+        for (int b = 0; b < L::kOpBarriers + 1; ++b) __syncthreads();
+      if (more) nz_cur = L::store(sm.st[(k + 1) & 1], l, s);
+      __syncthreads();
+    }
+  } else {
+    // shell checks: 16 lanes per shell item, non-zero ones appended to the list
+    constexpr int LPI = 16, IPP = L::NTC / LPI;
+    for (int jb = 0; jb < n_sh; jb += IPP) {
+      const int j = jb + t / LPI;
+      bool any = false;
+      if (j < n_sh) {
+        const int64_t k = s0 + (int64_t)j * W;
+        const int nc = a.items[a.nitems + k].nc;
+        const int32_t e1 = a.shell_ptr[k + 1];
+        for (int32_t e = a.shell_ptr[k] + (t % LPI); e < e1; e += LPI) {
+          const double* __restrict__ xp = a.X + (int64_t)a.shell_ro[e];
+          for (int c = 0; c < nc; ++c) any |= (xp[c] != 0.0);
+        }
+      }
+      const uint64_t b = __ballot(any);
+      if ((l % LPI) == 0 && ((b >> l) & 0xFFFFull) != 0) {
+        const int pos = atomicAdd(&sm.nlist, 1);
+        if (pos < L::kListMax) sm.list[pos] = (int32_t)(s0 + (int64_t)j * W);
+      }
+    }
+    __syncthreads();
+    const int nk = n_own + min(__builtin_amdgcn_readfirstlane(sm.nlist), L::kListMax);
+    if (nk == 0) return;
+    if (n_own == 0) __syncthreads();
+    for (int k = 0; k < nk; ++k) {
+      Stage<P>& cur = sm.st[k & 1];
+      if (__builtin_amdgcn_readfirstlane(cur.nz)) L::compute(a, cur, sm.T, sm.wg, t, wv);
+      __syncthreads();
+    }
+  }
+}
+
 // Software-pipelined persistent form of BatchProc.  Workgroup w of XCD x
 // walks a strided list of the own items of x's contiguous range, then of
 // its shell items.  Before computing item j it issues the value loads of
@@ -1164,9 +1420,43 @@ hipError_t launch_fused(const ApplyParams& p, int spw, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Loader-wave pipeline at p = 2 (grid = total workgroups, 0 = as many as are
+// resident); the fused grid at p = 4, where two fp64 stages and the tiles do
+// not fit a CU's LDS.
+template <typename R, int P, bool MF, int OP>
+hipError_t launch_ws(const ApplyParams& p, int grid, hipStream_t st) {
+  if constexpr (P != 2) {
+    return launch_fused<R, P, MF, OP>(p, 0, st);
+  } else {
+    if (p.nitems + p.nshell == 0) return hipSuccess;
+    const bool dest = p.rowoff_out != p.rowoff;
+    const void* fn = dest ? reinterpret_cast<const void*>(&apply_ws_kernel<R, P, MF, OP, true>)
+                          : reinterpret_cast<const void*>(&apply_ws_kernel<R, P, MF, OP, false>);
+    constexpr int NT = 64 * (P + 2);
+    if (grid <= 0) {
+      int per_cu = 0;
+      hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NT, 0);
+      if (e != hipSuccess) return e;
+      grid = std::max(1, per_cu) * std::max(1, device_cu_count());
+    }
+    const int64_t po = (p.nitems + 7) >> 3, ps = (p.nshell + 7) >> 3;
+    constexpr int64_t LM = LoaderPipe<R, P, MF, OP, false>::kListMax;
+    int64_t W = std::max<int64_t>(1, grid / 8);
+    W = std::min<int64_t>(W, std::max<int64_t>(1, std::max(po, ps)));
+    W = std::max<int64_t>(W, (ps + LM - 1) / LM);  // every workgroup's shell list fits
+    const dim3 g((unsigned)(8 * W)), b(NT);
+    if (dest)
+      hipLaunchKernelGGL((apply_ws_kernel<R, P, MF, OP, true>), g, b, 0, st, p);
+    else
+      hipLaunchKernelGGL((apply_ws_kernel<R, P, MF, OP, false>), g, b, 0, st, p);
+    return hipGetLastError();
+  }
+}
+
 template <typename R, int P, bool MF = false>
 hipError_t launch_apply_t(const ApplyParams& p, int kernel, hipStream_t st) {
   if (kernel == 6) return launch_pipe<R, P, MF>(p, st);
+  if (kernel == 7) return launch_ws<R, P, MF, 0>(p, p.grid, st);
   const bool queue = (kernel & 1) != 0;
   // processor: kernels 0/1 the default for the degree, 2/3 the batch
   // processor, 4/5 the single-wave processor (RegProc for p = 2, CellProc

@@ -81,7 +81,7 @@ def test_generic_values_ragged_blocks(degree):
     dp.set_X_coo(op.node, op.orb, op.val)
     for prec, tol in ((0, TOL64), (3, TOL32), (2, TOL32)):
         _check_full(wl, op, dp, prec, tol)
-    for kernel in range(1, 7):
+    for kernel in range(1, 8):
         _check_full(wl, op, dp, 0, TOL64, tuned=kernel)
         _check_full(wl, op, dp, 2, TOL32, tuned=kernel)
     for spw in (1, 4, 64):
@@ -190,7 +190,7 @@ def test_repeat_determinism_and_queue_kernel():
     Y2, S2, _ = _run(dp, 0)
     scale = np.abs(Y1).max()
     assert np.abs(Y1 - Y2).max() <= 1e-14 * scale
-    for kernel in range(1, 7):
+    for kernel in range(1, 8):
         Y3, S3, _ = _run(dp, 0, tuned=kernel)
         assert np.abs(Y1 - Y3).max() <= 1e-14 * scale, kernel
     # the overlap reduction has a fixed order: bitwise repeatable for equal inputs
