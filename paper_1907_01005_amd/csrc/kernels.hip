@@ -1721,12 +1721,14 @@ int launch_apply_op(const ApplyParams& p, int degree, int prec, int op, int64_t 
   }
   hipError_t e;
   const bool q2 = degree == 2;
+  // p = 2: the loader-wave pipeline (about 5% faster on closure destinations);
+  // p = 4 and the fp32 VALU form: the fused grid
   if (prec == 0)
-    e = op == 0 ? (q2 ? launch_fused<double, 2, false, 0>(p, 0, st) : launch_fused<double, 4, false, 0>(p, 0, st))
-                : (q2 ? launch_fused<double, 2, false, 1>(p, 0, st) : launch_fused<double, 4, false, 1>(p, 0, st));
+    e = op == 0 ? (q2 ? launch_ws<double, 2, false, 0>(p, 0, st) : launch_fused<double, 4, false, 0>(p, 0, st))
+                : (q2 ? launch_ws<double, 2, false, 1>(p, 0, st) : launch_fused<double, 4, false, 1>(p, 0, st));
   else if (prec == 2)
-    e = op == 0 ? (q2 ? launch_fused<float, 2, true, 0>(p, 0, st) : launch_fused<float, 4, true, 0>(p, 0, st))
-                : (q2 ? launch_fused<float, 2, true, 1>(p, 0, st) : launch_fused<float, 4, true, 1>(p, 0, st));
+    e = op == 0 ? (q2 ? launch_ws<float, 2, true, 0>(p, 0, st) : launch_fused<float, 4, true, 0>(p, 0, st))
+                : (q2 ? launch_ws<float, 2, true, 1>(p, 0, st) : launch_fused<float, 4, true, 1>(p, 0, st));
   else if (prec == 3)
     e = op == 0 ? (q2 ? launch_fused<float, 2, false, 0>(p, 0, st) : launch_fused<float, 4, false, 0>(p, 0, st))
                 : (q2 ? launch_fused<float, 2, false, 1>(p, 0, st) : launch_fused<float, 4, false, 1>(p, 0, st));
