@@ -93,7 +93,7 @@ typedef enum {
 
 /* Box [0,Lx]x[0,Ly]x[0,Lz] split into nx x ny x nz equal Q_p cells.
  * nx, ny, nz must be even (cells are grouped in 2x2x2 batches, the coarse
- * level of Alg. 1).  degree p in {2, 4} (else MFB_EUNSUPPORTED).
+ * level of Alg. 1).  degree p in 1..4 (else MFB_EUNSUPPORTED).
  * dirichlet_faces: bit 2d = face x_d = 0, bit 2d+1 = face x_d = L_d.
  * order: 0 = batches along the Hilbert curve (Alg. 1 step 2), 1 = batches
  * in lexicographic order (x fastest).                                      */

@@ -440,9 +440,9 @@ struct BatchProc {
   using D = Dims<P>;
   static constexpr int NT = 64 * D::n, UPI = 1;
   static constexpr int NV = D::NB3 * 8, K = (NV + NT - 1) / NT;
-  // p = 4: the gather/sum buffer shares the storage of the transpose tiles
-  // (three more barriers, half the LDS); p = 2: separate buffers.
-  static constexpr bool ALIAS = P >= 4;
+  // p >= 3: the gather/sum buffer shares the storage of the transpose tiles
+  // (three more barriers, about half the LDS); p <= 2: separate buffers.
+  static constexpr bool ALIAS = P >= 3;
   struct SepBuf {
     R T[64 * D::n3];
     double G[NV];
@@ -1695,17 +1695,25 @@ int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
   }
+  // one instantiation per degree and precision form
+  auto by_degree = [&](auto form) -> hipError_t {
+    switch (degree) {
+      case 1: return form(std::integral_constant<int, 1>());
+      case 2: return form(std::integral_constant<int, 2>());
+      case 3: return form(std::integral_constant<int, 3>());
+      case 4: return form(std::integral_constant<int, 4>());
+      default: return hipErrorInvalidValue;
+    }
+  };
   hipError_t e;
-  if (prec == 0) {
-    e = degree == 2 ? launch_apply_t<double, 2>(p, kernel, st) : launch_apply_t<double, 4>(p, kernel, st);
-  } else if (prec == 3) {
-    e = degree == 2 ? launch_apply_t<float, 2>(p, kernel, st) : launch_apply_t<float, 4>(p, kernel, st);
-  } else if (prec == 2) {
-    e = degree == 2 ? launch_apply_t<float, 2, true>(p, kernel, st)
-                    : launch_apply_t<float, 4, true>(p, kernel, st);
-  } else {
+  if (prec == 0)
+    e = by_degree([&](auto d) { return launch_apply_t<double, decltype(d)::value>(p, kernel, st); });
+  else if (prec == 3)
+    e = by_degree([&](auto d) { return launch_apply_t<float, decltype(d)::value>(p, kernel, st); });
+  else if (prec == 2)
+    e = by_degree([&](auto d) { return launch_apply_t<float, decltype(d)::value, true>(p, kernel, st); });
+  else
     return -2;
-  }
   return (int)e;
 }
 
@@ -1719,19 +1727,34 @@ int launch_apply_op(const ApplyParams& p, int degree, int prec, int op, int64_t 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
   }
+  // p = 2: the loader-wave pipeline (about 5% faster on closure destinations;
+  // launch_ws runs the fused grid at other degrees); the fp32 VALU form: the
+  // fused grid
+  auto by_degree = [&](auto form) -> hipError_t {
+    switch (degree) {
+      case 1: return form(std::integral_constant<int, 1>());
+      case 2: return form(std::integral_constant<int, 2>());
+      case 3: return form(std::integral_constant<int, 3>());
+      case 4: return form(std::integral_constant<int, 4>());
+      default: return hipErrorInvalidValue;
+    }
+  };
   hipError_t e;
-  const bool q2 = degree == 2;
-  // p = 2: the loader-wave pipeline (about 5% faster on closure destinations);
-  // p = 4 and the fp32 VALU form: the fused grid
   if (prec == 0)
-    e = op == 0 ? (q2 ? launch_ws<double, 2, false, 0>(p, 0, st) : launch_fused<double, 4, false, 0>(p, 0, st))
-                : (q2 ? launch_ws<double, 2, false, 1>(p, 0, st) : launch_fused<double, 4, false, 1>(p, 0, st));
+    e = by_degree([&](auto d) {
+      constexpr int P = decltype(d)::value;
+      return op == 0 ? launch_ws<double, P, false, 0>(p, 0, st) : launch_ws<double, P, false, 1>(p, 0, st);
+    });
   else if (prec == 2)
-    e = op == 0 ? (q2 ? launch_ws<float, 2, true, 0>(p, 0, st) : launch_fused<float, 4, true, 0>(p, 0, st))
-                : (q2 ? launch_ws<float, 2, true, 1>(p, 0, st) : launch_fused<float, 4, true, 1>(p, 0, st));
+    e = by_degree([&](auto d) {
+      constexpr int P = decltype(d)::value;
+      return op == 0 ? launch_ws<float, P, true, 0>(p, 0, st) : launch_ws<float, P, true, 1>(p, 0, st);
+    });
   else if (prec == 3)
-    e = op == 0 ? (q2 ? launch_fused<float, 2, false, 0>(p, 0, st) : launch_fused<float, 4, false, 0>(p, 0, st))
-                : (q2 ? launch_fused<float, 2, false, 1>(p, 0, st) : launch_fused<float, 4, false, 1>(p, 0, st));
+    e = by_degree([&](auto d) {
+      constexpr int P = decltype(d)::value;
+      return op == 0 ? launch_fused<float, P, false, 0>(p, 0, st) : launch_fused<float, P, false, 1>(p, 0, st);
+    });
   else
     return -2;
   return (int)e;

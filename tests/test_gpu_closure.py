@@ -78,7 +78,7 @@ def test_config1_closure_energy():
         _check(wl, op, dp, prec, tol)
 
 
-@pytest.mark.parametrize("degree", [2, 4])
+@pytest.mark.parametrize("degree", [1, 2, 3, 4])
 def test_closure_generic_values_ragged_blocks(degree):
     wl = _small(degree)
     say(f"closure generic Q{degree}")
@@ -89,7 +89,7 @@ def test_closure_generic_values_ragged_blocks(degree):
     _check(wl, op, dp, 2, TOL32)
 
 
-@pytest.mark.parametrize("degree", [2, 4])
+@pytest.mark.parametrize("degree", [1, 2, 3, 4])
 def test_mass_on_the_pattern_of_x(degree):
     """mfb_apply_op with y = x: M X and H X kept on X's own pattern, as
     mfb_apply_H keeps H X."""

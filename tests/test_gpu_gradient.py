@@ -37,7 +37,7 @@ def _values_dense(layout, values, N, M):
     return D
 
 
-@pytest.mark.parametrize("degree", [2, 4])
+@pytest.mark.parametrize("degree", [1, 2, 3, 4])
 def test_mmult_truncation_against_oracle(degree):
     import torch
     from paper_1907_01005_amd import mmult
@@ -100,7 +100,7 @@ def test_gradient_config1():
     _check_gradient(wl, op, dp, 2, 1e-5)
 
 
-@pytest.mark.parametrize("degree", [2, 4])
+@pytest.mark.parametrize("degree", [1, 2, 3, 4])
 def test_gradient_generic_ragged(degree):
     wl = _small(degree)
     say(f"gradient generic Q{degree}")

@@ -71,7 +71,7 @@ def test_config1_full(prec, tol):
     _check_full(wl, op, dp, prec, tol)
 
 
-@pytest.mark.parametrize("degree", [2, 4])
+@pytest.mark.parametrize("degree", [1, 2, 3, 4])
 def test_generic_values_ragged_blocks(degree):
     """Values at every stored entry (shell items do work) and ragged column blocks."""
     wl = _small((8, 6, 4), degree, 29, 2.2, 11, sizes=[8, 5, 12, 4])
@@ -88,7 +88,7 @@ def test_generic_values_ragged_blocks(degree):
         _check_full(wl, op, dp, 0, TOL64, tuned=(0, spw))
 
 
-@pytest.mark.parametrize("degree", [2, 4])
+@pytest.mark.parametrize("degree", [1, 2, 3, 4])
 def test_few_nonzero_shell_items(degree):
     """Orbital values plus a few values at stored entries off the supports:
     only some shell items of a checked group hold non-zeros."""
@@ -125,7 +125,7 @@ def test_natural_bc_lexicographic_free_faces():
     _check_full(wl, op, dp, 0, TOL64)
 
 
-@pytest.mark.parametrize("degree", [2, 4])
+@pytest.mark.parametrize("degree", [1, 2, 3, 4])
 def test_closed_form_through_library(degree):
     """V = 1, natural BCs, full support: S = X^T H X hits closed-form integrals."""
     from oracle.fe1d import gll_nodes
