@@ -26,19 +26,29 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from .element import hamiltonian_matrices, laplace_matrix, mass_matrix, potential_matrices
+from .element import (curved_matrices, hamiltonian_matrices, laplace_matrix, mass_matrix,
+                      potential_matrices)
 from .mesh import BoxMesh
 from .pattern import Pattern
 
 
+def _cell_nodes(mesh: BoxMesh, cells: np.ndarray) -> np.ndarray:
+    """(c, n^3, 3) node positions of the listed cells (curved meshes)."""
+    return np.asarray(mesh.nodes)[mesh.cell_dofs()[cells]]
+
+
 def element_masses(mesh: BoxMesh, cells: np.ndarray) -> np.ndarray:
     """M_K for the listed cells (the same on every cell of a uniform box)."""
+    if mesh.curved:
+        return curved_matrices(mesh.p, _cell_nodes(mesh, cells), which="M")
     Mk = mass_matrix(mesh.p, mesh.h)
     return np.broadcast_to(Mk, (len(cells),) + Mk.shape)
 
 
 def element_hamiltonians(mesh: BoxMesh, v_qp: np.ndarray, cells: np.ndarray) -> np.ndarray:
     """H_K for the listed cells (indices into the lexicographic cell order)."""
+    if mesh.curved:
+        return curved_matrices(mesh.p, _cell_nodes(mesh, cells), np.asarray(v_qp)[cells], "H")
     return hamiltonian_matrices(mesh.p, mesh.h, np.asarray(v_qp)[cells])
 
 
@@ -111,7 +121,11 @@ def assemble(mesh: BoxMesh, v_qp: np.ndarray | None = None, which: str = "H") ->
     N = mesh.ndofs
     dofs = mesh.cell_dofs()
     A = np.zeros((N, N))
-    if which == "H":
+    if mesh.curved:
+        allc = np.arange(mesh.ncells)
+        Ke = curved_matrices(mesh.p, _cell_nodes(mesh, allc),
+                             None if v_qp is None else np.asarray(v_qp), which)
+    elif which == "H":
         Ke = hamiltonian_matrices(mesh.p, mesh.h, v_qp)
     elif which == "K":
         Ke = np.broadcast_to(laplace_matrix(mesh.p, mesh.h), (mesh.ncells,) + (dofs.shape[1],) * 2)

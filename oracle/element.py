@@ -14,6 +14,10 @@ is assembled here as a plain sum over quadrature points -- no sum
 factorisation -- so that it can be checked against the paper by eye:
 
     H_K = 1/2 sum_d G_d^T diag(JxW) G_d + N^T diag(JxW * V) N
+
+On a curved cell (isoparametric map x(xi) = sum_k x_k N_k(xi)), the Jacobian
+J_ab(q) = dx_a/dxi_b = sum_k x_k,a dN_k/dxi_b (xi_q), the physical gradient is
+grad N_i = J^{-T} grad_xi N_i and JxW_q = w_q |det J(q)|, per cell.
 """
 
 from __future__ import annotations
@@ -70,3 +74,39 @@ def hamiltonian_matrices(p: int, h, v_qp: np.ndarray, nq: int | None = None) -> 
     """H_K = K_K + M_K[V] for every cell (eq. fe_matrices)."""
     K = laplace_matrix(p, h, nq)
     return K[None, :, :] + potential_matrices(p, h, v_qp, nq)
+
+
+def curved_tables(p: int, xcell: np.ndarray, nq: int | None = None):
+    """Per cell of an isoparametric mesh: values N[q,i], physical gradients
+    G[c,q,a,i] = (J^{-T} grad_xi N_i)_a and JxW[c,q] = w_q |det J|.
+
+    ``xcell`` (c, n^3, 3): the cells' node positions in local order.
+    """
+    xq, wq, S, D = basis_tables(p, nq)
+    N = np.kron(S, np.kron(S, S))
+    # reference gradients d/dxi_1, d/dxi_2, d/dxi_3 on [0,1]^3
+    Gr = np.stack([np.kron(S, np.kron(S, D)), np.kron(S, np.kron(D, S)), np.kron(D, np.kron(S, S))])
+    J = np.einsum("bqk,cka->cqab", Gr, np.asarray(xcell, dtype=np.float64))
+    det = np.linalg.det(J)
+    Jinv = np.linalg.inv(J)
+    G = np.einsum("cqba,bqi->cqai", Jinv, Gr)         # J^{-T} grad_xi N_i
+    W = np.kron(wq, np.kron(wq, wq))
+    JxW = W[None, :] * np.abs(det)
+    return N, G, JxW
+
+
+def curved_matrices(p: int, xcell: np.ndarray, v_qp: np.ndarray | None = None,
+                    which: str = "H", nq: int | None = None) -> np.ndarray:
+    """Element matrices of curved cells, plain sums over quadrature points:
+    "K" = 1/2 sum_q JxW grad N_i . grad N_j, "M" = sum_q JxW N_i N_j,
+    "V" = sum_q JxW V N_i N_j, "H" = K + V."""
+    N, G, JxW = curved_tables(p, xcell, nq)
+    out = 0.0
+    if which in ("K", "H"):
+        out = out + 0.5 * np.einsum("cqai,cq,cqaj->cij", G, JxW, G)
+    if which in ("V", "H"):
+        c = JxW * np.asarray(v_qp, dtype=np.float64)
+        out = out + np.einsum("qi,cq,qj->cij", N, c, N)
+    if which == "M":
+        out = np.einsum("qi,cq,qj->cij", N, JxW, N)
+    return out

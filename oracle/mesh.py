@@ -10,6 +10,13 @@ Homogeneous Dirichlet conditions (the H^1_0 space of Sec. 3.1) are imposed on
 the faces selected by a bit mask (bit 2d: x_d = 0, bit 2d+1: x_d = L_d): the
 nodes there remain rows of the multivector, but the operator is restricted to
 the other nodes, i.e. X is read as 0 and Y is 0 on them.
+
+Curved cells (the general hexahedral meshes of Sec. 3.1): when ``nodes``
+holds a physical position for every global node, each cell is the image of
+the reference cube under the isoparametric map x(xi) = sum_k x_k N_k(xi) of
+its own node positions, so cells may be rotated, sheared or curved.  The
+node numbering, the faces and the box [0, L] stay those of the index grid,
+which also defines batches, supports and the column order.
 """
 
 from __future__ import annotations
@@ -29,6 +36,11 @@ class BoxMesh:
     L: tuple
     p: int
     dirichlet: int = 0x3F
+    nodes: np.ndarray | None = None  # (N, 3) physical node positions (curved cells), or None
+
+    @property
+    def curved(self) -> bool:
+        return self.nodes is not None
 
     @property
     def n(self):
@@ -81,6 +93,8 @@ class BoxMesh:
 
     def node_points(self) -> np.ndarray:
         """(N, 3) physical node positions (GLL nodes inside each cell)."""
+        if self.nodes is not None:
+            return np.asarray(self.nodes, dtype=np.float64)
         xi = gll_nodes(self.p)
         pos = []
         for d in range(3):
@@ -97,6 +111,14 @@ class BoxMesh:
         """(ncells, nq^3, 3) physical quadrature points, q = q1 + nq q2 + nq^2 q3."""
         cc = self.cell_coords() if cells is None else np.asarray(cells).reshape(-1, 3)
         m = self.n if nq is None else nq
+        if self.nodes is not None:
+            # x(xi_q) = sum_k x_k N_k(xi_q) over the cell's own nodes
+            from .fe1d import basis_tables
+            _, _, S, _ = basis_tables(self.p, m)
+            N = np.kron(S, np.kron(S, S))                 # (m^3, n^3)
+            lin = cc[:, 0] + self.nx * (cc[:, 1] + self.ny * cc[:, 2])
+            xc = np.asarray(self.nodes)[self.cell_dofs()[lin]]   # (c, n^3, 3)
+            return np.einsum("qk,cka->cqa", N, xc)
         xq, _ = gauss_rule(m)
         k3, j3, i3 = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")
         h = self.h

@@ -426,3 +426,73 @@ def test_mmult_truncation_brute_force():
         for j in range(9):
             ref = sum(A[i, k] * B[k, j] for k in range(9)) if mask[i, j] else 0.0
             assert abs(C[i, j] - ref) <= 1e-12 * (1 + abs(ref))
+
+
+# ---------------------------------------------------------------- curved cells
+# Cells given by node positions (isoparametric map).  None of these checks
+# restates the element formula: the identity map must reproduce the box
+# path, a rigid motion must keep the spectrum (a J^{-1} / J^{-T} mix-up
+# changes it by about 15%), an affine shear must keep volumes and kill
+# linear functions exactly, and a boundary-preserving interior deformation
+# must keep the order-2p convergence of the 1D-box eigenvalues.
+def _with_nodes(m, x):
+    return BoxMesh(m.nx, m.ny, m.nz, m.L, m.p, m.dirichlet, nodes=x)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_curved_path_on_the_identity_map_equals_box_path(p):
+    m = BoxMesh(2, 3, 2, (1.0, 2.0, 0.5), p, 0)
+    mc = _with_nodes(m, m.node_points())
+    v = np.random.default_rng(2).random((m.ncells, (p + 1) ** 3))
+    for which in ("K", "M", "H"):
+        a, b = oapply.assemble(m, v, which), oapply.assemble(mc, v, which)
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max(), which
+    assert np.abs(m.qp_points() - mc.qp_points()).max() <= 1e-14
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_rigid_motion_keeps_the_box_spectrum(p):
+    m = BoxMesh(3, 2, 2, (1.0, 1.6, 0.7), p, 0x3F)
+    Q, _ = np.linalg.qr(np.random.default_rng(3).standard_normal((3, 3)))
+    mr = _with_nodes(m, m.node_points() @ Q.T + np.array([0.3, -1.0, 2.0]))
+    a, b = _first_eigs(m, 6), _first_eigs(mr, 6)
+    assert np.abs(a - b).max() <= 1e-10 * a.max()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_affine_shear_keeps_volume_and_kills_linears(p):
+    A = np.array([[1.0, 0.3, 0.1], [0.0, 1.0, 0.2], [0.0, 0.0, 1.0]]) * np.array([1.0, 1.0, 1.3])
+    m = BoxMesh(2, 3, 2, (1.0, 2.0, 0.5), p, 0)
+    ms = _with_nodes(m, m.node_points() @ A.T)
+    one = np.ones(ms.ndofs)
+    vol = one @ oapply.assemble(ms, which="M") @ one
+    assert abs(vol - np.linalg.det(A) * 1.0 * 2.0 * 0.5) <= 1e-13
+    K = oapply.assemble(ms, which="K")
+    assert np.abs(K @ one).max() < 1e-12
+    nc = ms.node_coords()
+    interior = np.all((nc > 0) & (nc < np.array(ms.nodes_per_axis) - 1), axis=1)
+    x = ms.node_points()
+    r = K @ (2 * x[:, 0] - x[:, 1] + 3 * x[:, 2] + 1)
+    assert np.abs(r[interior]).max() < 1e-12
+    assert np.abs(r[~interior]).max() > 1e-6
+
+
+@pytest.mark.parametrize("p,ns,rate", [(1, (4, 8, 16), 2.0), (2, (8, 16, 32), 4.0),
+                                       (3, (4, 8, 16), 6.0)])
+def test_curved_1d_box_eigenvalues_converge_at_2p(p, ns, rate):
+    """Dirichlet at x=0 and x=L: the cells are bent along x (x + a sin(2 pi x / L))
+    and the cross-section sheared; the domain and the eigenfunctions sin(k pi x / L)
+    are unchanged, so lambda_k = pi^2 k^2 / (2 L^2) still holds."""
+    L = 1.5
+    errs = []
+    for nx in ns:
+        m = BoxMesh(nx, 1, 1, (L, 0.7, 0.4), p, dirichlet=0b11)
+        x = m.node_points().copy()
+        x[:, 0] += 0.02 * L * np.sin(2 * np.pi * x[:, 0] / L)
+        x[:, 1] += 0.1 * x[:, 2]
+        lam = _first_eigs(_with_nodes(m, x), 2)
+        exact = np.pi ** 2 * np.array([1, 4]) / (2 * L ** 2)
+        errs.append(np.abs(lam - exact) / exact)
+    errs = np.array(errs)
+    obs = np.log2(errs[:-1, 0] / errs[1:, 0])
+    assert np.all(np.abs(obs - rate) < 0.6), obs
