@@ -113,7 +113,8 @@ def build_problem(cfg: int, mesh_index: int = 0, radius: float = 0.0):
         wl = dataclasses.replace(wl, radius=float(radius), name=f"{wl.name}-r{radius:g}")
     ms = wl.meshes[mesh_index]
     dp = DeviceProblem((ms.nx, ms.ny, ms.nz), ms.L, ms.degree, ms.dirichlet, wl.centres,
-                       wl.radius, wl.colblock_sizes, lambda P: synth.potential_at(wl, P))
+                       wl.radius, wl.colblock_sizes, lambda P: synth.potential_at(wl, P),
+                       node_map=ms.bend_points if ms.bend else None)
     node, orb, val = synth.orbital_values(wl, mesh_index)
     dp.set_X_coo(node, orb, val)
     return wl, dp

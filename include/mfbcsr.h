@@ -127,8 +127,29 @@ int mfb_mesh_get_info(const mfb_mesh* mesh, mfb_mesh_info* out);
  * ijk: host array of ncells*3 int32.                                         */
 int mfb_mesh_cells(const mfb_mesh* mesh, int32_t* ijk);
 
-/* Physical quadrature points x_q = x_K + h (.) xi_q of every cell, library
- * cell order, q = q1 + n q2 + n^2 q3: host array [ncells][(p+1)^3][3].       */
+/* Node positions, host array [ndofs][3] in global lexicographic node order
+ * (x fastest): the GLL points of every box cell, or the positions given to
+ * mfb_mesh_set_nodes.                                                        */
+int mfb_mesh_node_points(const mfb_mesh* mesh, double* xyz);
+
+/* Curved cells (Sec. 3.1: general hexahedral meshes).  xyz: host array
+ * [ndofs][3] of node positions in global lexicographic node order (x fastest
+ * over the index grid of the box).  Each cell becomes the image of the
+ * reference cube under the isoparametric Q_p map of its own nodes; the
+ * library tabulates, per cell and quadrature point, 1/2 JxW J^{-1} J^{-T}
+ * and JxW (JxW = w_q |det J|), and the Hamiltonian and mass operators use
+ * them.  Batches, row blocks, supports and the column order stay those of
+ * the index grid (the box of the descriptor).  The device layout grows by
+ * 56 (p+1)^3 bytes per cell: query mfb_mesh_get_info (meta_bytes) afterwards.
+ * Must be called before mfb_mesh_set_potential (ESTATE otherwise).
+ * Errors: EINVAL (null, non-finite positions, a singular Jacobian), ESTATE.
+ * On curved cells mfb_apply_H_tuned takes the fused kernels (0, 2, 7) only
+ * (EUNSUPPORTED otherwise).                                                  */
+int mfb_mesh_set_nodes(mfb_mesh* mesh, const double* xyz);
+
+/* Physical quadrature points of every cell, library cell order, q = q1 +
+ * n q2 + n^2 q3: host array [ncells][(p+1)^3][3].  On a box x_q = x_K + h (.)
+ * xi_q; on curved cells the image of xi_q under the cell's map.              */
 int mfb_mesh_qp_points(const mfb_mesh* mesh, double* xyz);
 
 /* Potential values V(x_q) at those points (host array [ncells][(p+1)^3]).

@@ -23,6 +23,10 @@ class OracleProblem:
         ms = wl.meshes[mesh_index]
         self.wl = wl
         self.mesh = BoxMesh(ms.nx, ms.ny, ms.nz, tuple(ms.L), ms.degree, ms.dirichlet)
+        if getattr(ms, "bend", 0.0):
+            # curved cells: the seeded map applied to this oracle's own box nodes
+            self.mesh = BoxMesh(ms.nx, ms.ny, ms.nz, tuple(ms.L), ms.degree, ms.dirichlet,
+                                nodes=ms.bend_points(self.mesh.node_points()))
         qp = self.mesh.qp_points()
         self.v_qp = synth.potential_at(wl, qp.reshape(-1, 3)).reshape(qp.shape[:2])
         self.pattern = build_pattern(self.mesh, wl.centres, wl.radius, wl.colblock_sizes,

@@ -76,6 +76,8 @@ SIGNATURES = {
     "mfb_mesh_cells": (C.c_int, [VP, PI32]),
     "mfb_mesh_qp_points": (C.c_int, [VP, PD]),
     "mfb_mesh_set_potential": (C.c_int, [VP, PD]),
+    "mfb_mesh_set_nodes": (C.c_int, [VP, PD]),
+    "mfb_mesh_node_points": (C.c_int, [VP, PD]),
     "mfb_mesh_bind": (C.c_int, [VP, VP, VP]),
     "mfb_destroy_mesh": (None, [VP]),
     "mfb_create_bcsr_multivector": (C.c_int, [VP, C.POINTER(MvDesc), C.POINTER(VP)]),

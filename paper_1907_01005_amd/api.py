@@ -54,6 +54,7 @@ class Mesh:
         self.cells_shape = (nx, ny, nz)
         self.L = tuple(float(x) for x in L)
         self.dirichlet = dirichlet
+        self.curved = False
         self._meta = None
 
     @property
@@ -69,6 +70,22 @@ class Mesh:
         out = np.empty((self.ncells, self.qp_per_cell, 3), dtype=np.float64)
         check(lib().mfb_mesh_qp_points(self._h, _ptr(out, C.c_double)))
         return out
+
+    def node_points(self) -> np.ndarray:
+        """mfb_mesh_node_points: node positions [ndofs][3]."""
+        out = np.empty((self.ndofs, 3), dtype=np.float64)
+        check(lib().mfb_mesh_node_points(self._h, _ptr(out, C.c_double)))
+        return out
+
+    def set_nodes(self, xyz: np.ndarray) -> None:
+        """mfb_mesh_set_nodes: curved cells from node positions [ndofs][3]
+        (global lexicographic order); before set_potential."""
+        x = np.ascontiguousarray(xyz, dtype=np.float64).reshape(self.ndofs, 3)
+        check(lib().mfb_mesh_set_nodes(self._h, _ptr(x, C.c_double)))
+        info = N.MeshInfo()
+        check(lib().mfb_mesh_get_info(self._h, C.byref(info)))
+        self.meta_bytes = info.meta_bytes
+        self.curved = True
 
     def set_potential(self, v_qp: np.ndarray) -> None:
         v = np.ascontiguousarray(v_qp, dtype=np.float64).reshape(self.ncells, self.qp_per_cell)

@@ -20,7 +20,7 @@ thread_local std::string g_err;
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct MeshLayout {
-  size_t off_gtab = 0, off_cv = 0, off_wg = 0, bytes = 0;
+  size_t off_gtab = 0, off_cv = 0, off_wg = 0, off_cg = 0, off_cj = 0, bytes = 0;
 };
 
 MeshLayout mesh_layout(const mfb::MeshPlan& m) {
@@ -30,6 +30,11 @@ MeshLayout mesh_layout(const mfb::MeshPlan& m) {
   L.off_cv = align256(sizeof(int32_t) * nb3 * m.nbatch);
   L.off_wg = align256(L.off_cv + sizeof(double) * (size_t)m.ncells * n3);
   L.bytes = align256(L.off_wg + sizeof(double) * 4 * n3);
+  if (m.curved) {  // the metric (six planes) and JxW of every cell
+    L.off_cg = L.bytes;
+    L.off_cj = align256(L.off_cg + sizeof(double) * (size_t)m.ncells * 6 * n3);
+    L.bytes = align256(L.off_cj + sizeof(double) * (size_t)m.ncells * n3);
+  }
   return L;
 }
 
@@ -201,6 +206,27 @@ int mfb_mesh_qp_points(const mfb_mesh* mesh, double* xyz) {
   MFB_CATCH
 }
 
+int mfb_mesh_node_points(const mfb_mesh* mesh, double* xyz) {
+  MFB_TRY
+  if (!mesh || !xyz) fail(MFB_EINVAL, "null argument");
+  mfb::mesh_node_points(mesh->plan, xyz);
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_mesh_set_nodes(mfb_mesh* mesh, const double* xyz) {
+  MFB_TRY
+  if (!mesh || !xyz) fail(MFB_EINVAL, "null argument");
+  if (mesh->plan.has_potential) fail(MFB_ESTATE, "set the node positions before the potential");
+  for (int64_t i = 0; i < 3 * mesh->plan.N; ++i)
+    if (!std::isfinite(xyz[i])) fail(MFB_EINVAL, "node positions must be finite");
+  mfb::mesh_set_nodes(mesh->plan, xyz);
+  mesh->lay = mesh_layout(mesh->plan);
+  mesh->bound = false;
+  return MFB_OK;
+  MFB_CATCH
+}
+
 int mfb_mesh_set_potential(mfb_mesh* mesh, const double* v_qp) {
   MFB_TRY
   if (!mesh || !v_qp) fail(MFB_EINVAL, "null argument");
@@ -221,6 +247,10 @@ int mfb_mesh_bind(mfb_mesh* mesh, void* d_meta, void* stream) {
   std::memcpy(host.data() + mesh->lay.off_cv, m.cV.data(), sizeof(double) * m.cV.size());
   const std::vector<double> wg = grad_scales(m);
   std::memcpy(host.data() + mesh->lay.off_wg, wg.data(), sizeof(double) * wg.size());
+  if (m.curved) {
+    std::memcpy(host.data() + mesh->lay.off_cg, m.cG.data(), sizeof(double) * m.cG.size());
+    std::memcpy(host.data() + mesh->lay.off_cj, m.cJ.data(), sizeof(double) * m.cJ.size());
+  }
   hipStream_t st = (hipStream_t)stream;
   check_hip(hipMemcpyAsync(d_meta, host.data(), host.size(), hipMemcpyHostToDevice, st),
             "hipMemcpyAsync(mesh metadata)");
@@ -439,6 +469,8 @@ static void fill_apply_params(const mfb_mesh* mesh, const mfb_mv* mv, const doub
   a.Wg = (const double*)(gb + mesh->lay.off_wg);
   a.jxw = a.Wg + 3 * m.n * m.n * m.n;
   a.rowoff_out = a.rowoff;
+  a.cG = m.curved ? (const double*)(gb + mesh->lay.off_cg) : nullptr;
+  a.cJ = m.curved ? (const double*)(gb + mesh->lay.off_cj) : nullptr;
   const int n = m.n;
   for (int i = 0; i < n * n; ++i) {
     a.S[i] = b.S[i];
@@ -482,6 +514,8 @@ int mfb_apply_H_tuned(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X,
   if ((tune->kernel == 0 || tune->kernel == 2) &&
       (tune->grid > 64 || (tune->grid & (tune->grid - 1)) != 0))
     fail(MFB_EINVAL, "kernels 0 and 2 take grid = 0 or a power of two up to 64");
+  if (mesh->plan.curved && tune->kernel != 0 && tune->kernel != 2 && tune->kernel != 7)
+    fail(MFB_EUNSUPPORTED, "curved cells run the fused kernels only (0, 2 and 7)");
   if ((tune->kernel & 1) && tune->kernel != 7 && !d_work)
     fail(MFB_EINVAL, "the queue kernels need the workspace");
   mfb::gpu::ApplyParams a;

@@ -325,6 +325,99 @@ __device__ __forceinline__ void plane_operator(const Ctr& ctr, R* __restrict__ T
   ctr.template c<0, true, 0>(B, out);
 }
 
+// The operator on curved cells.  The metric c(q) = 1/2 JxW_q J^{-1} J^{-T}
+// (six planes per cell: 00, 11, 22, 01, 02, 12) couples the three reference
+// gradients at every quadrature point, so they must meet there.  D_y
+// commutes with S_z and S_x: the y-derivative is taken in layout A before the
+// z-interpolation and crosses to layout B with the values (tiles T1, T2);
+// there the gradients are combined with the metric, and the y-part crosses
+// back beside the rest:
+//   g   = (D_x u_q, S_z D_y S_y S_x u, D_z u_q),   g' = c g,
+//   w   = c_V (.) u_q + D_x^T g'_x + D_z^T g'_z,
+//   out = S_x^T S_y^T (S_z^T w + D_y^T S_z^T g'_y).
+// With a diagonal metric this is the box operator (plane_operator) taken in
+// another order: three barriers, fourteen 1D contractions.
+template <typename R, int P, class Ctr, class Hook>
+__device__ __forceinline__ void plane_operator_geo(const Ctr& ctr, R* __restrict__ T1,
+                                                   R* __restrict__ T2, int pl,
+                                                   const double* __restrict__ cv,
+                                                   const double* __restrict__ cg,
+                                                   const R (&u)[P + 1][P + 1],
+                                                   R (&out)[P + 1][P + 1],
+                                                   Hook after_first_barrier) {
+  using D = Dims<P>;
+  constexpr int n = D::n, n2 = D::n2, n3 = D::n3;
+  R A[n][n], B[n][n];
+  // layout A (z = pl): interpolate along x and y, differentiate along y
+  ctr.template c<0, false, 0>(u, A);
+  ctr.template c<1, false, 0>(A, B);
+  ctr.template c<1, false, 1>(B, A);
+#pragma unroll
+  for (int j = 0; j < n; ++j)
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      T1[i + n * j + n2 * pl] = B[i][j];
+      T2[i + n * j + n2 * pl] = A[i][j];
+    }
+  __syncthreads();
+  after_first_barrier();
+  // layout B (y = pl): interpolate along z, the metric, back along z
+  R X1[n][n], X2[n][n];
+#pragma unroll
+  for (int k = 0; k < n; ++k)
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      X1[i][k] = T1[i + n * pl + n2 * k];
+      X2[i][k] = T2[i + n * pl + n2 * k];
+    }
+  R uq[n][n], gz[n][n], w[n][n];
+  ctr.template c<1, false, 0>(X1, uq);
+  ctr.template c<1, false, 0>(X2, B);   // y-derivative at the quadrature points
+  ctr.template c<0, false, 1>(uq, A);   // x-derivative
+  ctr.template c<1, false, 1>(uq, gz);  // z-derivative
+#pragma unroll
+  for (int i = 0; i < n; ++i)
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+      const int q = i + n * pl + n2 * k;
+      const double gx0 = (double)A[i][k], gy0 = (double)B[i][k], gz0 = (double)gz[i][k];
+      const double c00 = cg[q], c11 = cg[n3 + q], c22 = cg[2 * n3 + q];
+      const double c01 = cg[3 * n3 + q], c02 = cg[4 * n3 + q], c12 = cg[5 * n3 + q];
+      A[i][k] = (R)(c00 * gx0 + c01 * gy0 + c02 * gz0);
+      B[i][k] = (R)(c01 * gx0 + c11 * gy0 + c12 * gz0);
+      gz[i][k] = (R)(c02 * gx0 + c12 * gy0 + c22 * gz0);
+    }
+  ctr.template c<0, true, 1>(A, w);
+  ctr.template ca<1, true, 1>(gz, w);
+#pragma unroll
+  for (int i = 0; i < n; ++i)
+#pragma unroll
+    for (int k = 0; k < n; ++k)
+      w[i][k] = (R)((double)w[i][k] + cv[i + n * pl + n2 * k] * (double)uq[i][k]);
+  ctr.template c<1, true, 0>(w, X1);
+  ctr.template c<1, true, 0>(B, X2);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < n; ++k)
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      T1[i + n * pl + n2 * k] = X1[i][k];
+      T2[i + n * pl + n2 * k] = X2[i][k];
+    }
+  __syncthreads();
+  // layout A (z = pl): the y-derivative part, back along y, then x
+#pragma unroll
+  for (int j = 0; j < n; ++j)
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      X1[i][j] = T1[i + n * j + n2 * pl];
+      X2[i][j] = T2[i + n * j + n2 * pl];
+    }
+  ctr.template ca<1, true, 1>(X2, X1);
+  ctr.template c<1, true, 0>(X1, A);
+  ctr.template c<0, true, 0>(A, out);
+}
+
 // Mass operator on planes (eq. fe_matrices, the N_i N_j term): interpolate
 // to the quadrature points, scale by JxW (float64), integrate back; the same
 // layouts and calling convention as plane_operator, two layout switches.
@@ -435,25 +528,33 @@ __device__ __forceinline__ Contractor<R, P, MF> make_ctr(const ApplyParams& a) {
   return c;
 }
 
-template <typename R, int P, bool MF = false, int OP = 0, bool DEST = false>
+template <typename R, int P, bool MF = false, int OP = 0, bool DEST = false, bool GEO = false>
 struct BatchProc {
   using D = Dims<P>;
   static constexpr int NT = 64 * D::n, UPI = 1;
   static constexpr int NV = D::NB3 * 8, K = (NV + NT - 1) / NT;
-  // p >= 3: the gather/sum buffer shares the storage of the transpose tiles
+  // p >= 3: the gather/sum buffer shares the storage of a transpose tile
   // (three more barriers, about half the LDS); p <= 2: separate buffers.
+  // Curved cells (GEO) with the Hamiltonian take a second tile.
   static constexpr bool ALIAS = P >= 3;
-  struct SepBuf {
-    R T[64 * D::n3];
-    double G[NV];
-  };
-  union AliasBuf {
-    R T[64 * D::n3];
-    double G[NV];
-  };
+  static constexpr bool TWO = GEO && OP == 0;
+  static constexpr size_t kT = sizeof(R) * 64 * D::n3, kG = sizeof(double) * NV;
+  static constexpr size_t kShared = kT > kG ? kT : kG;
+  // byte offsets: [T][T2][G] separate, [T][T2 | G] or [T | G] aliased
+  static constexpr size_t kOffT2 = kT;
+  static constexpr size_t kOffG = ALIAS ? (TWO ? kT : 0) : (TWO ? 2 * kT : kT);
+  static constexpr size_t kBytes =
+      ALIAS ? (TWO ? kT + kShared : kShared) : (TWO ? 2 * kT + kG : kT + kG);
   struct Smem {
-    typename std::conditional<ALIAS, AliasBuf, SepBuf>::type b;
+    alignas(16) unsigned char raw[kBytes];
   };
+  static __device__ __forceinline__ R* tile(Smem& sm) { return reinterpret_cast<R*>(sm.raw); }
+  static __device__ __forceinline__ R* tile2(Smem& sm) {
+    return reinterpret_cast<R*>(sm.raw + kOffT2);
+  }
+  static __device__ __forceinline__ double* gbuf(Smem& sm) {
+    return reinterpret_cast<double*>(sm.raw + kOffG);
+  }
   // The row offsets are read independently of the item record (they already
   // hold the chunk's first column); the column count only masks them.
   static __device__ __forceinline__ void load(const ApplyParams& a, int64_t idx, int t,
@@ -485,7 +586,7 @@ struct BatchProc {
     const int c = t & 7, e = (t >> 3) & 7;
     const int pl = __builtin_amdgcn_readfirstlane(t >> 6);
     const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
-    double* __restrict__ G = sm.b.G;
+    double* __restrict__ G = gbuf(sm);
     R* __restrict__ Gr = reinterpret_cast<R*>(G);
     bool any = false;
 #pragma unroll
@@ -506,15 +607,20 @@ struct BatchProc {
         if (t + k * NT < NV) G[t + k * NT] = 0.0;
     };
     R out[n][n];
-    const double* cv = a.cV + ((int64_t)rank * 8 + e) * D::n3;
+    const int64_t cell = (int64_t)rank * 8 + e;
+    const double* cv = a.cV + cell * D::n3;
     const double* wg = a.Wg;
+    R* __restrict__ Tc = tile(sm) + (t & 63) * D::n3;
     auto op = [&](auto hook) {
-      if constexpr (OP == 0)
-        plane_operator<R, P>(make_ctr<R, P, MF>(a), sm.b.T + (t & 63) * D::n3, pl, cv, wg, true,
-                             u, out, hook);
+      if constexpr (GEO && OP == 0)
+        plane_operator_geo<R, P>(make_ctr<R, P, MF>(a), Tc, tile2(sm) + (t & 63) * D::n3, pl, cv,
+                                 a.cG + cell * 6 * D::n3, u, out, hook);
+      else if constexpr (OP == 0)
+        plane_operator<R, P>(make_ctr<R, P, MF>(a), Tc, pl, cv, wg, true, u, out, hook);
+      else if constexpr (GEO)
+        plane_mass<R, P>(make_ctr<R, P, MF>(a), Tc, pl, a.cJ + cell * D::n3, true, u, out, hook);
       else
-        plane_mass<R, P>(make_ctr<R, P, MF>(a), sm.b.T + (t & 63) * D::n3, pl, a.jxw, true, u,
-                         out, hook);
+        plane_mass<R, P>(make_ctr<R, P, MF>(a), Tc, pl, a.jxw, true, u, out, hook);
     };
     if constexpr (ALIAS) {
       __syncthreads();
@@ -996,9 +1102,9 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-template <typename R, int P, bool MF, int OP = 0, bool DEST = false>
+template <typename R, int P, bool MF, int OP = 0, bool DEST = false, bool GEO = false>
 __global__ __launch_bounds__(64 * (P + 1)) void apply_fused_kernel(ApplyParams a, int spw) {
-  using Proc = BatchProc<R, P, MF, OP, DEST>;
+  using Proc = BatchProc<R, P, MF, OP, DEST, GEO>;
   constexpr int NW = Proc::NT / 64;
   __shared__ typename Proc::Smem sm;
   __shared__ uint64_t s_hit[NW];
@@ -1413,10 +1519,17 @@ hipError_t launch_fused(const ApplyParams& p, int spw, hipStream_t st) {
   const int64_t po = (p.nitems + 7) >> 3, pg = ((p.nshell + G - 1) / G + 7) >> 3;
   if (po + pg == 0) return hipSuccess;
   const dim3 grid((unsigned)(8 * (po + pg))), block(Proc::NT);
-  if (p.rowoff_out == p.rowoff)
+  const bool dest = p.rowoff_out != p.rowoff;
+  if (p.cG) {
+    if (!dest)
+      hipLaunchKernelGGL((apply_fused_kernel<R, P, MF, OP, false, true>), grid, block, 0, st, p, spw);
+    else
+      hipLaunchKernelGGL((apply_fused_kernel<R, P, MF, OP, true, true>), grid, block, 0, st, p, spw);
+  } else if (!dest) {
     hipLaunchKernelGGL((apply_fused_kernel<R, P, MF, OP, false>), grid, block, 0, st, p, spw);
-  else
+  } else {
     hipLaunchKernelGGL((apply_fused_kernel<R, P, MF, OP, true>), grid, block, 0, st, p, spw);
+  }
   return hipGetLastError();
 }
 
@@ -1428,6 +1541,7 @@ hipError_t launch_ws(const ApplyParams& p, int grid, hipStream_t st) {
   if constexpr (P != 2) {
     return launch_fused<R, P, MF, OP>(p, 0, st);
   } else {
+    if (p.cG) return launch_fused<R, P, MF, OP>(p, 0, st);  // curved cells: the fused grid
     if (p.nitems + p.nshell == 0) return hipSuccess;
     const bool dest = p.rowoff_out != p.rowoff;
     const void* fn = dest ? reinterpret_cast<const void*>(&apply_ws_kernel<R, P, MF, OP, true>)
@@ -1455,6 +1569,8 @@ hipError_t launch_ws(const ApplyParams& p, int grid, hipStream_t st) {
 
 template <typename R, int P, bool MF = false>
 hipError_t launch_apply_t(const ApplyParams& p, int kernel, hipStream_t st) {
+  // curved cells: the fused grid only (kernel 7 runs it too)
+  if (p.cG && kernel != 0 && kernel != 2 && kernel != 7) return hipErrorNotSupported;
   if (kernel == 6) return launch_pipe<R, P, MF>(p, st);
   if (kernel == 7) return launch_ws<R, P, MF, 0>(p, p.grid, st);
   const bool queue = (kernel & 1) != 0;

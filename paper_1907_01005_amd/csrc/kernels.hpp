@@ -32,6 +32,11 @@ struct ApplyParams {
   const double* Wg;      // [3][ (p+1)^3 ]: 1/2 JxW_q / h_d^2 per direction d
   const double* jxw;     // [ (p+1)^3 ]: JxW_q (mass operator)
   const int32_t* rowoff_out;  // destination offsets per item and node (rowoff, or a closure's)
+  // curved cells only (else null): per cell 8 rank + e, the metric
+  // 1/2 JxW J^{-1} J^{-T} as six planes [00, 11, 22, 01, 02, 12][ (p+1)^3 ]
+  // and JxW [ (p+1)^3 ]
+  const double* cG;
+  const double* cJ;
 };
 
 struct TmParams {

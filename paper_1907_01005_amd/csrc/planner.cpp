@@ -271,10 +271,131 @@ void mesh_cells(const MeshPlan& m, int32_t* ijk) {
   }
 }
 
+namespace {
+// Global node ids of cell (cx, cy, cz) in local order i + n j + n^2 k.
+void cell_node_ids(const MeshPlan& m, const int32_t* ijk, int64_t* ids) {
+  const int n = m.n, p = m.p;
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i)
+        ids[i + n * (j + n * k)] =
+            m.node_id((int64_t)p * ijk[0] + i, (int64_t)p * ijk[1] + j, (int64_t)p * ijk[2] + k);
+}
+}  // namespace
+
+void mesh_node_points(const MeshPlan& m, double* xyz) {
+  if (m.curved) {
+    std::copy(m.nodes.begin(), m.nodes.end(), xyz);
+    return;
+  }
+  std::vector<double> pos[3];
+  for (int d = 0; d < 3; ++d) {
+    pos[d].resize(m.na[d]);
+    for (int64_t X = 0; X < m.na[d]; ++X) {
+      const int64_t c = std::min<int64_t>(X / m.p, m.nc[d] - 1);
+      pos[d][X] = (c + m.basis.nodes[X - m.p * c]) * m.h[d];
+    }
+  }
+  for (int64_t Z = 0; Z < m.na[2]; ++Z)
+    for (int64_t Y = 0; Y < m.na[1]; ++Y)
+      for (int64_t X = 0; X < m.na[0]; ++X) {
+        double* o = xyz + 3 * m.node_id(X, Y, Z);
+        o[0] = pos[0][X];
+        o[1] = pos[1][Y];
+        o[2] = pos[2][Z];
+      }
+}
+
+void mesh_set_nodes(MeshPlan& m, const double* xyz) {
+  const int n = m.n, n3 = n * n * n;
+  // phi_k and phi_k' of the GLL basis at the Gauss points
+  std::vector<double> dphi(n * n);
+  for (int q = 0; q < n; ++q)
+    for (int k = 0; k < n; ++k) dphi[q * n + k] = lagrange_d(m.basis.nodes, k, m.basis.xq[q]);
+  const std::vector<double>& phi = m.basis.S;
+  m.nodes.assign(xyz, xyz + 3 * m.N);
+  m.cG.assign((size_t)m.ncells * 6 * n3, 0.0);
+  m.cJ.assign((size_t)m.ncells * n3, 0.0);
+  std::vector<int32_t> ijk(3 * m.ncells);
+  mesh_cells(m, ijk.data());
+  std::vector<int64_t> ids(n3);
+  for (int64_t c = 0; c < m.ncells; ++c) {
+    cell_node_ids(m, ijk.data() + 3 * c, ids.data());
+    for (int q3 = 0; q3 < n; ++q3)
+      for (int q2 = 0; q2 < n; ++q2)
+        for (int q1 = 0; q1 < n; ++q1) {
+          const int q = q1 + n * (q2 + n * q3);
+          // J[a][b] = dx_a / dxi_b = sum_k x_k,a dN_k/dxi_b
+          double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+          for (int k3 = 0; k3 < n; ++k3)
+            for (int k2 = 0; k2 < n; ++k2)
+              for (int k1 = 0; k1 < n; ++k1) {
+                const double* x = xyz + 3 * ids[k1 + n * (k2 + n * k3)];
+                const double s1 = phi[q1 * n + k1], s2 = phi[q2 * n + k2], s3 = phi[q3 * n + k3];
+                const double d[3] = {dphi[q1 * n + k1] * s2 * s3, s1 * dphi[q2 * n + k2] * s3,
+                                     s1 * s2 * dphi[q3 * n + k3]};
+                for (int a = 0; a < 3; ++a)
+                  for (int b = 0; b < 3; ++b) J[a][b] += x[a] * d[b];
+              }
+          const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                             J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                             J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+          if (!std::isfinite(det) || det == 0.0)
+            throw Error(-1, "a cell's Jacobian is singular at a quadrature point");
+          // inverse by cofactors: Ji[a][b] = cof(J)[b][a] / det
+          double Ji[3][3];
+          Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+          Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+          Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+          Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+          Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+          Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+          Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+          Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+          Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+          const double jxw = m.basis.wq[q1] * m.basis.wq[q2] * m.basis.wq[q3] * std::fabs(det);
+          auto g = [&](int a, int b) {
+            return 0.5 * jxw * (Ji[a][0] * Ji[b][0] + Ji[a][1] * Ji[b][1] + Ji[a][2] * Ji[b][2]);
+          };
+          double* G = m.cG.data() + c * 6 * n3;
+          G[0 * n3 + q] = g(0, 0);
+          G[1 * n3 + q] = g(1, 1);
+          G[2 * n3 + q] = g(2, 2);
+          G[3 * n3 + q] = g(0, 1);
+          G[4 * n3 + q] = g(0, 2);
+          G[5 * n3 + q] = g(1, 2);
+          m.cJ[c * n3 + q] = jxw;
+        }
+  }
+  m.curved = true;
+}
+
 void mesh_qp_points(const MeshPlan& m, double* xyz) {
   const int n = m.n, n3 = n * n * n;
   std::vector<int32_t> ijk(3 * m.ncells);
   mesh_cells(m, ijk.data());
+  if (m.curved) {
+    // x(xi_q) = sum_k x_k N_k(xi_q) over the cell's own nodes
+    const std::vector<double>& phi = m.basis.S;
+    std::vector<int64_t> ids(n3);
+    for (int64_t c = 0; c < m.ncells; ++c) {
+      cell_node_ids(m, ijk.data() + 3 * c, ids.data());
+      for (int q3 = 0; q3 < n; ++q3)
+        for (int q2 = 0; q2 < n; ++q2)
+          for (int q1 = 0; q1 < n; ++q1) {
+            double* o = xyz + 3 * (c * n3 + q1 + n * (q2 + n * q3));
+            o[0] = o[1] = o[2] = 0.0;
+            for (int k3 = 0; k3 < n; ++k3)
+              for (int k2 = 0; k2 < n; ++k2)
+                for (int k1 = 0; k1 < n; ++k1) {
+                  const double w = phi[q1 * n + k1] * phi[q2 * n + k2] * phi[q3 * n + k3];
+                  const double* x = m.nodes.data() + 3 * ids[k1 + n * (k2 + n * k3)];
+                  for (int a = 0; a < 3; ++a) o[a] += w * x[a];
+                }
+          }
+    }
+    return;
+  }
   for (int64_t c = 0; c < m.ncells; ++c)
     for (int q3 = 0; q3 < n; ++q3)
       for (int q2 = 0; q2 < n; ++q2)
@@ -295,7 +416,8 @@ void mesh_set_potential(MeshPlan& m, const double* v) {
       for (int q2 = 0; q2 < n; ++q2)
         for (int q1 = 0; q1 < n; ++q1) {
           const int64_t i = c * n3 + q1 + n * (q2 + n * q3);
-          const double jxw = m.basis.wq[q1] * m.basis.wq[q2] * m.basis.wq[q3] * det;
+          const double jxw =
+              m.curved ? m.cJ[i] : m.basis.wq[q1] * m.basis.wq[q2] * m.basis.wq[q3] * det;
           m.cV[i] = jxw * v[i];
         }
   m.has_potential = true;

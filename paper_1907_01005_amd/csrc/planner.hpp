@@ -60,6 +60,11 @@ struct MeshPlan {
   Basis1D basis;
   std::vector<double> cV;            // [cell 8r+e][q]: JxW_q V(x_q)
   bool has_potential = false;
+  // curved cells (node positions given): the isoparametric map of each cell
+  bool curved = false;
+  std::vector<double> nodes;         // [N][3] node positions, global lexicographic order
+  std::vector<double> cG;            // [cell 8r+e][6][q]: 1/2 JxW (J^{-1} J^{-T}) 00,11,22,01,02,12
+  std::vector<double> cJ;            // [cell 8r+e][q]: JxW_q = w_q |det J(q)|
 
   int64_t node_id(int64_t X, int64_t Y, int64_t Z) const { return X + na[0] * (Y + na[1] * Z); }
   void batch_coords(int b, int& bx, int& by, int& bz) const {
@@ -71,7 +76,14 @@ void plan_mesh(MeshPlan& m, const int nc[3], const double L[3], int degree, unsi
                int order);
 void mesh_cells(const MeshPlan& m, int32_t* ijk);
 void mesh_qp_points(const MeshPlan& m, double* xyz);
+// Positions of the box's nodes (GLL points inside each cell), [N][3], global
+// lexicographic order; the positions given to mesh_set_nodes on curved cells.
+void mesh_node_points(const MeshPlan& m, double* xyz);
 void mesh_set_potential(MeshPlan& m, const double* v);
+// Curved cells: node positions [N][3] define every cell's isoparametric map
+// (Sec. 3.1: general hexahedral cells).  Fills nodes, cG and cJ; throws on a
+// singular Jacobian.  Must come before mesh_set_potential.
+void mesh_set_nodes(MeshPlan& m, const double* xyz);
 
 // ---------------------------------------------------------------- layouts
 // One work item of the apply kernel: an 8-column chunk of column block C on

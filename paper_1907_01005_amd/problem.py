@@ -18,10 +18,14 @@ from .api import (DOT_WORK_DOUBLES, FP64, OP_H, OP_M, Layout, Mesh, apply_H, app
 class DeviceProblem:
     def __init__(self, cells: Sequence[int], L: Sequence[float], degree: int, dirichlet: int,
                  centres: np.ndarray, radius, colblock_sizes, potential: Callable[[np.ndarray], np.ndarray],
-                 device: str = "cuda", stream=None):
+                 device: str = "cuda", stream=None,
+                 node_map: Optional[Callable[[np.ndarray], np.ndarray]] = None):
+        """node_map: curved cells, the box's node positions -> the mesh's."""
         import torch
         self.device = device
         self.mesh = Mesh(cells[0], cells[1], cells[2], L, degree, dirichlet)
+        if node_map is not None:
+            self.mesh.set_nodes(node_map(self.mesh.node_points()))
         qp = self.mesh.qp_points()
         self.mesh.set_potential(np.asarray(potential(qp.reshape(-1, 3)), dtype=np.float64))
         self.layout = Layout(self.mesh, centres, radius, colblock_sizes)

@@ -27,7 +27,8 @@ def device_problem(wl, mesh_index: int = 0):
     from paper_1907_01005_amd.problem import DeviceProblem
     ms = wl.meshes[mesh_index]
     return DeviceProblem((ms.nx, ms.ny, ms.nz), ms.L, ms.degree, ms.dirichlet, wl.centres,
-                         wl.radius, wl.colblock_sizes, lambda P: synth.potential_at(wl, P))
+                         wl.radius, wl.colblock_sizes, lambda P: synth.potential_at(wl, P),
+                         node_map=ms.bend_points if getattr(ms, "bend", 0.0) else None)
 
 
 def rel_fro(a: np.ndarray, b: np.ndarray) -> float:

@@ -124,3 +124,19 @@ def test_closure_and_operator_argument_checks():
     assert lib().mfb_energy(0, fake, fake, fake, fake, None) == N.MFB_EINVAL
     assert lib().mfb_energy(4, None, fake, fake, fake, None) == N.MFB_EINVAL
     assert lib().mfb_energy(4, fake, fake, fake, None, None) == N.MFB_EINVAL
+
+
+def test_curved_mesh_errors():
+    m = Mesh(4, 2, 2, (4.0, 2.0, 2.0), 2)
+    x = m.node_points()
+    with pytest.raises(MfbError) as e:
+        m.set_nodes(np.where(np.arange(x.size).reshape(x.shape) == 7, np.nan, x))
+    assert e.value.code == N.MFB_EINVAL
+    with pytest.raises(MfbError) as e:
+        m.set_nodes(np.zeros_like(x))                    # every cell collapsed
+    assert e.value.code == N.MFB_EINVAL
+    m.set_nodes(x + 0.01 * np.sin(x[:, ::-1]))
+    m.set_potential(np.zeros((m.ncells, m.qp_per_cell)))
+    with pytest.raises(MfbError) as e:
+        m.set_nodes(x)                                   # after the potential
+    assert e.value.code == N.MFB_ESTATE

@@ -22,8 +22,8 @@ def _need_gpu():
         pytest.fail("GPU tests need a visible GPU (run with -m 'not gpu' on CPU)")
 
 
-def _small(degree, values="orbitals"):
-    ms = synth.MeshSpec(8, 6, 4, (8.0, 6.0, 4.0), degree)
+def _small(degree, values="orbitals", bend=0.0):
+    ms = synth.MeshSpec(8, 6, 4, (8.0, 6.0, 4.0), degree, bend=bend)
     wl = synth.custom_workload(ms, 29, 2.2, 11, potential="wells",
                                name=f"8x6x4-Q{degree}-M29")
     wl.colblock_sizes = np.asarray([8, 5, 12, 4], dtype=np.int32)
@@ -153,3 +153,17 @@ def test_paper_scale_closure_energy(cfg):
     e1 = float(dp.E.cpu()[0])
     energy(dp.M, dp.Mbar, dp.Hbar, dp.E, dp.work_e)
     assert e1 == float(dp.E.cpu()[0]) and np.isfinite(float(E1.cpu()[0]))
+
+
+@pytest.mark.parametrize("degree", [1, 2, 3, 4])
+def test_curved_closure_energy(degree):
+    """Bent cells: H X and M X on the closure (per-cell metric and JxW),
+    Hbar, Mbar and the energy against the oracle."""
+    wl = _small(degree, bend=0.3)
+    say(f"curved closure Q{degree}")
+    op = OracleProblem(wl)
+    assert op.mesh.curved
+    dp = device_problem(wl)
+    dp.set_X_coo(op.node, op.orb, op.val)
+    for prec, tol in ((0, TOL64), (2, TOL32)):
+        _check(wl, op, dp, prec, tol)

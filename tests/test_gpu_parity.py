@@ -50,10 +50,10 @@ def _check_full(wl, op, dp, prec, tol, tuned=None):
 
 
 def _small(cfg_cells, degree, M, radius, seed, sizes=None, dirichlet=0x3F, potential="wells",
-           L=None):
+           L=None, bend=0.0):
     nx, ny, nz = cfg_cells
     L = L or (float(nx), float(ny), float(nz))
-    ms = synth.MeshSpec(nx, ny, nz, L, degree, dirichlet)
+    ms = synth.MeshSpec(nx, ny, nz, L, degree, dirichlet, bend=bend)
     wl = synth.custom_workload(ms, M, radius, seed, potential=potential,
                                name=f"{nx}x{ny}x{nz}-Q{degree}-M{M}")
     if sizes is not None:
@@ -232,3 +232,25 @@ def test_paper_scale_sampled(cfg):
             et = abs(tr - tro) / abs(tro)
             say(f"config{cfg} prec={prec} relS={eS:.2e} relTr={et:.2e}")
             assert eS <= tol and et <= tol
+
+
+@pytest.mark.parametrize("degree", [1, 2, 3, 4])
+def test_curved_cells(degree):
+    """Bent cells (isoparametric map, the metric coupling all three gradients):
+    generic values with ragged blocks, the default and the fused tuned
+    kernels in every precision; other tuned kernels are refused."""
+    from paper_1907_01005_amd import MfbError
+    import paper_1907_01005_amd._native as N
+    wl = _small((8, 6, 4), degree, 29, 2.2, 11, sizes=[8, 5, 12, 4], bend=0.3)
+    say(f"curved cells Q{degree}")
+    op = OracleProblem(wl, values="generic", value_seed=5)
+    assert op.mesh.curved
+    dp = device_problem(wl)
+    dp.set_X_coo(op.node, op.orb, op.val)
+    for prec, tol in ((0, TOL64), (3, TOL32), (2, TOL32)):
+        _check_full(wl, op, dp, prec, tol)
+    for kernel in (2, 7):
+        _check_full(wl, op, dp, 0, TOL64, tuned=kernel)
+    with pytest.raises(MfbError) as e:
+        dp.apply_tuned(0, kernel=1)
+    assert e.value.code == N.MFB_EUNSUPPORTED

@@ -121,3 +121,28 @@ def test_closure_random_small_meshes(seed):
     clo = lay.closure()
     _assert_same(clo, closure_pattern(op))
     assert clo.info["apply_items"] == 0 and clo.nvalues >= lay.nvalues
+
+
+# ---------------------------------------------------------------- curved cells
+@pytest.mark.parametrize("degree", [1, 2, 3, 4])
+def test_node_points_and_curved_qp_points_match_the_oracle(degree):
+    """The library's box node positions equal the oracle's; on a bent mesh the
+    library's mapped quadrature points equal the oracle's (cells reordered
+    from the oracle's lexicographic order to the library's batch order)."""
+    from paper_1907_01005_amd.api import Mesh
+    ms = synth.MeshSpec(4, 2, 2, (4.0, 2.5, 2.0), degree, 0x3F, bend=0.3)
+    om = BoxMesh(ms.nx, ms.ny, ms.nz, tuple(ms.L), ms.degree, ms.dirichlet)
+    lm = Mesh(ms.nx, ms.ny, ms.nz, ms.L, ms.degree, ms.dirichlet)
+    x_lib, x_or = lm.node_points(), om.node_points()
+    assert np.abs(x_lib - x_or).max() <= 1e-14 * max(ms.L)
+    meta_box = lm.meta_bytes
+    lm.set_nodes(ms.bend_points(x_lib))
+    assert lm.meta_bytes > meta_box                     # the metric and JxW tables
+    oc = BoxMesh(ms.nx, ms.ny, ms.nz, tuple(ms.L), ms.degree, ms.dirichlet,
+                 nodes=ms.bend_points(x_or))
+    q_lib = lm.qp_points()
+    ijk = lm.cells()
+    lin = ijk[:, 0] + ms.nx * (ijk[:, 1] + ms.ny * ijk[:, 2])
+    q_or = oc.qp_points()[lin]
+    assert np.abs(q_lib - q_or).max() <= 1e-13 * max(ms.L)
+    assert np.abs(q_lib - om.qp_points()[lin]).max() > 1e-3   # the map did bend the cells
