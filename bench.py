@@ -102,15 +102,20 @@ def measured_traffic(workload: str, prec: str):
     return rec.get("apply_H_bytes_per_launch")
 
 
-def build_problem(cfg: int, mesh_index: int = 0, radius: float = 0.0):
+def build_problem(cfg: int, mesh_index: int = 0, radius: float = 0.0, bend: float = 0.0):
     """The seeded workload of configuration `cfg` on the GPU; radius > 0 replaces the
-    support radius (same centres, potential and blocks; a different workload)."""
+    support radius (same centres, potential and blocks; a different workload); bend > 0
+    bends the cells (curved-cell form, amplitude in cell widths)."""
     import dataclasses
     import synth
     from paper_1907_01005_amd.problem import DeviceProblem
     wl = synth.make_workload(cfg)
     if radius > 0:
         wl = dataclasses.replace(wl, radius=float(radius), name=f"{wl.name}-r{radius:g}")
+    if bend > 0:
+        meshes = list(wl.meshes)
+        meshes[mesh_index] = dataclasses.replace(meshes[mesh_index], bend=float(bend))
+        wl = dataclasses.replace(wl, meshes=meshes, name=f"{wl.name}-bent{bend:g}")
     ms = wl.meshes[mesh_index]
     dp = DeviceProblem((ms.nx, ms.ny, ms.nz), ms.L, ms.degree, ms.dirichlet, wl.centres,
                        wl.radius, wl.colblock_sizes, lambda P: synth.potential_at(wl, P),
@@ -256,6 +261,30 @@ def time_path(dp, prec: int, steps: int, warmup: int, kernel: int = 0):
     t_apply = np.array([a.elapsed_time(b) for a, b, _ in ev]) * 1e-3
     t_tm = np.array([b.elapsed_time(c) for _, b, c in ev]) * 1e-3
     return wall, t_apply, t_tm
+
+
+def curved_form(cfg: int, bend: float = 0.3, steps: int = 50):
+    """The same workload on bent cells (isoparametric map, amplitude `bend` cell
+    widths): apply_H with the per-cell metric, and the step, in fp64 and fp32-MFMA."""
+    import torch
+    print(f"[bench] curved form (bend {bend})", file=sys.stderr, flush=True)
+    wl, dp = build_problem(cfg, bend=bend)
+    alg = algorithmic(dp, wl.mesh.degree)
+    n3 = (wl.mesh.degree + 1) ** 3
+    # X read, Y written, and per active cell JxW V plus the six metric planes
+    geo_bytes = 16 * alg["E"] + 7 * 8 * n3 * 8 * alg["active_batches"]
+    out = {"workload": wl.name, "algorithmic_bytes": geo_bytes}
+    for name in ("fp64", "fp32-mfma"):
+        wall, ta, tt = time_path(dp, PRECS[name], steps, 5)
+        t_ap = float(np.mean(ta))
+        out[name] = {"apply_ms_p50": float(np.percentile(ta, 50) * 1e3),
+                     "apply_gdofcols_s": alg["E"] / t_ap / 1e9,
+                     "apply_hbm_frac": geo_bytes / t_ap / 1e9 / HBM_PEAK_GBS,
+                     "tmmult_ms_mean": float(np.mean(tt) * 1e3),
+                     "step_ms": wall / steps * 1e3}
+    del dp
+    torch.cuda.empty_cache()
+    return out
 
 
 def time_graph(dp, prec: int, steps: int, kernel: int = 0) -> float:
@@ -424,6 +453,7 @@ def main(argv=None):
         forms["energy"] = energy_form(dp)
         forms["graph20-" + args.prec] = graph_form(dp, prec)
         forms["graph20-fp32-mfma"] = graph_form(dp, PRECS["fp32-mfma"])
+        forms["curved"] = curved_form(args.config)
         out["forms"] = forms
     if args.config4:
         out["config4"] = config4_forms()
