@@ -365,7 +365,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the path is not sharded across GPUs in this build "
+        print("bench.py measures one GPU: the path is not sharded across GPUs "
               "(run with --gpus 1)", file=sys.stderr)
         return 2
 

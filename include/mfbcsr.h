@@ -67,7 +67,7 @@ typedef struct mfb_mv mfb_mv;
 typedef enum {
   MFB_OK = 0,
   MFB_EINVAL = -1,        /* bad argument (null pointer, size, range)          */
-  MFB_EUNSUPPORTED = -2,  /* valid request this build does not implement      */
+  MFB_EUNSUPPORTED = -2,  /* valid request the library does not implement     */
   MFB_EPATTERN = -3,      /* layout/mesh mismatch, entry outside the pattern   */
   MFB_ENOMEM = -4,        /* host allocation failed                            */
   MFB_EHIP = -5,          /* a HIP runtime call failed                          */

@@ -497,7 +497,7 @@ int mfb_apply_H(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X, doubl
   mfb::gpu::ApplyParams a;
   fill_apply_params(mesh, mv, d_X, d_Y, a);
   const int rc = mfb::gpu::launch_apply(a, mesh->plan.p, prec, 0, mv->plan.block_offset.back(), stream);
-  if (rc == -2) fail(MFB_EUNSUPPORTED, "precision not implemented in this build");
+  if (rc == -2) fail(MFB_EUNSUPPORTED, "precision not implemented by the library");
   if (rc != 0) fail(MFB_EHIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)rc));
   return MFB_OK;
   MFB_CATCH
@@ -524,7 +524,7 @@ int mfb_apply_H_tuned(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X,
   a.grid = tune->grid;
   const int rc =
       mfb::gpu::launch_apply(a, mesh->plan.p, tune->prec, tune->kernel, mv->plan.block_offset.back(), stream);
-  if (rc == -2) fail(MFB_EUNSUPPORTED, "precision not implemented in this build");
+  if (rc == -2) fail(MFB_EUNSUPPORTED, "precision not implemented by the library");
   if (rc != 0) fail(MFB_EHIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)rc));
   return MFB_OK;
   MFB_CATCH
@@ -565,7 +565,7 @@ int mfb_apply_op(const mfb_mesh* mesh, const mfb_mv* x, const mfb_mv* y, int op,
   if (y != x) a.rowoff_out = (const int32_t*)((const char*)y->d_meta + y->lay.off_dest_rowoff);
   const int rc = mfb::gpu::launch_apply_op(a, mesh->plan.p, prec, op, y->plan.block_offset.back(),
                                            stream);
-  if (rc == -2) fail(MFB_EUNSUPPORTED, "precision not implemented in this build");
+  if (rc == -2) fail(MFB_EUNSUPPORTED, "precision not implemented by the library");
   if (rc != 0) fail(MFB_EHIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)rc));
   return MFB_OK;
   MFB_CATCH
