@@ -196,6 +196,8 @@ typedef struct {
   int64_t apply_pairs_own;  /* ... of which the batch's own block is stored    */
   int64_t tm_units;         /* (row block, C1, C2) products of Alg. 8          */
   int64_t s_pairs;          /* stored (C1, C2) blocks of S                     */
+  int64_t tm_tasks;         /* densely populated row blocks whose products of
+                               Alg. 8 run as one task each (not in tm_units)   */
 } mfb_mv_info;
 
 /* Table-1-style statistics of a layout (Sec. 6, Table 1).                   */

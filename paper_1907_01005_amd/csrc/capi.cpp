@@ -59,7 +59,8 @@ struct MvLayout {
   size_t off_items = 0, off_units = 0, off_pair_tab = 0, off_pair_ptr = 0, off_pair_list = 0,
          off_cb_of_col = 0, off_cb_start = 0, off_blk_off = 0, off_blk_col0 = 0, off_blk_w = 0,
          off_rowoff = 0, off_shell_ptr = 0, off_shell_ro = 0, off_s2 = 0, off_dest_rowoff = 0,
-         off_rowptr = 0, off_blk_row = 0, bytes = 0;
+         off_rowptr = 0, off_blk_row = 0, off_tasks = 0, off_task_blk = 0, off_task_part = 0,
+         bytes = 0;
 };
 
 MvLayout mv_layout(const mfb::MvPlan& v) {
@@ -99,6 +100,12 @@ MvLayout mv_layout(const mfb::MvPlan& v) {
   o = align256(o + sizeof(int64_t) * v.rowptr.size());
   L.off_blk_row = o;
   o = align256(o + sizeof(int32_t) * v.colidx.size());
+  L.off_tasks = o;
+  o = align256(o + sizeof(mfb::TmTask) * v.tasks.size());
+  L.off_task_blk = o;
+  o = align256(o + sizeof(mfb::TaskBlk) * v.task_blk.size());
+  L.off_task_part = o;
+  o = align256(o + sizeof(int64_t) * v.task_part.size());
 
   L.bytes = std::max<size_t>(o, 256);
   return L;
@@ -299,6 +306,7 @@ int mfb_mv_get_info(const mfb_mv* mv, mfb_mv_info* out) {
   out->apply_pairs_own = p.apply_pairs_own;
   out->tm_units = (int64_t)p.units.size();
   out->s_pairs = (int64_t)p.pair_ptr.size() - 1;
+  out->tm_tasks = (int64_t)p.tasks.size();
   return MFB_OK;
   MFB_CATCH
 }
@@ -420,6 +428,9 @@ int mfb_mv_bind(mfb_mv* mv, void* d_meta, void* stream) {
   put(L.off_s2, p.s2.data(), sizeof(mfb::S2Desc) * p.s2.size());
   put(L.off_dest_rowoff, p.dest_rowoff.data(), sizeof(int32_t) * p.dest_rowoff.size());
   put(L.off_rowptr, p.rowptr.data(), sizeof(int64_t) * p.rowptr.size());
+  put(L.off_tasks, p.tasks.data(), sizeof(mfb::TmTask) * p.tasks.size());
+  put(L.off_task_blk, p.task_blk.data(), sizeof(mfb::TaskBlk) * p.task_blk.size());
+  put(L.off_task_part, p.task_part.data(), sizeof(int64_t) * p.task_part.size());
   {
     std::vector<int32_t> brow(p.colidx.size());
     for (size_t r = 0; r + 1 < p.rowptr.size(); ++r)
@@ -673,6 +684,10 @@ int mfb_tmmult(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d
   t.units = (const mfb::TmUnit*)(mb + mv->lay.off_units);
   t.nunits = (int64_t)p.units.size();
   for (int c = 0; c < 4; ++c) t.class_end[c] = p.tm_class_end[c];
+  t.tasks = (const mfb::TmTask*)(mb + mv->lay.off_tasks);
+  t.task_blk = (const mfb::TaskBlk*)(mb + mv->lay.off_task_blk);
+  t.task_part = (const int64_t*)(mb + mv->lay.off_task_part);
+  for (int c = 0; c < 3; ++c) t.task_class_end[c] = p.task_class_end[c];
   t.part = (double*)((char*)d_work + kCounterBytes);
   t.pair_tab = (const int32_t*)(mb + mv->lay.off_pair_tab);
   t.pair_ptr = (const int32_t*)(mb + mv->lay.off_pair_ptr);

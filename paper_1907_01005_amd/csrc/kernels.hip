@@ -999,6 +999,149 @@ __global__ __launch_bounds__(64 * NW) void tm_stage1_mfma_kernel(TmParams p, int
   }
 }
 
+// f(std::integral_constant<int, n>) for a run-time n in [N, NMAX].
+template <int N, int NMAX, typename F>
+__device__ __forceinline__ void dispatch_count(int n, F& f) {
+  if constexpr (N <= NMAX) {
+    if (n == N)
+      f(std::integral_constant<int, N>{});
+    else
+      dispatch_count<N + 1, NMAX>(n, f);
+  }
+}
+
+// Stage 1 for densely populated row blocks (the planner's tasks): all block
+// products of row block r at once, C = X_r^T Y_r with X_r (rows x wa) and
+// Y_r (rows x wb) the row block's stored blocks side by side, on the fp64
+// matrix cores.  Chunks of 16 rows of X_r and Y_r go through LDS, double
+// buffered: the next chunk's loads are in flight while the current chunk's
+// products run.  Column c < wa + wb of [X_r | Y_r], whose rows lie w apart
+// in its block, is copied by thread c (and by c + 256 for every other row
+// with eight waves).  C is cut into 16x16 tiles and wave w of NW takes the
+// w-th contiguous share of them in row-major order.  Entry
+// (a, b) of C belongs to the block pair (i, j) holding columns a and b and
+// goes to that pair's partial slot, the one a unit would have written, so
+// the second stage serves both.  The sum over rows has a fixed order.
+template <int WMAX, int NW>
+__global__ __launch_bounds__(64 * NW) void tm_task_kernel(TmParams p, int64_t first, int64_t count) {
+  constexpr int kRC = 16;                                // rows per chunk
+  constexpr int kLd = WMAX + 1;                          // LDS row stride (doubles)
+  constexpr int kStage = 2 * kRC * kLd;                  // [X chunk | Y chunk]
+  constexpr int kNT = ((WMAX / 16) * (WMAX / 16) + NW - 1) / NW;  // tiles per wave at most
+  constexpr int kG = NW / 4;                             // threads per copied column
+  constexpr int kRG = kRC / kG;                          // rows each of them copies
+  __shared__ double st[2 * kStage];
+  __shared__ int64_t boff[2][WMAX];
+  __shared__ int16_t bcol[2][WMAX], bw[2][WMAX], cblk[2][WMAX];
+  __shared__ int64_t tpart[kTaskMaxPairs];
+  const int t = threadIdx.x, l = t & 63, col = l & 15, kr = l >> 4;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int64_t task = xcd_item(blockIdx.x, gridDim.x);
+  if (task >= count) return;
+  const TmTask T = p.tasks[first + task];
+  const int rows = T.rows, wa = T.wa, wb = T.wb;
+  const int TA = (wa + 15) >> 4, TB = (wb + 15) >> 4;
+  // block tables and the block of every column, per side
+  if (t < T.ka || (t >= 128 && t - 128 < T.kb)) {
+    const int s = t >= 128, k = t - 128 * s;
+    const TaskBlk b = p.task_blk[(s ? T.b_first : T.a_first) + k];
+    boff[s][k] = b.off;
+    bcol[s][k] = (int16_t)b.col;
+    bw[s][k] = (int16_t)b.w;
+    for (int c = b.col; c < b.col + b.w; ++c) cblk[s][c] = (int16_t)k;
+  }
+  for (int e = t; e < T.ka * T.kb; e += 64 * NW) tpart[e] = p.task_part[T.p_first + e];
+  // zero the padding columns of both stages (never written by the copy)
+  for (int e = t; e < 2 * 2 * kRC * 16; e += 64 * NW) {
+    const int c = e & 15, r = (e >> 4) % kRC, s = (e >> 4) / kRC;  // s: stage * 2 + side
+    const int w = (s & 1) ? wb : wa, cp = ((s & 1) ? TB : TA) * 16;
+    if (w + c < cp) st[(s >> 1) * kStage + (s & 1) * kRC * kLd + r * kLd + w + c] = 0.0;
+  }
+  __syncthreads();
+  // this thread's column of [X_r | Y_r] (rows g, g + kG, ... of each chunk)
+  const int fcol = t & 255, g = t >> 8;
+  const bool fc = fcol < wa + wb;
+  const int sd = fcol >= wa, cx = sd ? fcol - wa : fcol;
+  const double* __restrict__ src = p.X;
+  int sw = 0, dst = 0;
+  if (fc) {
+    const int k = cblk[sd][cx];
+    src = (sd ? p.Y : p.X) + boff[sd][k] + (cx - bcol[sd][k]);
+    sw = bw[sd][k];
+    dst = sd * kRC * kLd + cx;
+  }
+  double v[kRG];
+  auto load = [&](int i0) {
+#pragma unroll
+    for (int r = 0; r < kRG; ++r) {
+      const int i = i0 + g + kG * r;
+      v[r] = (fc && i < rows) ? src[(int64_t)i * sw] : 0.0;
+    }
+  };
+  auto store = [&](int s) {
+    if (fc)
+#pragma unroll
+      for (int r = 0; r < kRG; ++r) st[s * kStage + dst + (g + kG * r) * kLd] = v[r];
+  };
+  // this wave's tiles: the main loop is compiled for each tile count, so
+  // that the products carry no branches and the accumulators stay put
+  const int ntile = TA * TB;
+  const int t0 = ntile * wv / NW, nt = ntile * (wv + 1) / NW - t0;
+  load(0);
+  store(0);
+  __syncthreads();
+  auto main_loop = [&](auto ncount) {
+    constexpr int N = decltype(ncount)::value;
+    int ao[N > 0 ? N : 1], bo[N > 0 ? N : 1];
+    v4d acc[N > 0 ? N : 1];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      const int tt = t0 + q, ta = tt / TB, tb = tt - ta * TB;
+      ao[q] = kr * kLd + 16 * ta + col;
+      bo[q] = kRC * kLd + kr * kLd + 16 * tb + col;
+      acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+    for (int c = 0, i0 = 0; i0 < rows; ++c, i0 += kRC) {
+      const bool more = i0 + kRC < rows;
+      if (more) load(i0 + kRC);
+      const double* __restrict__ sb = st + (c & 1) * kStage;
+      const int steps = min(kRC / 4, (rows - i0 + 3) >> 2);
+      for (int k = 0; k < steps; ++k) {
+        const int ko = 4 * k * kLd;
+        double av[N > 0 ? N : 1], bv[N > 0 ? N : 1];
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+          av[q] = sb[ao[q] + ko];
+          bv[q] = sb[bo[q] + ko];
+        }
+#pragma unroll
+        for (int q = 0; q < N; ++q)
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc[q], 0, 0, 0);
+      }
+      if (more) store((c + 1) & 1);
+      __syncthreads();
+    }
+    // C(16 ta + kr + 4 r, 16 tb + col) -> the partial slot of its block pair
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      const int tt = t0 + q, ta = tt / TB, tb = tt - ta * TB;
+      const int b = 16 * tb + col;
+      if (b < wb) {
+        const int j = cblk[1][b], lb = b - bcol[1][j], wj = bw[1][j];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = 16 * ta + kr + 4 * r;
+          if (a < wa) {
+            const int i = cblk[0][a];
+            p.part[tpart[i * T.kb + j] + (a - bcol[0][i]) * wj + lb] = acc[q][r];
+          }
+        }
+      }
+    }
+  };
+  dispatch_count<0, kNT>(nt, main_loop);
+}
+
 __global__ __launch_bounds__(256) void tm_stage2_kernel(TmParams p) {
   __shared__ double red[256];
   const int t = threadIdx.x;
@@ -1941,6 +2084,18 @@ int launch_tmmult(const TmParams& p, void* stream) {
   launch(tm_stage1_kernel<1>, 1, 64);
   launch(tm_stage1_mfma_kernel<1, 2>, 2, 64);
   launch(tm_stage1_mfma_kernel<4, 2>, 3, 256);
+  {
+    const int64_t* te = p.task_class_end;
+    auto launch_tasks = [&](auto kernel, int c, int threads) {
+      const int64_t lo = c ? te[c - 1] : 0, n = te[c] - lo;
+      if (n <= 0) return;
+      const int64_t nwg = ((n + 7) / 8) * 8;
+      hipLaunchKernelGGL(kernel, dim3((unsigned)nwg), dim3(threads), 0, st, p, lo, n);
+    };
+    launch_tasks(tm_task_kernel<64, 4>, 0, 256);
+    launch_tasks(tm_task_kernel<96, 4>, 1, 256);
+    launch_tasks(tm_task_kernel<128, 8>, 2, 512);
+  }
   {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;

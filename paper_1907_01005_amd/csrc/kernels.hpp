@@ -45,6 +45,10 @@ struct TmParams {
   const TmUnit* units;
   int64_t nunits;
   int64_t class_end[4];      // cumulative unit counts of the four stage-1 kernel classes
+  const TmTask* tasks;       // dense row blocks, sorted by width class
+  const TaskBlk* task_blk;
+  const int64_t* task_part;
+  int64_t task_class_end[3]; // cumulative task counts (widths <= 64, 96, 128)
   double* part;
   const int32_t* pair_tab;   // [ncb*ncb]
   const int32_t* pair_ptr;   // [npairs+1] prefix counts of partial products per pair

@@ -472,8 +472,47 @@ void plan_overlap(MvPlan& mv, const MvPlan& A, const MvPlan& B, const MeshPlan& 
   }
   mv.part_doubles = part;
   std::vector<int64_t> fill(npairs, 0);
+  mv.tasks.clear();
+  mv.task_blk.clear();
+  mv.task_part.clear();
   for (int r = 0; r < nbt; ++r) {
     const int64_t rows = m.rb_start[r + 1] - m.rb_start[r];
+    const int64_t ka = A.rowptr[r + 1] - A.rowptr[r], kb = B.rowptr[r + 1] - B.rowptr[r];
+    int32_t wa = 0, wb = 0;
+    for (int64_t k1 = A.rowptr[r]; k1 < A.rowptr[r + 1]; ++k1) wa += w[A.colidx[k1]];
+    for (int64_t k2 = B.rowptr[r]; k2 < B.rowptr[r + 1]; ++k2) wb += w[B.colidx[k2]];
+    if (ka * kb >= kTaskMinPairs && ka * kb <= kTaskMaxPairs && wa <= kTaskMaxWidth &&
+        wb <= kTaskMaxWidth) {
+      // the whole row block as one task; partial slots as the units would have them
+      TmTask T;
+      T.a_first = (int64_t)mv.task_blk.size();
+      int32_t col = 0;
+      for (int64_t k1 = A.rowptr[r]; k1 < A.rowptr[r + 1]; ++k1) {
+        mv.task_blk.push_back(TaskBlk{A.block_offset[k1], col, w[A.colidx[k1]]});
+        col += w[A.colidx[k1]];
+      }
+      T.b_first = (int64_t)mv.task_blk.size();
+      col = 0;
+      for (int64_t k2 = B.rowptr[r]; k2 < B.rowptr[r + 1]; ++k2) {
+        mv.task_blk.push_back(TaskBlk{B.block_offset[k2], col, w[B.colidx[k2]]});
+        col += w[B.colidx[k2]];
+      }
+      T.p_first = (int64_t)mv.task_part.size();
+      for (int64_t k1 = A.rowptr[r]; k1 < A.rowptr[r + 1]; ++k1)
+        for (int64_t k2 = B.rowptr[r]; k2 < B.rowptr[r + 1]; ++k2) {
+          const int C1 = A.colidx[k1], C2 = B.colidx[k2];
+          const int32_t pid = mv.pair_tab[(size_t)C1 * ncb + C2];
+          mv.task_part.push_back(mv.pair_list[pid] + fill[pid]++ * (int64_t)w[C1] * w[C2]);
+        }
+      T.rows = (int32_t)rows;
+      T.ka = (int32_t)ka;
+      T.kb = (int32_t)kb;
+      T.wa = wa;
+      T.wb = wb;
+      T.pad = 0;
+      mv.tasks.push_back(T);
+      continue;
+    }
     for (int64_t k1 = A.rowptr[r]; k1 < A.rowptr[r + 1]; ++k1)
       for (int64_t k2 = B.rowptr[r]; k2 < B.rowptr[r + 1]; ++k2) {
         const int C1 = A.colidx[k1], C2 = B.colidx[k2];
@@ -514,6 +553,16 @@ void plan_overlap(MvPlan& mv, const MvPlan& A, const MvPlan& B, const MeshPlan& 
   mv.tm_class_end.fill(0);
   for (const TmUnit& u : mv.units)
     for (int c = tm_class(u); c < 4; ++c) ++mv.tm_class_end[c];
+  // tasks by register tile: 4, 6 or 8 columns of each block product per thread
+  auto task_class = [](const TmTask& T) {
+    const int wmax = T.wa > T.wb ? T.wa : T.wb;
+    return wmax <= 64 ? 0 : (wmax <= 96 ? 1 : 2);
+  };
+  std::stable_sort(mv.tasks.begin(), mv.tasks.end(),
+                   [&](const TmTask& x, const TmTask& y) { return task_class(x) < task_class(y); });
+  mv.task_class_end.fill(0);
+  for (const TmTask& T : mv.tasks)
+    for (int c = task_class(T); c < 3; ++c) ++mv.task_class_end[c];
 }
 
 void plan_mv(MvPlan& mv, const MeshPlan& m, int M, const double* centers, const double* radius,

@@ -114,6 +114,23 @@ struct S2Desc {
 };
 static_assert(sizeof(S2Desc) == 32, "S2Desc layout");
 
+// A densely populated row block of Alg. 8 as one task: every product
+// X_{r,C1}^T Y_{r,C2} of its blocks at once, X_r and Y_r read once.  Its
+// blocks are task_blk[a_first .. a_first + ka) (of A) and [b_first ..
+// b_first + kb) (of B); the partial of pair (i, j) goes to
+// task_part[p_first + i kb + j].
+struct TmTask {
+  int64_t a_first, b_first, p_first;
+  int32_t rows, ka, kb, wa, wb, pad;
+};
+static_assert(sizeof(TmTask) == 48, "TmTask layout");
+struct TaskBlk {
+  int64_t off;  // value offset of the block
+  int32_t col;  // first column within the task's columns
+  int32_t w;    // block width
+};
+static_assert(sizeof(TaskBlk) == 16, "TaskBlk layout");
+
 struct MvPlan {
   const MeshPlan* mesh = nullptr;
   int M = 0, ncb = 0;
@@ -135,6 +152,10 @@ struct MvPlan {
   // 0: 8x8 blocks of at most 128 rows, 1: longer 8x8 blocks with even
   // offsets, 2: other blocks of at most 128 rows, 3: the rest
   std::array<int64_t, 4> tm_class_end{};  // cumulative unit counts per class
+  std::vector<TmTask> tasks;         // dense row blocks, by tile class (widths <= 64, 96, 128)
+  std::array<int64_t, 3> task_class_end{};
+  std::vector<TaskBlk> task_blk;
+  std::vector<int64_t> task_part;
   std::vector<S2Desc> s2;            // [ncb*ncb] blocks of S
   int64_t part_doubles = 0;
   std::vector<int32_t> pair_tab;     // ncb*ncb -> pair id or -1
@@ -153,7 +174,13 @@ struct MvPlan {
 void plan_mv(MvPlan& mv, const MeshPlan& m, int M, const double* centers, const double* radius,
              int radius_count, int ncolblocks, const int32_t* sizes, int B, int col_order);
 
-// Overlap plan (units, pairs, S-block descriptors) of S = A^T B into mv.
+// Row blocks with at least kTaskMinPairs and at most kTaskMaxPairs block
+// pairs, and no more than kTaskMaxWidth columns on either side, become tasks.
+constexpr int kTaskMinPairs = 16;
+constexpr int kTaskMaxPairs = 1024;
+constexpr int kTaskMaxWidth = 128;
+
+// Overlap plan (units, tasks, pairs, S-block descriptors) of S = A^T B into mv.
 void plan_overlap(MvPlan& mv, const MvPlan& A, const MvPlan& B, const MeshPlan& m);
 
 // Closure destination of x: block (r, C) is stored iff a non-Dirichlet node of

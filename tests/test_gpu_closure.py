@@ -167,3 +167,19 @@ def test_curved_closure_energy(degree):
     dp.set_X_coo(op.node, op.orb, op.val)
     for prec, tol in ((0, TOL64), (2, TOL32)):
         _check(wl, op, dp, prec, tol)
+
+
+def test_dense_closure_energy():
+    """Closure with densely populated row blocks: the overlap X^T (H X) onto
+    the closure runs most row blocks as tasks whose two sides differ in width."""
+    sizes = [8, 5, 12, 4, 16, 7, 9, 3, 11, 6, 10, 9, 14, 2, 13, 11]
+    ms = synth.MeshSpec(8, 6, 4, (8.0, 6.0, 4.0), 2)
+    wl = synth.custom_workload(ms, sum(sizes), 2.0, 5, potential="wells", name="8x6x4-Q2-dense")
+    wl.colblock_sizes = np.asarray(sizes, dtype=np.int32)
+    say("dense closure")
+    op = OracleProblem(wl)
+    dp = device_problem(wl)
+    dp.set_X_coo(op.node, op.orb, op.val)
+    dp.enable_closure()
+    assert dp.closure.info["tm_tasks"] > 0
+    _check(wl, op, dp, 0, TOL64)

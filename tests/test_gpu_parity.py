@@ -254,3 +254,36 @@ def test_curved_cells(degree):
     with pytest.raises(MfbError) as e:
         dp.apply_tuned(0, kernel=1)
     assert e.value.code == N.MFB_EUNSUPPORTED
+
+
+DENSE_SIZES = [8, 5, 12, 4, 16, 7, 9, 3, 11, 6, 10, 9, 14, 2, 13, 11]
+
+
+@pytest.mark.parametrize("degree,cells,radius", [(1, (8, 6, 4), 2.0), (2, (8, 6, 4), 2.0),
+                                                 (3, (6, 4, 4), 2.5), (4, (4, 4, 4), 2.0)])
+def test_dense_row_blocks(degree, cells, radius):
+    """Row blocks with many stored blocks: their overlap products run as one
+    task each (all three width classes; rows in one chunk at Q1, up to 46
+    chunks at Q4, ragged), beside units for sparse rows and for rows wider than
+    a task.  S = X^T (H X) against the oracle, then S = X^T Z for generic Z
+    on X's pattern against the oracle's X^T Z."""
+    import scipy.sparse as sp
+    import torch
+    from oracle.apply import overlap as oracle_overlap
+    wl = _small(cells, degree, sum(DENSE_SIZES), radius, 5, sizes=DENSE_SIZES)
+    say(f"dense row blocks Q{degree} {cells} r={radius}")
+    op = OracleProblem(wl)
+    dp = device_problem(wl)
+    assert dp.layout.info["tm_tasks"] > 0
+    dp.set_X_coo(op.node, op.orb, op.val)
+    _check_full(wl, op, dp, 0, TOL64)
+    node, orb = dp.layout.entry_coords()
+    z = np.random.default_rng(17).standard_normal(len(node))
+    dp.Y[:dp.nvalues].copy_(torch.from_numpy(dp.layout.pack(node, orb, z)))
+    dp.overlap()
+    torch.cuda.synchronize()
+    So = oracle_overlap(op.X_sparse(), sp.csc_matrix((z, (node, orb)), shape=op.X_sparse().shape))
+    eS = rel_fro(dp.S_original_order(), So)
+    et = abs(float(dp.trace.cpu()[0]) - np.trace(So)) / abs(np.trace(So))
+    say(f"dense Q{degree}: X^T Z rel {eS:.2e}, trace rel {et:.2e}")
+    assert eS <= TOL64 and et <= TOL64

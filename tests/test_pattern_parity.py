@@ -146,3 +146,29 @@ def test_node_points_and_curved_qp_points_match_the_oracle(degree):
     q_or = oc.qp_points()[lin]
     assert np.abs(q_lib - q_or).max() <= 1e-13 * max(ms.L)
     assert np.abs(q_lib - om.qp_points()[lin]).max() > 1e-3   # the map did bend the cells
+
+
+@pytest.mark.parametrize("radius,closure", [(2.0, False), (3.0, False), (2.0, True)])
+def test_dense_row_blocks_become_tasks(radius, closure):
+    """The overlap's densely populated row blocks (16 to 1024 block pairs,
+    at most 128 columns on either side) run as one task each and every other
+    (row block, C1, C2) product as a unit: the counts follow from the pattern."""
+    sizes = [8, 5, 12, 4, 16, 7, 9, 3, 11, 6, 10, 9, 14, 2, 13, 11]
+    ms = synth.MeshSpec(8, 6, 4, (8.0, 6.0, 4.0), 2, 0x3F)
+    wl = synth.custom_workload(ms, sum(sizes), radius, 5, potential="wells", name="dense")
+    wl.colblock_sizes = np.asarray(sizes, dtype=np.int32)
+    mesh = Mesh(ms.nx, ms.ny, ms.nz, ms.L, ms.degree, ms.dirichlet)
+    x = Layout(mesh, wl.centres, wl.radius, wl.colblock_sizes)
+    y = x.closure() if closure else x
+    px, py = x.pattern(), y.pattern()
+    w = np.diff(px["col_block_start"])
+    tasks = units = 0
+    for r in range(len(px["rowptr"]) - 1):
+        ca = px["colidx"][px["rowptr"][r]:px["rowptr"][r + 1]]
+        cb = py["colidx"][py["rowptr"][r]:py["rowptr"][r + 1]]
+        if 16 <= len(ca) * len(cb) <= 1024 and w[ca].sum() <= 128 and w[cb].sum() <= 128:
+            tasks += 1
+        else:
+            units += len(ca) * len(cb)
+    assert tasks > 0
+    assert y.info["tm_tasks"] == tasks and y.info["tm_units"] == units
