@@ -695,6 +695,9 @@ int mfb_tmmult(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d
   t.cb_of_col = (const int32_t*)(mb + mv->lay.off_cb_of_col);
   t.cb_start = (const int32_t*)(mb + mv->lay.off_cb_start);
   t.s2 = (const mfb::S2Desc*)(mb + mv->lay.off_s2);
+  t.max_pair_parts = 0;
+  for (size_t i = 0; i + 1 < p.pair_ptr.size(); ++i)
+    t.max_pair_parts = std::max<int64_t>(t.max_pair_parts, p.pair_ptr[i + 1] - p.pair_ptr[i]);
   t.M = p.M;
   t.ncb = p.ncb;
 

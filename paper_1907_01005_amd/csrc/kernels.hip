@@ -1142,8 +1142,10 @@ __global__ __launch_bounds__(64 * NW) void tm_task_kernel(TmParams p, int64_t fi
   dispatch_count<0, kNT>(nt, main_loop);
 }
 
-__global__ __launch_bounds__(256) void tm_stage2_kernel(TmParams p) {
-  __shared__ double red[256];
+// NT threads per block of S: 256, or 1024 where some pair has many partials.
+template <int NT>
+__global__ __launch_bounds__(NT) void tm_stage2_kernel(TmParams p) {
+  __shared__ double red[NT];
   const int t = threadIdx.x;
   const S2Desc d = p.s2[blockIdx.x];
   const int E = d.w1 * d.w2;
@@ -1151,7 +1153,7 @@ __global__ __launch_bounds__(256) void tm_stage2_kernel(TmParams p) {
     if (t < E) p.S[(int64_t)(d.c1 + t / d.w2) * p.M + (d.c2 + t % d.w2)] = 0.0;
     return;
   }
-  const int G = 256 / E;
+  const int G = NT / E;
   const int g = t / E, e = t - g * E;
   double sum = 0.0;
   if (g < G) {
@@ -2092,16 +2094,19 @@ int launch_tmmult(const TmParams& p, void* stream) {
       const int64_t nwg = ((n + 7) / 8) * 8;
       hipLaunchKernelGGL(kernel, dim3((unsigned)nwg), dim3(threads), 0, st, p, lo, n);
     };
-    launch_tasks(tm_task_kernel<64, 4>, 0, 256);
-    launch_tasks(tm_task_kernel<96, 4>, 1, 256);
-    launch_tasks(tm_task_kernel<128, 8>, 2, 512);
+    launch_tasks(tm_task_kernel<64, 8>, 0, 512);
+    launch_tasks(tm_task_kernel<96, 8>, 1, 512);
+    launch_tasks(tm_task_kernel<128, 16>, 2, 1024);
   }
   {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
   }
   const int64_t nblk = (int64_t)p.ncb * p.ncb;
-  hipLaunchKernelGGL(tm_stage2_kernel, dim3((unsigned)nblk), dim3(256), 0, st, p);
+  if (p.max_pair_parts > 512)
+    hipLaunchKernelGGL(tm_stage2_kernel<1024>, dim3((unsigned)nblk), dim3(1024), 0, st, p);
+  else
+    hipLaunchKernelGGL(tm_stage2_kernel<256>, dim3((unsigned)nblk), dim3(256), 0, st, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
   hipLaunchKernelGGL(tm_trace_kernel, dim3(1), dim3(256), 0, st, p);

@@ -56,6 +56,7 @@ struct TmParams {
   const int32_t* cb_of_col;  // [M]
   const int32_t* cb_start;   // [ncb+1]
   const S2Desc* s2;          // [ncb*ncb] blocks of S for the second stage
+  int64_t max_pair_parts;    // most partial products of one pair
   int32_t M, ncb;
   double* S;
   double* trace;

@@ -177,7 +177,7 @@ void plan_mv(MvPlan& mv, const MeshPlan& m, int M, const double* centers, const 
 // Row blocks with at least kTaskMinPairs and at most kTaskMaxPairs block
 // pairs, and no more than kTaskMaxWidth columns on either side, become tasks.
 constexpr int kTaskMinPairs = 16;
-constexpr int kTaskMaxPairs = 1024;
+constexpr int kTaskMaxPairs = 512;
 constexpr int kTaskMaxWidth = 128;
 
 // Overlap plan (units, tasks, pairs, S-block descriptors) of S = A^T B into mv.
