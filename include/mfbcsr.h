@@ -355,7 +355,10 @@ int mfb_mv_dot(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d
  * d_S: M*M doubles, fully written (entries outside the product pattern are
  * exactly 0); d_trace: one double; d_work: info.work_bytes of scratch for the
  * per-row-block partial products, which are summed in a fixed order (the
- * result is bitwise reproducible).  Errors: ESTATE (not bound), EHIP.       */
+ * result is bitwise reproducible).  Densely populated row blocks
+ * (info.tm_tasks) compute all their block products at once; the partial
+ * products and their order of summation are the same.  Errors: ESTATE (not
+ * bound), EHIP.                                                              */
 int mfb_tmmult(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d_S,
                double* d_trace, void* d_work, void* stream);
 

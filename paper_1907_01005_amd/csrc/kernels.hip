@@ -1182,18 +1182,15 @@ __global__ __launch_bounds__(NT) void tm_stage2_kernel(TmParams p) {
     p.S[(int64_t)(d.c1 + a) * p.M + (d.c2 + b)] = tot;
   }
 }
-__global__ __launch_bounds__(256) void tm_trace_kernel(TmParams p) {
-  __shared__ double red[256];
-  const int t = threadIdx.x;
+// One wave: lane l sums S[a][a] for a = l, l + 64, ... in order, then an xor
+// butterfly across the wave (a fixed order, so the trace is repeatable).
+__global__ __launch_bounds__(64) void tm_trace_kernel(TmParams p) {
+  const int l = threadIdx.x;
   double d = 0.0;
-  for (int al = t; al < p.M; al += 256) d += p.S[(int64_t)al * p.M + al];
-  red[t] = d;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (t < h) red[t] += red[t + h];
-    __syncthreads();
-  }
-  if (t == 0) *p.trace = red[0];
+  for (int a = l; a < p.M; a += 64) d += p.S[(int64_t)a * p.M + a];
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) d += shfl_xor_d(d, m);
+  if (l == 0) *p.trace = d;
 }
 
 // Shell items: batches whose own block is not stored for C.  One wave reads
@@ -2109,7 +2106,7 @@ int launch_tmmult(const TmParams& p, void* stream) {
     hipLaunchKernelGGL(tm_stage2_kernel<256>, dim3((unsigned)nblk), dim3(256), 0, st, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
-  hipLaunchKernelGGL(tm_trace_kernel, dim3(1), dim3(256), 0, st, p);
+  hipLaunchKernelGGL(tm_trace_kernel, dim3(1), dim3(64), 0, st, p);
   return (int)hipGetLastError();
 }
 

@@ -482,7 +482,7 @@ void plan_overlap(MvPlan& mv, const MvPlan& A, const MvPlan& B, const MeshPlan& 
     for (int64_t k1 = A.rowptr[r]; k1 < A.rowptr[r + 1]; ++k1) wa += w[A.colidx[k1]];
     for (int64_t k2 = B.rowptr[r]; k2 < B.rowptr[r + 1]; ++k2) wb += w[B.colidx[k2]];
     if (ka * kb >= kTaskMinPairs && ka * kb <= kTaskMaxPairs && wa <= kTaskMaxWidth &&
-        wb <= kTaskMaxWidth) {
+        wb <= kTaskMaxWidth && rows <= kTaskMaxRows) {
       // the whole row block as one task; partial slots as the units would have them
       TmTask T;
       T.a_first = (int64_t)mv.task_blk.size();

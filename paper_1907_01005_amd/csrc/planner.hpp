@@ -175,10 +175,14 @@ void plan_mv(MvPlan& mv, const MeshPlan& m, int M, const double* centers, const 
              int radius_count, int ncolblocks, const int32_t* sizes, int B, int col_order);
 
 // Row blocks with at least kTaskMinPairs and at most kTaskMaxPairs block
-// pairs, and no more than kTaskMaxWidth columns on either side, become tasks.
+// pairs, no more than kTaskMaxWidth columns on either side and at most
+// kTaskMaxRows rows become tasks.  A task walks its rows in a chain of
+// 16-row chunks, so longer row blocks stay with the units, which spread
+// their rows over the lanes.
 constexpr int kTaskMinPairs = 16;
 constexpr int kTaskMaxPairs = 512;
 constexpr int kTaskMaxWidth = 128;
+constexpr int kTaskMaxRows = 128;
 
 // Overlap plan (units, tasks, pairs, S-block descriptors) of S = A^T B into mv.
 void plan_overlap(MvPlan& mv, const MvPlan& A, const MvPlan& B, const MeshPlan& m);

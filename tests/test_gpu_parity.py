@@ -262,11 +262,12 @@ DENSE_SIZES = [8, 5, 12, 4, 16, 7, 9, 3, 11, 6, 10, 9, 14, 2, 13, 11]
 @pytest.mark.parametrize("degree,cells,radius", [(1, (8, 6, 4), 2.0), (2, (8, 6, 4), 2.0),
                                                  (3, (6, 4, 4), 2.5), (4, (4, 4, 4), 2.0)])
 def test_dense_row_blocks(degree, cells, radius):
-    """Row blocks with many stored blocks: their overlap products run as one
-    task each (all three width classes; rows in one chunk at Q1, up to 46
-    chunks at Q4, ragged), beside units for sparse rows and for rows wider than
-    a task.  S = X^T (H X) against the oracle, then S = X^T Z for generic Z
-    on X's pattern against the oracle's X^T Z."""
+    """Row blocks with many stored blocks: at Q1 and Q2 their overlap products
+    run as one task each (all three width classes; rows in one chunk at Q1,
+    up to 7 chunks at Q2, ragged), beside units for sparse rows and for rows
+    wider than a task.  At Q3 and Q4 the row blocks are longer than a task
+    takes and every product is a unit.  S = X^T (H X) against the oracle,
+    then S = X^T Z for generic Z on X's pattern against the oracle's X^T Z."""
     import scipy.sparse as sp
     import torch
     from oracle.apply import overlap as oracle_overlap
@@ -274,7 +275,7 @@ def test_dense_row_blocks(degree, cells, radius):
     say(f"dense row blocks Q{degree} {cells} r={radius}")
     op = OracleProblem(wl)
     dp = device_problem(wl)
-    assert dp.layout.info["tm_tasks"] > 0
+    assert (dp.layout.info["tm_tasks"] > 0) == (degree <= 2)
     dp.set_X_coo(op.node, op.orb, op.val)
     _check_full(wl, op, dp, 0, TOL64)
     node, orb = dp.layout.entry_coords()

@@ -151,8 +151,9 @@ def test_node_points_and_curved_qp_points_match_the_oracle(degree):
 @pytest.mark.parametrize("radius,closure", [(2.0, False), (3.0, False), (2.0, True)])
 def test_dense_row_blocks_become_tasks(radius, closure):
     """The overlap's densely populated row blocks (16 to 512 block pairs,
-    at most 128 columns on either side) run as one task each and every other
-    (row block, C1, C2) product as a unit: the counts follow from the pattern."""
+    at most 128 columns on either side, at most 128 rows) run as one task each and every other
+    (row block, C1, C2) product as a unit: the counts follow from the pattern.
+    Row blocks longer than 128 rows stay units."""
     sizes = [8, 5, 12, 4, 16, 7, 9, 3, 11, 6, 10, 9, 14, 2, 13, 11]
     ms = synth.MeshSpec(8, 6, 4, (8.0, 6.0, 4.0), 2, 0x3F)
     wl = synth.custom_workload(ms, sum(sizes), radius, 5, potential="wells", name="dense")
@@ -163,10 +164,12 @@ def test_dense_row_blocks_become_tasks(radius, closure):
     px, py = x.pattern(), y.pattern()
     w = np.diff(px["col_block_start"])
     tasks = units = 0
+    rows = np.diff(px["row_block_start"])
     for r in range(len(px["rowptr"]) - 1):
         ca = px["colidx"][px["rowptr"][r]:px["rowptr"][r + 1]]
         cb = py["colidx"][py["rowptr"][r]:py["rowptr"][r + 1]]
-        if 16 <= len(ca) * len(cb) <= 512 and w[ca].sum() <= 128 and w[cb].sum() <= 128:
+        if (16 <= len(ca) * len(cb) <= 512 and w[ca].sum() <= 128 and w[cb].sum() <= 128
+                and rows[r] <= 128):
             tasks += 1
         else:
             units += len(ca) * len(cb)
