@@ -541,6 +541,10 @@ void plan_overlap(MvPlan& mv, const MvPlan& A, const MvPlan& B, const MeshPlan& 
       d.w1 = w[C1];
       d.w2 = w[C2];
     }
+  // longest sums first: the workgroups start in this order, so the blocks
+  // with the most partials do not end up last on a busy CU
+  std::stable_sort(mv.s2.begin(), mv.s2.end(),
+                   [](const S2Desc& x, const S2Desc& y) { return x.n > y.n; });
   // one overlap kernel per class, each with its own thread count and
   // register budget
   auto tm_class = [](const TmUnit& u) {

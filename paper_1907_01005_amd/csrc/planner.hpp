@@ -156,7 +156,7 @@ struct MvPlan {
   std::array<int64_t, 3> task_class_end{};
   std::vector<TaskBlk> task_blk;
   std::vector<int64_t> task_part;
-  std::vector<S2Desc> s2;            // [ncb*ncb] blocks of S
+  std::vector<S2Desc> s2;            // [ncb*ncb] blocks of S, most partials first
   int64_t part_doubles = 0;
   std::vector<int32_t> pair_tab;     // ncb*ncb -> pair id or -1
   std::vector<int32_t> pair_ptr;     // npairs + 1: prefix count of partial products per pair
