@@ -1010,18 +1010,20 @@ __device__ __forceinline__ void dispatch_count(int n, F& f) {
   }
 }
 
-// Stage 1 for densely populated row blocks (the planner's tasks): all block
-// products of row block r at once, C = X_r^T Y_r with X_r (rows x wa) and
-// Y_r (rows x wb) the row block's stored blocks side by side, on the fp64
-// matrix cores.  Chunks of 16 rows of X_r and Y_r go through LDS, double
-// buffered: the next chunk's loads are in flight while the current chunk's
-// products run.  Column c < wa + wb of [X_r | Y_r], whose rows lie w apart
-// in its block, is copied by thread c (and by c + 256 for every other row
-// with eight waves).  C is cut into 16x16 tiles and wave w of NW takes the
-// w-th contiguous share of them in row-major order.  Entry
-// (a, b) of C belongs to the block pair (i, j) holding columns a and b and
-// goes to that pair's partial slot, the one a unit would have written, so
-// the second stage serves both.  The sum over rows has a fixed order.
+// Stage 1 for runs of densely populated row blocks (the planner's tasks):
+// all block products of the run at once, C = X^T Y with X (rows x wa) and Y
+// (rows x wb) the run's rows over the union of its column blocks (zero where
+// a row block does not store a block), on the fp64 matrix cores.  Chunks of
+// 16 rows of X and Y go through LDS, double buffered: the next chunk's
+// loads are in flight while the current chunk's products run.  Column
+// c < wa + wb of [X | Y], whose rows lie w apart in its block, is copied by
+// thread c (and by c + 256, ... for the other rows of the chunk with more
+// than four waves).  C is cut into 16x16 tiles and wave w of NW takes the
+// w-th contiguous share of them in row-major order.  Entry (a, b) of C
+// belongs to the block pair (i, j) holding columns a and b and goes to that
+// pair's partial slot for the run; pairs that meet in no row block of the
+// run are dropped.  Units and tasks share the partial layout, so the second
+// stage serves both.  The sum over rows has a fixed order.
 template <int WMAX, int NW>
 __global__ __launch_bounds__(64 * NW) void tm_task_kernel(TmParams p, int64_t first, int64_t count) {
   constexpr int kRC = 16;                                // rows per chunk
@@ -1031,7 +1033,7 @@ __global__ __launch_bounds__(64 * NW) void tm_task_kernel(TmParams p, int64_t fi
   constexpr int kG = NW / 4;                             // threads per copied column
   constexpr int kRG = kRC / kG;                          // rows each of them copies
   __shared__ double st[2 * kStage];
-  __shared__ int64_t boff[2][WMAX];
+  __shared__ int64_t boff[2][kTaskMaxSeg][WMAX];
   __shared__ int16_t bcol[2][WMAX], bw[2][WMAX], cblk[2][WMAX];
   __shared__ int64_t tpart[kTaskMaxPairs];
   const int t = threadIdx.x, l = t & 63, col = l & 15, kr = l >> 4;
@@ -1041,11 +1043,12 @@ __global__ __launch_bounds__(64 * NW) void tm_task_kernel(TmParams p, int64_t fi
   const TmTask T = p.tasks[first + task];
   const int rows = T.rows, wa = T.wa, wb = T.wb;
   const int TA = (wa + 15) >> 4, TB = (wb + 15) >> 4;
-  // block tables and the block of every column, per side
+  // block tables (per segment) and the block of every column, per side
   if (t < T.ka || (t >= 128 && t - 128 < T.kb)) {
-    const int s = t >= 128, k = t - 128 * s;
-    const TaskBlk b = p.task_blk[(s ? T.b_first : T.a_first) + k];
-    boff[s][k] = b.off;
+    const int s = t >= 128, k = t - 128 * s, kk = s ? T.kb : T.ka;
+    const int64_t f = s ? T.b_first : T.a_first;
+    const TaskBlk b = p.task_blk[f + k];
+    for (int sg = 0; sg < T.nseg; ++sg) boff[s][sg][k] = p.task_blk[f + (int64_t)sg * kk + k].off;
     bcol[s][k] = (int16_t)b.col;
     bw[s][k] = (int16_t)b.w;
     for (int c = b.col; c < b.col + b.w; ++c) cblk[s][c] = (int16_t)k;
@@ -1058,24 +1061,31 @@ __global__ __launch_bounds__(64 * NW) void tm_task_kernel(TmParams p, int64_t fi
     if (w + c < cp) st[(s >> 1) * kStage + (s & 1) * kRC * kLd + r * kLd + w + c] = 0.0;
   }
   __syncthreads();
-  // this thread's column of [X_r | Y_r] (rows g, g + kG, ... of each chunk)
+  // this thread's column of [X | Y] (rows g, g + kG, ... of each chunk)
   const int fcol = t & 255, g = t >> 8;
   const bool fc = fcol < wa + wb;
   const int sd = fcol >= wa, cx = sd ? fcol - wa : fcol;
-  const double* __restrict__ src = p.X;
-  int sw = 0, dst = 0;
+  const double* __restrict__ src = sd ? p.Y : p.X;
+  const int64_t* __restrict__ sboff = &boff[sd][0][0];
+  int sw = 0, dst = 0, kc = 0;
   if (fc) {
     const int k = cblk[sd][cx];
-    src = (sd ? p.Y : p.X) + boff[sd][k] + (cx - bcol[sd][k]);
+    src += cx - bcol[sd][k];
     sw = bw[sd][k];
     dst = sd * kRC * kLd + cx;
+    kc = k;
   }
   double v[kRG];
   auto load = [&](int i0) {
 #pragma unroll
     for (int r = 0; r < kRG; ++r) {
       const int i = i0 + g + kG * r;
-      v[r] = (fc && i < rows) ? src[(int64_t)i * sw] : 0.0;
+      // segment of row i (seg_start[s] = rows for s >= nseg); the block's
+      // offset there comes from LDS, -1 where the row block lacks it
+      const int sg = (i >= T.seg_start[1]) + (i >= T.seg_start[2]) + (i >= T.seg_start[3]);
+      const int64_t o = (fc && i < rows) ? sboff[sg * WMAX + kc] : -1;
+      const int ss = sg == 0 ? 0 : sg == 1 ? T.seg_start[1] : sg == 2 ? T.seg_start[2] : T.seg_start[3];
+      v[r] = o >= 0 ? src[o + (int64_t)(i - ss) * sw] : 0.0;
     }
   };
   auto store = [&](int s) {
@@ -1133,7 +1143,8 @@ __global__ __launch_bounds__(64 * NW) void tm_task_kernel(TmParams p, int64_t fi
           const int a = 16 * ta + kr + 4 * r;
           if (a < wa) {
             const int i = cblk[0][a];
-            p.part[tpart[i * T.kb + j] + (a - bcol[0][i]) * wj + lb] = acc[q][r];
+            const int64_t slot = tpart[i * T.kb + j];
+            if (slot >= 0) p.part[slot + (a - bcol[0][i]) * wj + lb] = acc[q][r];
           }
         }
       }

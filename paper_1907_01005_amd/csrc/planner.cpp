@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <iterator>
 #include <numeric>
 
 namespace mfb {
@@ -443,25 +444,114 @@ void plan_overlap(MvPlan& mv, const MvPlan& A, const MvPlan& B, const MeshPlan& 
   for (int C = 0; C < ncb; ++C) w[C] = A.cb_start[C + 1] - A.cb_start[C];
   mv.units.clear();
   mv.pair_tab.assign((size_t)ncb * ncb, -1);
-  std::vector<int64_t> pair_count;
+  int npairs = 0;
   for (int r = 0; r < nbt; ++r)
     for (int64_t k1 = A.rowptr[r]; k1 < A.rowptr[r + 1]; ++k1)
       for (int64_t k2 = B.rowptr[r]; k2 < B.rowptr[r + 1]; ++k2) {
         int32_t& pid = mv.pair_tab[(size_t)A.colidx[k1] * ncb + B.colidx[k2]];
-        if (pid < 0) {
-          pid = (int32_t)pair_count.size();
-          pair_count.push_back(0);
-        }
-        ++pair_count[pid];
+        if (pid < 0) pid = npairs++;
       }
-  const int npairs = (int)pair_count.size();
   std::vector<int32_t> pair_c1(npairs), pair_c2(npairs);
   for (int C1 = 0; C1 < ncb; ++C1)
     for (int C2 = 0; C2 < ncb; ++C2) {
       const int32_t pid = mv.pair_tab[(size_t)C1 * ncb + C2];
       if (pid >= 0) { pair_c1[pid] = C1; pair_c2[pid] = C2; }
     }
-  // pair_ptr: first unit slot of each pair; pair_list[pid] = partial base
+
+  // Tasks: runs of up to kTaskMaxSeg consecutive densely populated row blocks
+  // over the union of their column blocks.  A row block qualifies on its own
+  // (pairs, widths, rows); a run grows while the union stays within the
+  // task limits and costs at most kTaskMaxWaste times the members' products.
+  auto rows_of = [&](int r) { return (int64_t)(m.rb_start[r + 1] - m.rb_start[r]); };
+  auto width = [&](const std::vector<int32_t>& cs) {
+    int64_t s = 0;
+    for (int C : cs) s += w[C];
+    return s;
+  };
+  auto blocks = [&](const MvPlan& L, int r) {
+    return std::vector<int32_t>(L.colidx.begin() + L.rowptr[r], L.colidx.begin() + L.rowptr[r + 1]);
+  };
+  auto qualifies = [&](int r) {
+    const int64_t ka = A.rowptr[r + 1] - A.rowptr[r], kb = B.rowptr[r + 1] - B.rowptr[r];
+    return ka * kb >= kTaskMinPairs && ka * kb <= kTaskMaxPairs &&
+           width(blocks(A, r)) <= kTaskMaxWidth && width(blocks(B, r)) <= kTaskMaxWidth &&
+           rows_of(r) <= kTaskMaxRows;
+  };
+  // widths of the task kernel classes: a run stays in its widest member's
+  auto task_width_cap = [](int64_t wmax) -> int64_t { return wmax <= 64 ? 64 : (wmax <= 96 ? 96 : 128); };
+  auto merged = [](const std::vector<int32_t>& x, const std::vector<int32_t>& y) {
+    std::vector<int32_t> u;
+    std::set_union(x.begin(), x.end(), y.begin(), y.end(), std::back_inserter(u));
+    return u;
+  };
+  std::vector<int32_t> run_len(nbt, 0);  // > 0 at the first row block of a run
+  for (int r = 0; r < nbt;) {
+    if (!qualifies(r)) { ++r; continue; }
+    std::vector<int32_t> ua = blocks(A, r), ub = blocks(B, r);
+    int64_t rows = rows_of(r);
+    double own = (double)rows * width(ua) * width(ub);
+    int64_t wcap = task_width_cap(std::max(width(ua), width(ub)));
+    int len = 1;
+    while (len < kTaskMaxSeg && r + len < nbt && qualifies(r + len)) {
+      const int q = r + len;
+      std::vector<int32_t> na = merged(ua, blocks(A, q)), nb = merged(ub, blocks(B, q));
+      const int64_t nrows = rows + rows_of(q);
+      const double nown = own + (double)rows_of(q) * width(blocks(A, q)) * width(blocks(B, q));
+      const int64_t ncap =
+          std::max(wcap, task_width_cap(std::max(width(blocks(A, q)), width(blocks(B, q)))));
+      if (width(na) > ncap || width(nb) > ncap ||
+          (int64_t)na.size() * (int64_t)nb.size() > kTaskMaxPairs || nrows > kTaskMaxRunRows ||
+          (double)nrows * width(na) * width(nb) > kTaskMaxWaste * nown)
+        break;
+      ua.swap(na);
+      ub.swap(nb);
+      rows = nrows;
+      own = nown;
+      wcap = ncap;
+      ++len;
+    }
+    run_len[r] = len;
+    r += len;
+  }
+  // the union blocks of a run and which of their pairs meet in some member
+  struct Run {
+    std::vector<int32_t> ua, ub;
+    std::vector<char> meet;  // [ua.size()][ub.size()]
+  };
+  auto run_of = [&](int r) {
+    Run R;
+    for (int q = r; q < r + run_len[r]; ++q) {
+      R.ua = merged(R.ua, blocks(A, q));
+      R.ub = merged(R.ub, blocks(B, q));
+    }
+    R.meet.assign(R.ua.size() * R.ub.size(), 0);
+    for (int q = r; q < r + run_len[r]; ++q)
+      for (int64_t k1 = A.rowptr[q]; k1 < A.rowptr[q + 1]; ++k1)
+        for (int64_t k2 = B.rowptr[q]; k2 < B.rowptr[q + 1]; ++k2) {
+          const size_t i = std::lower_bound(R.ua.begin(), R.ua.end(), A.colidx[k1]) - R.ua.begin();
+          const size_t j = std::lower_bound(R.ub.begin(), R.ub.end(), B.colidx[k2]) - R.ub.begin();
+          R.meet[i * R.ub.size() + j] = 1;
+        }
+    return R;
+  };
+
+  // one partial per (unit) and per (run, pair meeting in it)
+  std::vector<int64_t> pair_count(npairs, 0);
+  for (int r = 0; r < nbt;) {
+    if (run_len[r] > 0) {
+      const Run R = run_of(r);
+      for (size_t i = 0; i < R.ua.size(); ++i)
+        for (size_t j = 0; j < R.ub.size(); ++j)
+          if (R.meet[i * R.ub.size() + j]) ++pair_count[mv.pair_tab[(size_t)R.ua[i] * ncb + R.ub[j]]];
+      r += run_len[r];
+      continue;
+    }
+    for (int64_t k1 = A.rowptr[r]; k1 < A.rowptr[r + 1]; ++k1)
+      for (int64_t k2 = B.rowptr[r]; k2 < B.rowptr[r + 1]; ++k2)
+        ++pair_count[mv.pair_tab[(size_t)A.colidx[k1] * ncb + B.colidx[k2]]];
+    ++r;
+  }
+  // pair_ptr: first slot of each pair; pair_list[pid] = partial base
   mv.pair_ptr.assign(npairs + 1, 0);
   mv.pair_list.assign(npairs, 0);
   int64_t part = 0;
@@ -475,44 +565,55 @@ void plan_overlap(MvPlan& mv, const MvPlan& A, const MvPlan& B, const MeshPlan& 
   mv.tasks.clear();
   mv.task_blk.clear();
   mv.task_part.clear();
-  for (int r = 0; r < nbt; ++r) {
-    const int64_t rows = m.rb_start[r + 1] - m.rb_start[r];
-    const int64_t ka = A.rowptr[r + 1] - A.rowptr[r], kb = B.rowptr[r + 1] - B.rowptr[r];
-    int32_t wa = 0, wb = 0;
-    for (int64_t k1 = A.rowptr[r]; k1 < A.rowptr[r + 1]; ++k1) wa += w[A.colidx[k1]];
-    for (int64_t k2 = B.rowptr[r]; k2 < B.rowptr[r + 1]; ++k2) wb += w[B.colidx[k2]];
-    if (ka * kb >= kTaskMinPairs && ka * kb <= kTaskMaxPairs && wa <= kTaskMaxWidth &&
-        wb <= kTaskMaxWidth && rows <= kTaskMaxRows) {
-      // the whole row block as one task; partial slots as the units would have them
-      TmTask T;
-      T.a_first = (int64_t)mv.task_blk.size();
-      int32_t col = 0;
-      for (int64_t k1 = A.rowptr[r]; k1 < A.rowptr[r + 1]; ++k1) {
-        mv.task_blk.push_back(TaskBlk{A.block_offset[k1], col, w[A.colidx[k1]]});
-        col += w[A.colidx[k1]];
-      }
-      T.b_first = (int64_t)mv.task_blk.size();
-      col = 0;
-      for (int64_t k2 = B.rowptr[r]; k2 < B.rowptr[r + 1]; ++k2) {
-        mv.task_blk.push_back(TaskBlk{B.block_offset[k2], col, w[B.colidx[k2]]});
-        col += w[B.colidx[k2]];
-      }
-      T.p_first = (int64_t)mv.task_part.size();
-      for (int64_t k1 = A.rowptr[r]; k1 < A.rowptr[r + 1]; ++k1)
-        for (int64_t k2 = B.rowptr[r]; k2 < B.rowptr[r + 1]; ++k2) {
-          const int C1 = A.colidx[k1], C2 = B.colidx[k2];
-          const int32_t pid = mv.pair_tab[(size_t)C1 * ncb + C2];
-          mv.task_part.push_back(mv.pair_list[pid] + fill[pid]++ * (int64_t)w[C1] * w[C2]);
+  for (int r = 0; r < nbt;) {
+    if (run_len[r] > 0) {
+      // the run as one task; task_blk holds [segment][union block] per side
+      // (offset -1 where the member does not store the block)
+      const Run R = run_of(r);
+      const int ns = run_len[r];
+      TmTask T{};
+      T.ka = (int32_t)R.ua.size();
+      T.kb = (int32_t)R.ub.size();
+      T.nseg = ns;
+      T.seg_start[0] = 0;
+      for (int sgi = 0; sgi < ns; ++sgi)
+        T.seg_start[sgi + 1] = T.seg_start[sgi] + (int32_t)rows_of(r + sgi);
+      for (int sgi = ns + 1; sgi <= kTaskMaxSeg; ++sgi) T.seg_start[sgi] = T.seg_start[ns];
+      T.rows = T.seg_start[ns];
+      auto side = [&](const MvPlan& L, const std::vector<int32_t>& u, int32_t& wsum) {
+        const int64_t first = (int64_t)mv.task_blk.size();
+        for (int sgi = 0; sgi < ns; ++sgi) {
+          const int q = r + sgi;
+          int32_t col = 0;
+          for (int C : u) {
+            const int32_t* b = std::lower_bound(L.colidx.data() + L.rowptr[q],
+                                                L.colidx.data() + L.rowptr[q + 1], C);
+            const bool has = b != L.colidx.data() + L.rowptr[q + 1] && *b == C;
+            const int64_t off = has ? L.block_offset[b - L.colidx.data()] : -1;
+            mv.task_blk.push_back(TaskBlk{off, col, w[C]});
+            col += w[C];
+          }
+          wsum = col;
         }
-      T.rows = (int32_t)rows;
-      T.ka = (int32_t)ka;
-      T.kb = (int32_t)kb;
-      T.wa = wa;
-      T.wb = wb;
-      T.pad = 0;
+        return first;
+      };
+      T.a_first = side(A, R.ua, T.wa);
+      T.b_first = side(B, R.ub, T.wb);
+      T.p_first = (int64_t)mv.task_part.size();
+      for (size_t i = 0; i < R.ua.size(); ++i)
+        for (size_t j = 0; j < R.ub.size(); ++j) {
+          if (!R.meet[i * R.ub.size() + j]) {
+            mv.task_part.push_back(-1);
+            continue;
+          }
+          const int32_t pid = mv.pair_tab[(size_t)R.ua[i] * ncb + R.ub[j]];
+          mv.task_part.push_back(mv.pair_list[pid] + fill[pid]++ * (int64_t)w[R.ua[i]] * w[R.ub[j]]);
+        }
       mv.tasks.push_back(T);
+      r += ns;
       continue;
     }
+    const int64_t rows = rows_of(r);
     for (int64_t k1 = A.rowptr[r]; k1 < A.rowptr[r + 1]; ++k1)
       for (int64_t k2 = B.rowptr[r]; k2 < B.rowptr[r + 1]; ++k2) {
         const int C1 = A.colidx[k1], C2 = B.colidx[k2];
@@ -528,6 +629,7 @@ void plan_overlap(MvPlan& mv, const MvPlan& A, const MvPlan& B, const MeshPlan& 
         u.pad = 0;
         mv.units.push_back(u);
       }
+    ++r;
   }
   mv.s2.assign((size_t)ncb * ncb, S2Desc{0, 0, 0, 0, 0, 0, 0});
   for (int C1 = 0; C1 < ncb; ++C1)

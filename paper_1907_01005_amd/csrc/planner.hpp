@@ -114,18 +114,24 @@ struct S2Desc {
 };
 static_assert(sizeof(S2Desc) == 32, "S2Desc layout");
 
-// A densely populated row block of Alg. 8 as one task: every product
-// X_{r,C1}^T Y_{r,C2} of its blocks at once, X_r and Y_r read once.  Its
-// blocks are task_blk[a_first .. a_first + ka) (of A) and [b_first ..
-// b_first + kb) (of B); the partial of pair (i, j) goes to
-// task_part[p_first + i kb + j].
+// A run of densely populated row blocks of Alg. 8 as one task: every
+// product X_{r,C1}^T Y_{r,C2} of its row blocks at once, over the union of
+// their column blocks (ka on the X side, kb on the Y side), X and Y read
+// once.  Segment s covers task rows [seg_start[s], seg_start[s + 1]), row
+// block r0 + s.  The blocks of segment s are task_blk[a_first + s ka + i]
+// (X side) and task_blk[b_first + s kb + j] (Y side), offset -1 where that
+// row block does not store the block.  The partial of union pair (i, j) goes
+// to task_part[p_first + i kb + j], -1 where the pair meets in no member.
+constexpr int kTaskMaxSeg = 4;
 struct TmTask {
   int64_t a_first, b_first, p_first;
-  int32_t rows, ka, kb, wa, wb, pad;
+  int32_t rows, ka, kb, wa, wb, nseg;
+  int32_t seg_start[kTaskMaxSeg + 1];
+  int32_t pad;
 };
-static_assert(sizeof(TmTask) == 48, "TmTask layout");
+static_assert(sizeof(TmTask) == 72, "TmTask layout");
 struct TaskBlk {
-  int64_t off;  // value offset of the block
+  int64_t off;  // value offset of the block, -1 if not stored in this segment
   int32_t col;  // first column within the task's columns
   int32_t w;    // block width
 };
@@ -176,13 +182,18 @@ void plan_mv(MvPlan& mv, const MeshPlan& m, int M, const double* centers, const 
 
 // Row blocks with at least kTaskMinPairs and at most kTaskMaxPairs block
 // pairs, no more than kTaskMaxWidth columns on either side and at most
-// kTaskMaxRows rows become tasks.  A task walks its rows in a chain of
+// kTaskMaxRows rows qualify for tasks.  A task walks its rows in a chain of
 // 16-row chunks, so longer row blocks stay with the units, which spread
-// their rows over the lanes.
+// their rows over the lanes.  Runs of qualifying row blocks are merged while
+// the union stays within the pair limit, kTaskMaxRunRows rows and the width
+// class (64, 96, 128 columns) of its widest member, and its products cost at
+// most kTaskMaxWaste times the members' own.
 constexpr int kTaskMinPairs = 16;
 constexpr int kTaskMaxPairs = 512;
 constexpr int kTaskMaxWidth = 128;
 constexpr int kTaskMaxRows = 128;
+constexpr int kTaskMaxRunRows = 256;
+constexpr double kTaskMaxWaste = 1.25;
 
 // Overlap plan (units, tasks, pairs, S-block descriptors) of S = A^T B into mv.
 void plan_overlap(MvPlan& mv, const MvPlan& A, const MvPlan& B, const MeshPlan& m);

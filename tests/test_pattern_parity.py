@@ -150,10 +150,15 @@ def test_node_points_and_curved_qp_points_match_the_oracle(degree):
 
 @pytest.mark.parametrize("radius,closure", [(2.0, False), (3.0, False), (2.0, True)])
 def test_dense_row_blocks_become_tasks(radius, closure):
-    """The overlap's densely populated row blocks (16 to 512 block pairs,
-    at most 128 columns on either side, at most 128 rows) run as one task each and every other
-    (row block, C1, C2) product as a unit: the counts follow from the pattern.
-    Row blocks longer than 128 rows stay units."""
+    """The overlap's densely populated row blocks (16 to 512 block pairs, at
+    most 128 columns on either side, at most 128 rows) run as tasks: runs of
+    up to 4 consecutive such row blocks over the union of their column blocks,
+    grown while the union keeps the pair limit, 256 rows and the width class
+    (64, 96, 128 columns) of its widest member, and costs at most 1.25 times
+    the members' own products.  Every other
+    (row block, C1, C2) product is a unit.  One partial per unit and per
+    (run, pair meeting in one of its row blocks): the task count, the unit
+    count and the workspace follow from the pattern."""
     sizes = [8, 5, 12, 4, 16, 7, 9, 3, 11, 6, 10, 9, 14, 2, 13, 11]
     ms = synth.MeshSpec(8, 6, 4, (8.0, 6.0, 4.0), 2, 0x3F)
     wl = synth.custom_workload(ms, sum(sizes), radius, 5, potential="wells", name="dense")
@@ -163,15 +168,46 @@ def test_dense_row_blocks_become_tasks(radius, closure):
     y = x.closure() if closure else x
     px, py = x.pattern(), y.pattern()
     w = np.diff(px["col_block_start"])
-    tasks = units = 0
     rows = np.diff(px["row_block_start"])
-    for r in range(len(px["rowptr"]) - 1):
-        ca = px["colidx"][px["rowptr"][r]:px["rowptr"][r + 1]]
-        cb = py["colidx"][py["rowptr"][r]:py["rowptr"][r + 1]]
-        if (16 <= len(ca) * len(cb) <= 512 and w[ca].sum() <= 128 and w[cb].sum() <= 128
-                and rows[r] <= 128):
-            tasks += 1
-        else:
-            units += len(ca) * len(cb)
+    nr = len(rows)
+    A = [set(px["colidx"][px["rowptr"][r]:px["rowptr"][r + 1]].tolist()) for r in range(nr)]
+    B = [set(py["colidx"][py["rowptr"][r]:py["rowptr"][r + 1]].tolist()) for r in range(nr)]
+    wid = lambda cs: int(sum(w[c] for c in cs))
+
+    def width_class(wmax):
+        return 64 if wmax <= 64 else (96 if wmax <= 96 else 128)
+
+    def qualifies(r):
+        return (16 <= len(A[r]) * len(B[r]) <= 512 and wid(A[r]) <= 128 and wid(B[r]) <= 128
+                and rows[r] <= 128)
+
+    tasks = units = 0
+    parts = 0
+    r = 0
+    while r < nr:
+        if not qualifies(r):
+            units += len(A[r]) * len(B[r])
+            parts += sum(w[a] * w[b] for a in A[r] for b in B[r])
+            r += 1
+            continue
+        ua, ub, nrows = set(A[r]), set(B[r]), int(rows[r])
+        own = nrows * wid(A[r]) * wid(B[r])
+        cap = width_class(max(wid(A[r]), wid(B[r])))
+        n = 1
+        while n < 4 and r + n < nr and qualifies(r + n):
+            q = r + n
+            na, nb = ua | A[q], ub | B[q]
+            mrows = nrows + int(rows[q])
+            mown = own + int(rows[q]) * wid(A[q]) * wid(B[q])
+            mcap = max(cap, width_class(max(wid(A[q]), wid(B[q]))))
+            if (wid(na) > mcap or wid(nb) > mcap or len(na) * len(nb) > 512 or mrows > 256
+                    or mrows * wid(na) * wid(nb) > 1.25 * mown):
+                break
+            ua, ub, nrows, own, cap, n = na, nb, mrows, mown, mcap, n + 1
+        meet = {(a, b) for q in range(r, r + n) for a in A[q] for b in B[q]}
+        parts += sum(w[a] * w[b] for a, b in meet)
+        tasks += 1
+        r += n
     assert tasks > 0
     assert y.info["tm_tasks"] == tasks and y.info["tm_units"] == units
+    assert y.info["work_bytes"] == 256 + 8 * parts
