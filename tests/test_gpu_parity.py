@@ -288,3 +288,34 @@ def test_dense_row_blocks(degree, cells, radius):
     et = abs(float(dp.trace.cpu()[0]) - np.trace(So)) / abs(np.trace(So))
     say(f"dense Q{degree}: X^T Z rel {eS:.2e}, trace rel {et:.2e}")
     assert eS <= TOL64 and et <= TOL64
+
+
+def test_dense_runs_of_row_blocks():
+    """Runs of dense row blocks merged into one task (Q1, 16x12x8 cells, 96
+    orbitals in ragged blocks, support radius 6 cells): about 80 tasks, most
+    over two to four row blocks, many with blocks that one member does not
+    store (zero rows) and a few union pairs that meet in no member (dropped).
+    S = X^T Z for generic Z on X's pattern against the oracle's X^T Z."""
+    import scipy.sparse as sp
+    import torch
+    from oracle.apply import overlap as oracle_overlap
+    sizes = [8, 5, 12, 4, 16, 7, 9, 3, 11, 6, 10, 5]
+    wl = _small((16, 12, 8), 1, sum(sizes), 6.0, 5, sizes=sizes)
+    say("dense runs Q1 16x12x8 r=6")
+    op = OracleProblem(wl)
+    dp = device_problem(wl)
+    pat = dp.layout.pattern()
+    ka = np.diff(pat["rowptr"])
+    qualifying = int(((ka * ka >= 16) & (ka * ka <= 512)).sum())
+    assert 0 < dp.layout.info["tm_tasks"] < qualifying
+    dp.set_X_coo(op.node, op.orb, op.val)
+    _check_full(wl, op, dp, 0, TOL64)
+    node, orb = dp.layout.entry_coords()
+    z = np.random.default_rng(23).standard_normal(len(node))
+    dp.Y[:dp.nvalues].copy_(torch.from_numpy(dp.layout.pack(node, orb, z)))
+    dp.overlap()
+    torch.cuda.synchronize()
+    So = oracle_overlap(op.X_sparse(), sp.csc_matrix((z, (node, orb)), shape=op.X_sparse().shape))
+    eS = rel_fro(dp.S_original_order(), So)
+    say(f"dense runs: X^T Z rel {eS:.2e}")
+    assert eS <= TOL64
