@@ -424,7 +424,8 @@ def main(argv=None):
                    "colblocks": int(len(wl.colblock_sizes)), "radius": wl.radius,
                    "degree": degree, "stored_entries": alg["E"], "prec": args.prec,
                    "kernel": ["grid", "queue"][args.kernel]},
-        "launch": "the K timed steps as one hipGraph (5 kernels per step); eager loop below",
+        "launch": "the K timed steps as one hipGraph (apply_H: zero fill + apply; tmmult: "
+                  "stage-1 classes present in the layout, stage 2, trace); eager loop below",
         "eager": {"value": alg["E"] * args.steps / wall / 1e9, "ms_per_step": wall / args.steps * 1e3},
         "apply_ms_p50": float(np.percentile(t_apply, 50) * 1e3),
         "apply_ms_p99": float(np.percentile(t_apply, 99) * 1e3),
