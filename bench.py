@@ -57,9 +57,27 @@ def algorithmic(dp, degree: int):
             "cell_columns": cell_cols, "active_batches": active_batches}
 
 
-def cpu_baseline(wl, budget_s: float = 12.0):
-    """The oracle's apply + overlap timed on the host cores on a bounded sample."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, budget_s: float = 12.0, one_thread: bool = False):
+    """The oracle's apply + overlap timed on the host cores (or on one thread)
+    on a bounded sample."""
     from oracle.workload import OracleProblem
+    if one_thread:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            rec = cpu_baseline(wl, budget_s)
+        rec["cores"] = 1
+        rec["sample"] = rec["sample"].replace(" s on ", " s on one thread of ")
+        return rec
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
@@ -84,7 +102,7 @@ def cpu_baseline(wl, budget_s: float = 12.0):
             "kind": "oracle",
             "sample": f"oracle masked apply (element matrices built on the fly) over "
                       f"{blocks} of {op.pattern.ncb} column blocks ({entries} stored entries), "
-                      f"{dt:.1f} s on {os.cpu_count()} visible host cores"}
+                      f"{dt:.1f} s on {os.cpu_count()} visible host cores ({cpu_model()})"}
 
 
 def measured_traffic(workload: str, prec: str):
@@ -471,6 +489,7 @@ def main(argv=None):
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)
+        out["cpu_baseline_1thread"] = cpu_baseline(wl, budget_s=5.0, one_thread=True)
     print(json.dumps(out), flush=True)
     return 0
 
