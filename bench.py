@@ -120,6 +120,27 @@ def measured_traffic(workload: str, prec: str):
     return rec.get("apply_H_bytes_per_launch")
 
 
+def copy_bandwidth(mib: int = 1024, reps: int = 5) -> float:
+    """Device-to-device copy rate in GB/s (bytes read + bytes written), the
+    practical HBM ceiling the apply's byte rate is also compared with."""
+    import torch
+    src = torch.ones(mib << 17, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    t = a.elapsed_time(b) * 1e-3 / reps
+    gbs = 2 * src.numel() * 8 / t / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def build_problem(cfg: int, mesh_index: int = 0, radius: float = 0.0, bend: float = 0.0):
     """The seeded workload of configuration `cfg` on the GPU; radius > 0 replaces the
     support radius (same centres, potential and blocks; a different workload); bend > 0
@@ -418,11 +439,15 @@ def main(argv=None):
     else:
         roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": gbs / HBM_PEAK_GBS}
+    copy_gbs = copy_bandwidth()
     roof.update({"traffic": measured_traffic(wl.name, args.prec),
                  "kernel": "apply_H launch (fill_zero_kernel + apply_fused_kernel)",
                  "algorithmic_bytes": alg["bytes"], "algorithmic_flops": alg["flops"],
                  "avg_launch_s": t_ap, "hbm_frac": gbs / HBM_PEAK_GBS,
-                 "alu_frac": tfl / peak_f})
+                 "alu_frac": tfl / peak_f,
+                 # min(P, B I): the roof at this arithmetic intensity
+                 "attainable_frac": tfl / min(peak_f, HBM_PEAK_GBS * alg["flops"] / alg["bytes"] / 1e3),
+                 "copy_gbs": copy_gbs, "hbm_frac_vs_copy": gbs / copy_gbs})
     tm_bytes = 16 * alg["E"] + 8 * dp.M * dp.M
     t_t = float(np.mean(t_tm))
     out = {
@@ -488,8 +513,11 @@ def main(argv=None):
         out["copy_calibration_bytes"] = int(src.numel() * 8)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl)
-        out["cpu_baseline_1thread"] = cpu_baseline(wl, budget_s=5.0, one_thread=True)
+        # the oracle's apply is numpy work on small element matrices: it runs on
+        # one thread whatever the BLAS pool holds, so the baseline is taken on
+        # one thread (cores = 1 exactly) and the pool's run is reported beside it
+        out["cpu_baseline"] = cpu_baseline(wl, one_thread=True)
+        out["cpu_baseline_all_threads"] = cpu_baseline(wl, budget_s=5.0)
     print(json.dumps(out), flush=True)
     return 0
 
