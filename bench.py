@@ -441,7 +441,9 @@ def main(argv=None):
                 "frac": gbs / HBM_PEAK_GBS}
     copy_gbs = copy_bandwidth()
     roof.update({"traffic": measured_traffic(wl.name, args.prec),
-                 "kernel": "apply_H launch (fill_zero_kernel + apply_fused_kernel)",
+                 "kernel": "apply_H launch (fill_zero_kernel + %s)" % (
+                     "apply_ws_kernel" if args.kernel == 0 and degree == 2 and args.prec in ("fp64", "fp32-mfma")
+                     else "apply_fused_kernel" if args.kernel == 0 else "apply_queue_kernel"),
                  "algorithmic_bytes": alg["bytes"], "algorithmic_flops": alg["flops"],
                  "avg_launch_s": t_ap, "hbm_frac": gbs / HBM_PEAK_GBS,
                  "alu_frac": tfl / peak_f,
@@ -466,7 +468,7 @@ def main(argv=None):
         "config": {"workload": wl.name, "dofs": dp.mesh.ndofs, "orbitals": dp.M,
                    "colblocks": int(len(wl.colblock_sizes)), "radius": wl.radius,
                    "degree": degree, "stored_entries": alg["E"], "prec": args.prec,
-                   "kernel": ["grid", "queue"][args.kernel]},
+                   "kernel": ["default", "queue"][args.kernel]},
         "launch": "the K timed steps as one hipGraph (apply_H: zero fill + apply; tmmult: "
                   "stage-1 classes present in the layout, stage 2, trace); eager loop below",
         "eager": {"value": alg["E"] * args.steps / wall / 1e9, "ms_per_step": wall / args.steps * 1e3},

@@ -507,7 +507,12 @@ int mfb_apply_H(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X, doubl
   if (prec < 0 || prec > 3) fail(MFB_EINVAL, "unknown precision");
   mfb::gpu::ApplyParams a;
   fill_apply_params(mesh, mv, d_X, d_Y, a);
-  const int rc = mfb::gpu::launch_apply(a, mesh->plan.p, prec, 0, mv->plan.block_offset.back(), stream);
+  // the loader-pipelined kernel (7) for the fp64 and fp32-MFMA forms (it runs
+  // the fused grid itself at p != 2 and on curved cells), the fused grid (0)
+  // for the fp32 VALU form
+  const int kernel = (prec == MFB_FP64 || prec == MFB_FP32_MFMA) ? 7 : 0;
+  const int rc =
+      mfb::gpu::launch_apply(a, mesh->plan.p, prec, kernel, mv->plan.block_offset.back(), stream);
   if (rc == -2) fail(MFB_EUNSUPPORTED, "precision not implemented by the library");
   if (rc != 0) fail(MFB_EHIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)rc));
   return MFB_OK;
