@@ -211,3 +211,36 @@ def test_dense_row_blocks_become_tasks(radius, closure):
     assert tasks > 0
     assert y.info["tm_tasks"] == tasks and y.info["tm_units"] == units
     assert y.info["work_bytes"] == 256 + 8 * parts
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_row_blocks_cover_the_rows_and_columns_ascend(cfg):
+    """Sec. 3.4 invariants: the row blocks partition the N rows (their sizes
+    sum to N, so the mean is N / number of batches exactly), and the column
+    block indices of every block row are strictly ascending."""
+    wl = synth.make_workload(cfg)
+    ms = wl.mesh
+    m = Mesh(ms.nx, ms.ny, ms.nz, ms.L, ms.degree, ms.dirichlet)
+    lay = Layout(m, wl.centres, wl.radius, wl.colblock_sizes)
+    pat = lay.pattern()
+    rbs = pat["row_block_start"]
+    ndofs = (ms.degree * ms.nx + 1) * (ms.degree * ms.ny + 1) * (ms.degree * ms.nz + 1)
+    assert rbs[0] == 0 and rbs[-1] == ndofs and np.all(np.diff(rbs) > 0)
+    nb = len(rbs) - 1
+    assert nb == (ms.nx // 2) * (ms.ny // 2) * (ms.nz // 2)
+    assert lay.stats()["rows_mean"] == ndofs / nb
+    rp, ci = pat["rowptr"], pat["colidx"]
+    assert all(np.all(np.diff(ci[rp[r]:rp[r + 1]]) > 0) for r in range(nb))
+
+
+def test_statistics_at_the_paper_density():
+    """Table 1 (soft): at the paper's orbital density (the 64x40x40 Q2 box
+    with support radius 16 cells) the row blocks have a standard deviation
+    near 18 rows and a cell meets about 9.5 to 12 non-empty column blocks."""
+    import dataclasses
+    wl = dataclasses.replace(synth.make_workload(2), radius=16.0)
+    ms = wl.mesh
+    m = Mesh(ms.nx, ms.ny, ms.nz, ms.L, ms.degree, ms.dirichlet)
+    st = Layout(m, wl.centres, wl.radius, wl.colblock_sizes).stats()
+    assert 15.0 < st["rows_std"] < 21.0
+    assert 9.5 <= st["colblocks_per_cell_mean"] <= 12.0
