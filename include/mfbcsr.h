@@ -168,7 +168,7 @@ void mfb_destroy_mesh(mfb_mesh* mesh);
 /* Sparse multivector layout.  centers: M x 3 orbital centres (original
  * order).  radius: radius_count == 1 (shared) or M values: the patch of an
  * orbital is the set of batches whose centre lies within the radius (the
- * support construction of Sec. 6); block (r, C) is stored iff row block r's
+ * support construction of Sec. 4); block (r, C) is stored iff row block r's
  * batch is in the patch of an orbital of C.  Column blocks: colblock_sizes
  * (ncolblocks values summing to M) or, when NULL, blocks of B with the
  * remainder on the last block (Alg. 2 step 4).  col_order: 0 = Hilbert order
@@ -200,7 +200,7 @@ typedef struct {
                                Alg. 8 run as one task each (not in tm_units)   */
 } mfb_mv_info;
 
-/* Table-1-style statistics of a layout (Sec. 6, Table 1).                   */
+/* Table-1-style statistics of a layout (Sec. 4.1, Table 1).                   */
 typedef struct {
   double rows_mean, rows_std;        /* row block sizes                        */
   double cols_mean, cols_std;        /* column block sizes                     */

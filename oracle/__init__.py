@@ -15,7 +15,7 @@ element  explicit element matrices H_K = K_K + M_K[V] (eq. fe_matrices)
 mesh     box mesh numbering, quadrature points, Dirichlet nodes
 hilbert  Hilbert space-filling-curve index (Alg. 1 step 2, Alg. 2 step 3)
 pattern  batch order, row blocks, column order and blocks, BCSR pattern
-         (Alg. 1, Alg. 2, Sec. 6 support construction)
+         (Alg. 1, Alg. 2, Sec. 4 support construction)
 apply    Y = mask(H X) cell by cell (eq. fe_matrices_cell_based, Alg. 6),
          S = X^T Y (Alg. 8), trace; dense assembly for pins
 """

@@ -1,7 +1,7 @@
 """BCSR pattern of the sparse multivector (oracle).
 
 Rows (Alg. 1).  Coarse cells of level L are 2x2x2 batches of fine cells (the
-experiments take L one coarser than the finest, Sec. 6).  Batches are sorted
+experiments take L one coarser than the finest, Sec. 4).  Batches are sorted
 by the Hilbert index of their integer batch coordinates (step 2).  Walking the
 batches in that order, every node of a batch that no earlier batch has
 claimed gets the next row number; the rows claimed by one batch form one row
@@ -13,7 +13,7 @@ Hilbert index of that batch (stable, ties kept in original id order) and cut
 into column blocks (B with the remainder on the last block, or explicit
 sizes).
 
-Support (Sec. 6).  The patch of orbital alpha is the set of batches whose
+Support (Sec. 4).  The patch of orbital alpha is the set of batches whose
 centre lies within distance r of the orbital centre; a block (r, C) is stored
 iff row block r's batch lies in the patch of some orbital of C.  Blocks are
 numbered in CSR order and laid out back to back, each row-major with row
