@@ -196,3 +196,56 @@ def test_serving_orbital_minimisation_alone_and_in_mix():
         err = rel_fro(res["X"], alone.results[r.rid]["X"])
         say(f"om request {r.rid}: alone-vs-mix rel {err:.2e}")
         assert err <= (1e-12 if r.prec == FP64 else 1e-5)
+
+
+def test_graph_replays_with_overlap_tasks():
+    """apply_H + tmmult captured in a hipGraph on a layout whose dense row
+    blocks run as overlap tasks (runs of row blocks, Q1, 16x12x8 cells, 96
+    orbitals, radius 6): every replay, with eager work between replays,
+    gives the eager Y and S (Y is summed with atomics, so to rounding), and
+    an eager overlap of the replay's Y gives the replay's S bitwise (the
+    overlap sums in a fixed order)."""
+    import numpy as np
+    import torch
+    from paper_1907_01005_amd import FP64
+    sizes = [8, 5, 12, 4, 16, 7, 9, 3, 11, 6, 10, 5]
+    ms = synth.MeshSpec(16, 12, 8, (16.0, 12.0, 8.0), 1, 0x3F)
+    wl = synth.custom_workload(ms, sum(sizes), 6.0, 5, potential="wells", name="16x12x8-Q1-dense")
+    wl.colblock_sizes = np.asarray(sizes, dtype=np.int32)
+    say("graph with overlap tasks")
+    op = OracleProblem(wl)
+    dp = device_problem(wl)
+    assert dp.layout.info["tm_tasks"] > 0
+    dp.set_X_coo(op.node, op.orb, op.val)
+    dp.apply(FP64)
+    dp.overlap()
+    torch.cuda.synchronize()
+    Y0, S0, t0 = dp.Y.clone(), dp.S.clone(), dp.trace.clone()
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            dp.apply(FP64)
+            dp.overlap()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        dp.Y.zero_()
+        dp.S.zero_()
+        dp.trace.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        eY = (dp.Y - Y0).abs().max().item() / Y0.abs().max().item()
+        eS = (dp.S - S0).abs().max().item() / S0.abs().max().item()
+        et = abs(dp.trace.item() - t0.item()) / abs(t0.item())
+        Sg, tg = dp.S.clone(), dp.trace.clone()
+        dp.overlap()
+        torch.cuda.synchronize()
+        say(f"replay {rep}: maxrel Y {eY:.2e} S {eS:.2e} trace {et:.2e}")
+        assert eY <= 1e-14 and eS <= 1e-13 and et <= 1e-13
+        assert torch.equal(dp.S, Sg) and torch.equal(dp.trace, tg)
+        dp.apply(FP64)
+        dp.overlap()
+        torch.cuda.synchronize()
