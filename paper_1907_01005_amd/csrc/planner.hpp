@@ -192,7 +192,7 @@ constexpr int kTaskMinPairs = 16;
 constexpr int kTaskMaxPairs = 512;
 constexpr int kTaskMaxWidth = 128;
 constexpr int kTaskMaxRows = 128;
-constexpr int kTaskMaxRunRows = 256;
+constexpr int kTaskMaxRunRows = 160;
 constexpr double kTaskMaxWaste = 1.25;
 
 // Overlap plan (units, tasks, pairs, S-block descriptors) of S = A^T B into mv.

@@ -153,7 +153,7 @@ def test_dense_row_blocks_become_tasks(radius, closure):
     """The overlap's densely populated row blocks (16 to 512 block pairs, at
     most 128 columns on either side, at most 128 rows) run as tasks: runs of
     up to 4 consecutive such row blocks over the union of their column blocks,
-    grown while the union keeps the pair limit, 256 rows and the width class
+    grown while the union keeps the pair limit, 160 rows and the width class
     (64, 96, 128 columns) of its widest member, and costs at most 1.25 times
     the members' own products.  Every other
     (row block, C1, C2) product is a unit.  One partial per unit and per
@@ -200,7 +200,7 @@ def test_dense_row_blocks_become_tasks(radius, closure):
             mrows = nrows + int(rows[q])
             mown = own + int(rows[q]) * wid(A[q]) * wid(B[q])
             mcap = max(cap, width_class(max(wid(A[q]), wid(B[q]))))
-            if (wid(na) > mcap or wid(nb) > mcap or len(na) * len(nb) > 512 or mrows > 256
+            if (wid(na) > mcap or wid(nb) > mcap or len(na) * len(nb) > 512 or mrows > 160
                     or mrows * wid(na) * wid(nb) > 1.25 * mown):
                 break
             ua, ub, nrows, own, cap, n = na, nb, mrows, mown, mcap, n + 1
