@@ -39,6 +39,13 @@
  *    contractions; loads, stores, quadrature scaling and accumulation into
  *    Y stay float64.
  *  - Device buffers must be 256-byte aligned (any torch CUDA allocation is).
+ *  - Destinations that the apply calls accumulate into (d_Y of mfb_apply_H,
+ *    mfb_apply_H_tuned and mfb_apply_op) must be coarse-grained device
+ *    memory (hipMalloc, or any torch CUDA tensor).  The float64 additions
+ *    into Y are hardware atomics that are not coherent on fine-grained or
+ *    host-mapped memory, so such a destination gives wrong sums.
+ *  - Arguments are checked before anything is enqueued: a call that returns
+ *    an error has not touched any device buffer.
  *
  * Value layout of a multivector
  * -----------------------------
@@ -77,7 +84,8 @@ typedef enum {
 /* Arithmetic of the sum-factorisation contractions (mfb_apply_H). */
 typedef enum {
   MFB_FP64 = 0,       /* float64 on the vector ALUs                            */
-  MFB_FP64_MFMA = 1,  /* float64 on the matrix cores                           */
+  MFB_FP64_MFMA = 1,  /* float64 on the matrix cores (v_mfma_f64_16x16x4f64),
+                         float64 accumulation; a measured comparison form      */
   MFB_FP32_MFMA = 2,  /* float32 on the matrix cores, float32 accumulation;
                          quadrature scaling, S and trace stay float64          */
   MFB_FP32 = 3        /* float32 on the vector ALUs (comparison form)          */
@@ -242,6 +250,37 @@ int mfb_mv_pack(const mfb_mv* mv, int64_t nnz, const int64_t* node, const int32_
  * k < info.nvalues (host arrays).                                           */
 int mfb_mv_entry_coords(const mfb_mv* mv, int64_t* node, int32_t* orb);
 
+/* A second handle with the pattern of x (the destination Y = H X is kept
+ * "on the pattern of X", Alg. 6): same rows, columns, stored blocks, value
+ * layout and device plan size.  Its own lifetime and binding; calls that take
+ * two layouts (mfb_apply_op, mfb_mmult) treat the two as the same pattern.
+ * If x is a closure layout the new one is a closure of the same source.
+ * Errors: EINVAL (null).                                                    */
+int mfb_create_like(const mfb_mv* x, mfb_mv** out);
+
+/* Device bytes of one multivector of this layout (value_bytes = 8 nvalues,
+ * the figure an admission rule by BCSR memory footprint needs) and of its
+ * device plan (meta_bytes, for mfb_mv_bind).  Host only.  Errors: EINVAL.    */
+int mfb_mv_sizes(const mfb_mv* mv, size_t* value_bytes, size_t* meta_bytes);
+
+/* Scatter COO triplets given in global coordinates (host arrays: node id,
+ * original orbital id, value) into the device value array d_values
+ * (info.nvalues doubles, caller-owned) of layout mv; stored positions not
+ * named are set to 0.  Marshalling only: packs on the host, then copies on
+ * the stream and waits for the copy.  Errors: EPATTERN when a triplet falls
+ * outside the stored blocks and EINVAL on out-of-range ids (d_values is not
+ * touched then), EHIP.                                                      */
+int mfb_mv_set_global(const mfb_mv* mv, int64_t nnz, const int64_t* node, const int32_t* orb,
+                      const double* val, double* d_values, void* stream);
+
+/* The inverse: every stored value of d_values in global coordinates.  val
+ * (host, info.nvalues doubles) receives the values in stored order; when
+ * node and orb are not NULL (host, info.nvalues each) they receive each
+ * position's global node id and original orbital id.  Copies on the stream
+ * and waits for the copy.  Errors: EINVAL, EHIP.                            */
+int mfb_mv_get_global(const mfb_mv* mv, const double* d_values, int64_t* node, int32_t* orb,
+                      double* val, void* stream);
+
 /* Copies the layout's device plan (apply work list, Alg. 8 product list)
  * into d_meta (caller-owned, info.meta_bytes, 256-B aligned).               */
 int mfb_mv_bind(mfb_mv* mv, void* d_meta, void* stream);
@@ -255,7 +294,7 @@ void mfb_destroy_mv(mfb_mv* mv);
  * d_X, d_Y: device arrays of info.nvalues doubles in the layout of mv; d_Y
  * is overwritten and must not alias d_X.  Values of X on Dirichlet rows are
  * ignored; Y is 0 there.  Errors: EPATTERN (mv planned on another mesh),
- * ESTATE (mesh or mv not bound), EUNSUPPORTED (precision), EHIP.             */
+ * ESTATE (mesh or mv not bound), EINVAL (unknown precision), EHIP.           */
 int mfb_apply_H(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X, double* d_Y,
                 int prec, void* stream);
 
@@ -303,8 +342,9 @@ int mfb_create_closure(const mfb_mv* x, mfb_mv** out);
 
 /* Y = mask_y(op X) with op = H or M (MFB_OP_H / MFB_OP_M, eq. fe_matrices),
  * the same cell loop as mfb_apply_H.  d_X: layout x (info.nvalues of x);
- * d_Y: layout y, which is x itself (the result is kept on the pattern of X,
- * as mfb_apply_H does) or the closure of x (nothing is dropped).  d_Y is
+ * d_Y: layout y, which is x itself or a layout created like it (the result
+ * is kept on the pattern of X, as mfb_apply_H does) or the closure of x
+ * (nothing is dropped).  d_Y is
  * overwritten and must not alias d_X.  prec as for mfb_apply_H; the mass
  * form scales with JxW in float64.  Errors: EPATTERN (y is neither x nor its
  * closure, or another mesh), ESTATE (not bound), EINVAL, EUNSUPPORTED, EHIP. */

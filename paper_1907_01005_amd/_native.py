@@ -86,6 +86,10 @@ SIGNATURES = {
     "mfb_mv_pattern": (C.c_int, [VP, C.POINTER(PatternView)]),
     "mfb_mv_pack": (C.c_int, [VP, C.c_int64, PI64, PI32, PD, PD]),
     "mfb_mv_entry_coords": (C.c_int, [VP, PI64, PI32]),
+    "mfb_create_like": (C.c_int, [VP, C.POINTER(VP)]),
+    "mfb_mv_sizes": (C.c_int, [VP, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    "mfb_mv_set_global": (C.c_int, [VP, C.c_int64, PI64, PI32, PD, VP, VP]),
+    "mfb_mv_get_global": (C.c_int, [VP, VP, PI64, PI32, PD, VP]),
     "mfb_mv_bind": (C.c_int, [VP, VP, VP]),
     "mfb_destroy_mv": (None, [VP]),
     "mfb_apply_H": (C.c_int, [VP, VP, VP, VP, C.c_int, VP]),

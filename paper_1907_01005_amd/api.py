@@ -33,6 +33,30 @@ def _dev_ptr(t) -> C.c_void_p:
     return C.c_void_p(t.data_ptr())
 
 
+def _dev(t, name: str, nbytes: int, dtype=None) -> C.c_void_p:
+    """Pointer of a contiguous GPU tensor of at least nbytes bytes (and the
+    given dtype); a mismatch raises ValueError before the library is called,
+    so no kernel ever reads past the end of a caller's buffer."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name}: must live on a GPU, not {t.device}")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name}: must be {dtype}, not {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    have = t.numel() * t.element_size()
+    if have < nbytes:
+        raise ValueError(f"{name}: {have} bytes, needs at least {nbytes}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _f64(t, name: str, count: int) -> C.c_void_p:
+    import torch
+    return _dev(t, name, 8 * max(int(count), 1), torch.float64)
+
+
 class Mesh:
     """mfb_create_mesh: a box of Q_p cells grouped in Hilbert-ordered 2x2x2 batches."""
 
@@ -94,7 +118,8 @@ class Mesh:
     def bind(self, device="cuda", stream=None) -> None:
         import torch
         self._meta = torch.empty(max(self.meta_bytes, 256), dtype=torch.uint8, device=device)
-        check(lib().mfb_mesh_bind(self._h, _dev_ptr(self._meta), _stream(stream)))
+        check(lib().mfb_mesh_bind(self._h, _dev(self._meta, "meta", self.meta_bytes),
+                                  _stream(stream)))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -151,6 +176,46 @@ class Layout:
         out._finish(h)
         return out
 
+    def like(self) -> "Layout":
+        """mfb_create_like: a second handle with this layout's pattern (it
+        keeps this layout's mesh alive)."""
+        h = C.c_void_p()
+        check(lib().mfb_create_like(self._h, C.byref(h)))
+        out = Layout.__new__(Layout)
+        out.mesh = self.mesh
+        out.source = self.source
+        out._keep = self
+        out._finish(h)
+        return out
+
+    def sizes(self):
+        """mfb_mv_sizes: (value bytes of one multivector, device plan bytes)."""
+        vb, mb = C.c_size_t(), C.c_size_t()
+        check(lib().mfb_mv_sizes(self._h, C.byref(vb), C.byref(mb)))
+        return vb.value, mb.value
+
+    def set_global(self, node, orb, val, values, stream=None) -> None:
+        """mfb_mv_set_global: COO triplets (global node, original orbital,
+        value) into the device value tensor `values` of this layout."""
+        node = np.ascontiguousarray(node, dtype=np.int64)
+        orb = np.ascontiguousarray(orb, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        if not (len(node) == len(orb) == len(val)):
+            raise ValueError("node, orb and val must have the same length")
+        check(lib().mfb_mv_set_global(self._h, len(node), _ptr(node, C.c_int64),
+                                      _ptr(orb, C.c_int32), _ptr(val, C.c_double),
+                                      _f64(values, "values", self.nvalues), _stream(stream)))
+
+    def get_global(self, values, stream=None):
+        """mfb_mv_get_global: (node, orb, val) of every stored position."""
+        node = np.empty(self.nvalues, dtype=np.int64)
+        orb = np.empty(self.nvalues, dtype=np.int32)
+        val = np.empty(self.nvalues, dtype=np.float64)
+        check(lib().mfb_mv_get_global(self._h, _f64(values, "values", self.nvalues),
+                                      _ptr(node, C.c_int64), _ptr(orb, C.c_int32),
+                                      _ptr(val, C.c_double), _stream(stream)))
+        return node, orb, val
+
     @property
     def handle(self):
         return self._h
@@ -197,7 +262,8 @@ class Layout:
     def bind(self, device="cuda", stream=None) -> None:
         import torch
         self._meta = torch.empty(max(self.meta_bytes, 256), dtype=torch.uint8, device=device)
-        check(lib().mfb_mv_bind(self._h, _dev_ptr(self._meta), _stream(stream)))
+        check(lib().mfb_mv_bind(self._h, _dev(self._meta, "meta", self.meta_bytes),
+                                _stream(stream)))
 
     def new_values(self, device="cuda"):
         import torch
@@ -221,35 +287,43 @@ class Layout:
 
 def apply_H(mesh: Mesh, layout: Layout, X, Y, prec: int = FP64, stream=None) -> None:
     """mfb_apply_H: Y = mask(H X) on the caller's stream (asynchronous)."""
-    check(lib().mfb_apply_H(mesh.handle, layout.handle, _dev_ptr(X), _dev_ptr(Y), int(prec),
-                            _stream(stream)))
+    n = layout.nvalues
+    check(lib().mfb_apply_H(mesh.handle, layout.handle, _f64(X, "X", n), _f64(Y, "Y", n),
+                            int(prec), _stream(stream)))
 
 
 def apply_H_tuned(mesh: Mesh, layout: Layout, X, Y, work, prec: int = FP64, kernel: int = 0,
                   grid: int = 0, stream=None) -> None:
     """mfb_apply_H_tuned: the same result through an explicit kernel configuration."""
     t = N.Tune(int(prec), int(kernel), int(grid), 0)
-    check(lib().mfb_apply_H_tuned(mesh.handle, layout.handle, _dev_ptr(X), _dev_ptr(Y),
-                                  C.byref(t), _dev_ptr(work), _stream(stream)))
+    n = layout.nvalues
+    check(lib().mfb_apply_H_tuned(mesh.handle, layout.handle, _f64(X, "X", n), _f64(Y, "Y", n),
+                                  C.byref(t), _dev(work, "work", layout.work_bytes),
+                                  _stream(stream)))
 
 
 def tmmult(layout: Layout, X, Y, S, trace, work, stream=None) -> None:
     """mfb_tmmult: S = X^T Y (M x M, library column order) and trace."""
-    check(lib().mfb_tmmult(layout.handle, _dev_ptr(X), _dev_ptr(Y), _dev_ptr(S), _dev_ptr(trace),
-                           _dev_ptr(work), _stream(stream)))
+    nx = layout.source.nvalues if layout.source is not None else layout.nvalues
+    M = layout.M
+    check(lib().mfb_tmmult(layout.handle, _f64(X, "X", nx), _f64(Y, "Y", layout.nvalues),
+                           _f64(S, "S", M * M), _f64(trace, "trace", 1),
+                           _dev(work, "work", layout.work_bytes), _stream(stream)))
 
 
 def mv_update(layout: Layout, X, Y, S, S2, tau: float, stream=None) -> None:
     """mfb_mv_update: X <- X - tau (Y - X diag(S)/diag(S2)) on the stored entries."""
-    check(lib().mfb_mv_update(layout.handle, _dev_ptr(X), _dev_ptr(Y), _dev_ptr(S), _dev_ptr(S2),
-                              float(tau), _stream(stream)))
+    n, M = layout.nvalues, layout.M
+    check(lib().mfb_mv_update(layout.handle, _f64(X, "X", n), _f64(Y, "Y", n),
+                              _f64(S, "S", M * M), _f64(S2, "S2", M * M), float(tau),
+                              _stream(stream)))
 
 
 def apply_op(mesh: Mesh, x: Layout, y: Layout, op: int, X, Y, prec: int = FP64,
              stream=None) -> None:
     """mfb_apply_op: Y = mask_y(op X), op = OP_H or OP_M; y is x or x.closure()."""
-    check(lib().mfb_apply_op(mesh.handle, x.handle, y.handle, int(op), _dev_ptr(X), _dev_ptr(Y),
-                             int(prec), _stream(stream)))
+    check(lib().mfb_apply_op(mesh.handle, x.handle, y.handle, int(op), _f64(X, "X", x.nvalues),
+                             _f64(Y, "Y", y.nvalues), int(prec), _stream(stream)))
 
 
 def energy_work_bytes(M: int) -> int:
@@ -260,20 +334,26 @@ def energy_work_bytes(M: int) -> int:
 
 def energy(M: int, Mbar, Hbar, E, work, stream=None) -> None:
     """mfb_energy: E = tr((2 I - Mbar) Hbar) into the one-element tensor E."""
-    check(lib().mfb_energy(int(M), _dev_ptr(Mbar), _dev_ptr(Hbar), _dev_ptr(E), _dev_ptr(work),
+    M = int(M)
+    check(lib().mfb_energy(M, _f64(Mbar, "Mbar", M * M), _f64(Hbar, "Hbar", M * M),
+                           _f64(E, "E", 1), _dev(work, "work", energy_work_bytes(M)),
                            _stream(stream)))
 
 
 def mmult(a: Layout, c: Layout, A, B, alpha: float, beta: float, Cv, accumulate: bool = False,
           stream=None) -> None:
     """mfb_mmult (Alg. 7 with truncation): Cv = [Cv +] mask_c(A (alpha B + beta I))."""
-    check(lib().mfb_mmult(a.handle, c.handle, _dev_ptr(A), _dev_ptr(B), float(alpha), float(beta),
-                          _dev_ptr(Cv), int(bool(accumulate)), _stream(stream)))
+    M = a.M
+    check(lib().mfb_mmult(a.handle, c.handle, _f64(A, "A", a.nvalues), _f64(B, "B", M * M),
+                          float(alpha), float(beta), _f64(Cv, "C", c.nvalues),
+                          int(bool(accumulate)), _stream(stream)))
 
 
 def mv_axpy(layout: Layout, alpha: float, X, Y, stream=None) -> None:
     """mfb_mv_axpy: Y += alpha X over the stored values."""
-    check(lib().mfb_mv_axpy(layout.handle, float(alpha), _dev_ptr(X), _dev_ptr(Y), _stream(stream)))
+    n = layout.nvalues
+    check(lib().mfb_mv_axpy(layout.handle, float(alpha), _f64(X, "X", n), _f64(Y, "Y", n),
+                            _stream(stream)))
 
 
 DOT_WORK_DOUBLES = 1024
@@ -281,10 +361,12 @@ DOT_WORK_DOUBLES = 1024
 
 def mv_dot(layout: Layout, X, Y, out, work, stream=None) -> None:
     """mfb_mv_dot: out = tr(X^T Y) over the stored entries (fixed order)."""
-    check(lib().mfb_mv_dot(layout.handle, _dev_ptr(X), _dev_ptr(Y), _dev_ptr(out), _dev_ptr(work),
-                           _stream(stream)))
+    n = layout.nvalues
+    check(lib().mfb_mv_dot(layout.handle, _f64(X, "X", n), _f64(Y, "Y", n), _f64(out, "out", 1),
+                           _f64(work, "work", DOT_WORK_DOUBLES), _stream(stream)))
 
 
 def mv_scale_columns(layout: Layout, scale, X, stream=None) -> None:
     """mfb_mv_scale_columns: X[:, c] *= scale[c] (library column order)."""
-    check(lib().mfb_mv_scale_columns(layout.handle, _dev_ptr(scale), _dev_ptr(X), _stream(stream)))
+    check(lib().mfb_mv_scale_columns(layout.handle, _f64(scale, "scale", layout.M),
+                                     _f64(X, "X", layout.nvalues), _stream(stream)))

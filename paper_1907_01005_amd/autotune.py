@@ -6,9 +6,10 @@ with or without their own block stored), and three thread mappings
 per-workgroup grid or as persistent workgroups pulling from a queue.  The
 tuner times every variant (a few persistent grid sizes, and for the fused
 grid the number of shell items each wave checks) on the caller's layout with
-HIP events and keeps the fastest; the choice is cached per layout
-signature.  `GraphLoop` captures `n` iterations of apply_H + tmmult with the
-chosen variant in one hipGraph and replays it.
+HIP events, checks its result against the default apply's (max relative
+deviation within the precision's tolerance) and keeps the fastest; the
+choice is cached per layout signature.  `GraphLoop` captures `n` iterations
+of apply_H + tmmult with the chosen variant in one hipGraph and replays it.
 """
 
 from __future__ import annotations
@@ -49,13 +50,22 @@ _CACHE: Dict[str, TuneChoice] = {}
 def layout_signature(dp, prec: int) -> str:
     info = dp.layout.info
     m = dp.mesh
-    return json.dumps([m.cells_shape, m.degree, m.dirichlet, info["M"], info["ncolblocks"],
-                       info["nblocks"], info["nvalues"], info["apply_items"], prec])
+    return json.dumps([m.cells_shape, m.degree, m.dirichlet, bool(m.curved), info["M"],
+                       info["ncolblocks"], info["nblocks"], info["nvalues"],
+                       info["apply_items"], prec])
 
 
-def candidates(cu_count: int) -> List[tuple]:
+# Kernels that take curved cells (the others return EUNSUPPORTED there).
+CURVED_KERNELS = (0, 2, 7)
+
+
+def candidates(cu_count: int, curved: bool = False) -> List[tuple]:
     # kernel 0: own and shell items in one grid, grid = shell items checked
     # per wave; 4: one wave per unit; 6, 7 and odd: persistent (grid = workgroups)
+    if curved:
+        out = [(0, spw) for spw in (0, 1, 4, 8)] + [(2, 0), (7, 0)]
+        assert all(k in CURVED_KERNELS for k, _ in out)
+        return out
     out = [(0, spw) for spw in (0, 1, 4, 8)] + [(4, 0)]
     for per_cu in (0, 1, 2, 3):
         out.append((6, per_cu * cu_count))
@@ -84,7 +94,8 @@ def _time_apply(dp, prec: int, kernel: int, grid: int, iters: int, warmup: int) 
 
 def tune(dp, prec: int, iters: int = 20, warmup: int = 3, cache_file: Optional[str] = None,
          verbose: bool = False) -> TuneChoice:
-    """Time every kernel variant on this layout and return the fastest."""
+    """Time every kernel variant that takes this mesh on this layout and return
+    the fastest whose Y agrees with the default apply's."""
     import torch
     key = layout_signature(dp, prec)
     if key in _CACHE:
@@ -98,13 +109,26 @@ def tune(dp, prec: int, iters: int = 20, warmup: int = 3, cache_file: Optional[s
         except (OSError, ValueError, TypeError):
             pass
     cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    # the default apply's result: a candidate whose Y differs from it by more
+    # than the precision's tolerance is not accepted, however fast
+    Y_saved = dp.Y.clone()
+    dp.apply(prec)
+    torch.cuda.synchronize()
+    ref = dp.Y.clone()
+    scale = max(ref.abs().max().item(), 1e-300)
+    tol = 1e-12 if prec in (api.FP64, api.FP64_MFMA) else 1e-5
     best: Optional[TuneChoice] = None
-    for kernel, grid in candidates(cus):
+    for kernel, grid in candidates(cus, bool(dp.mesh.curved)):
         us = _time_apply(dp, prec, kernel, grid, iters, warmup)
+        dev = (dp.Y - ref).abs().max().item() / scale
         if verbose:
-            print(f"[tune] {KERNEL_NAMES[kernel]} grid={grid}: {us:.1f} us", flush=True)
+            print(f"[tune] {KERNEL_NAMES[kernel]} grid={grid}: {us:.1f} us, max dev {dev:.1e}",
+                  flush=True)
+        if dev > tol:
+            continue
         if best is None or us < best.us:
             best = TuneChoice(prec, kernel, grid, us)
+    dp.Y.copy_(Y_saved)
     assert best is not None
     _CACHE[key] = best
     if cache_file:

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -16,6 +17,7 @@
 namespace {
 
 thread_local std::string g_err;
+std::atomic<uint64_t> g_next_pattern_id{1};
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -132,6 +134,7 @@ struct mfb_mv {
   mfb::MvPlan plan;
   const mfb_mesh* mesh = nullptr;
   const mfb_mv* source = nullptr;  // closure layouts: the layout they are the closure of
+  uint64_t pattern_id = 0;         // equal for a layout and the layouts created like it
   MvLayout lay;
   size_t work_bytes = 0;
   void* d_meta = nullptr;
@@ -281,6 +284,7 @@ int mfb_create_bcsr_multivector(const mfb_mesh* mesh, const mfb_mv_desc* desc, m
     v->mesh = mesh;
     v->lay = mv_layout(v->plan);
     v->work_bytes = kCounterBytes + sizeof(double) * (size_t)v->plan.part_doubles;
+    v->pattern_id = g_next_pattern_id++;
   } catch (...) {
     delete v;
     throw;
@@ -404,6 +408,74 @@ int mfb_mv_entry_coords(const mfb_mv* mv, int64_t* node, int32_t* orb) {
   MFB_CATCH
 }
 
+int mfb_create_like(const mfb_mv* x, mfb_mv** out) {
+  MFB_TRY
+  if (!x || !out) fail(MFB_EINVAL, "null argument");
+  *out = nullptr;
+  auto* v = new mfb_mv();
+  try {
+    v->plan = x->plan;
+    v->mesh = x->mesh;
+    v->source = x->source;
+    v->pattern_id = x->pattern_id;
+    v->lay = x->lay;
+    v->work_bytes = x->work_bytes;
+  } catch (...) {
+    delete v;
+    throw;
+  }
+  *out = v;
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_mv_sizes(const mfb_mv* mv, size_t* value_bytes, size_t* meta_bytes) {
+  MFB_TRY
+  if (!mv || !value_bytes || !meta_bytes) fail(MFB_EINVAL, "null argument");
+  *value_bytes = sizeof(double) * (size_t)mv->plan.block_offset.back();
+  *meta_bytes = mv->lay.bytes;
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_mv_set_global(const mfb_mv* mv, int64_t nnz, const int64_t* node, const int32_t* orb,
+                      const double* val, double* d_values, void* stream) {
+  MFB_TRY
+  if (!mv || !d_values) fail(MFB_EINVAL, "null argument");
+  std::vector<double> host((size_t)std::max<int64_t>(1, mv->plan.block_offset.back()));
+  const int rc = mfb_mv_pack(mv, nnz, node, orb, val, host.data());
+  if (rc != MFB_OK) return rc;
+  const size_t bytes = sizeof(double) * (size_t)mv->plan.block_offset.back();
+  hipStream_t st = (hipStream_t)stream;
+  if (bytes) {
+    check_hip(hipMemcpyAsync(d_values, host.data(), bytes, hipMemcpyHostToDevice, st),
+              "hipMemcpyAsync(values)");
+    check_hip(hipStreamSynchronize(st), "hipStreamSynchronize");
+  }
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_mv_get_global(const mfb_mv* mv, const double* d_values, int64_t* node, int32_t* orb,
+                      double* val, void* stream) {
+  MFB_TRY
+  if (!mv || !d_values || !val) fail(MFB_EINVAL, "null argument");
+  if ((node == nullptr) != (orb == nullptr)) fail(MFB_EINVAL, "give both node and orb, or neither");
+  const size_t bytes = sizeof(double) * (size_t)mv->plan.block_offset.back();
+  hipStream_t st = (hipStream_t)stream;
+  if (bytes) {
+    check_hip(hipMemcpyAsync(val, d_values, bytes, hipMemcpyDeviceToHost, st),
+              "hipMemcpyAsync(values)");
+    check_hip(hipStreamSynchronize(st), "hipStreamSynchronize");
+  }
+  if (node) {
+    const int rc = mfb_mv_entry_coords(mv, node, orb);
+    if (rc != MFB_OK) return rc;
+  }
+  return MFB_OK;
+  MFB_CATCH
+}
+
 int mfb_mv_bind(mfb_mv* mv, void* d_meta, void* stream) {
   MFB_TRY
   if (!mv || !d_meta) fail(MFB_EINVAL, "null argument");
@@ -491,6 +563,11 @@ static void fill_apply_params(const mfb_mesh* mesh, const mfb_mv* mv, const doub
   }
 }
 
+// The same BCSR pattern: one handle, or layouts created like one another.
+static bool same_pattern(const mfb_mv* a, const mfb_mv* b) {
+  return a == b || (a->pattern_id != 0 && a->pattern_id == b->pattern_id);
+}
+
 static void check_apply_args(const mfb_mesh* mesh, const mfb_mv* mv, const double* X, const double* Y) {
   if (!mesh || !mv || !X || !Y) fail(MFB_EINVAL, "null argument");
   if (mv->mesh != mesh) fail(MFB_EPATTERN, "layout was planned on another mesh");
@@ -558,6 +635,7 @@ int mfb_create_closure(const mfb_mv* x, mfb_mv** out) {
     v->source = x;
     v->lay = mv_layout(v->plan);
     v->work_bytes = kCounterBytes + sizeof(double) * (size_t)v->plan.part_doubles;
+    v->pattern_id = g_next_pattern_id++;
   } catch (...) {
     delete v;
     throw;
@@ -572,13 +650,15 @@ int mfb_apply_op(const mfb_mesh* mesh, const mfb_mv* x, const mfb_mv* y, int op,
   MFB_TRY
   check_apply_args(mesh, x, d_X, d_Y);
   if (!y) fail(MFB_EINVAL, "null argument");
-  if (y != x && y->source != x) fail(MFB_EPATTERN, "y must be x or the closure of x");
+  const bool closure_dest = y->source && same_pattern(y->source, x);
+  if (!same_pattern(y, x) && !closure_dest)
+    fail(MFB_EPATTERN, "y must have the pattern of x or be its closure");
   if (!y->bound) fail(MFB_ESTATE, "destination layout metadata not bound");
   if (op != MFB_OP_H && op != MFB_OP_M) fail(MFB_EINVAL, "unknown operator");
   if (prec < 0 || prec > 3) fail(MFB_EINVAL, "unknown precision");
   mfb::gpu::ApplyParams a;
   fill_apply_params(mesh, x, d_X, d_Y, a);
-  if (y != x) a.rowoff_out = (const int32_t*)((const char*)y->d_meta + y->lay.off_dest_rowoff);
+  if (closure_dest) a.rowoff_out = (const int32_t*)((const char*)y->d_meta + y->lay.off_dest_rowoff);
   const int rc = mfb::gpu::launch_apply_op(a, mesh->plan.p, prec, op, y->plan.block_offset.back(),
                                            stream);
   if (rc == -2) fail(MFB_EUNSUPPORTED, "precision not implemented by the library");
@@ -599,9 +679,13 @@ int mfb_energy(int32_t M, const double* d_Mbar, const double* d_Hbar, double* d_
   MFB_CATCH
 }
 
-// Two layouts with the same rows and columns: equal, or one the closure of the other.
+// Two layouts with the same rows and columns: the same pattern, one the
+// closure of the other, or two closures of the same pattern.
 static bool same_rows_and_columns(const mfb_mv* a, const mfb_mv* b) {
-  return a == b || a->source == b || b->source == a;
+  if (same_pattern(a, b)) return true;
+  if (a->source && same_pattern(a->source, b)) return true;
+  if (b->source && same_pattern(b->source, a)) return true;
+  return a->source && b->source && same_pattern(a->source, b->source);
 }
 
 static mfb::gpu::BlockView block_view(const mfb_mv* v) {

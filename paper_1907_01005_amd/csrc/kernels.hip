@@ -166,6 +166,75 @@ struct MfmaCtr {
   }
 };
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// fp64 contractions on the matrix cores.  In v_mfma_f64_16x16x4f64 lane l
+// supplies A(l % 16, l / 16) and B(l / 16, l % 16) and receives rows
+// l / 16 + 4 r (r = 0..3) of column l % 16 of the product.  Each lane
+// supplies B = its own pencil value of step k; A is block diagonal,
+// A(i, kk) = M(4 g + i / 4, k) where i % 4 == kk and 0 elsewhere, so that
+// row l / 16 + 4 r of column l % 16 is M(4 g + r, k) times lane l's own
+// value: every lane receives rows 4 g .. 4 g + 3 of M times its own pencil,
+// accumulated in fp64 over the n steps k (a second row group covers rows
+// 4..7 when n = 5).  Only a quarter of each product is used, so this form
+// costs several times the vector form's issue time; it exists to measure
+// the fp64 matrix cores on the same operator.
+template <int n>
+struct MfmaCtr64 {
+  static constexpr int G = (n + 3) / 4;
+  double m[4][G][n];  // [S, S^T, D, D^T][row group][k]: this lane's entry of A
+  __device__ __forceinline__ void init(const double* __restrict__ S, const double* __restrict__ D) {
+    const int i = threadIdx.x & 15, kk = (threadIdx.x >> 4) & 3;
+    const bool on = (i & 3) == kk;
+#pragma unroll
+    for (int mat = 0; mat < 4; ++mat)
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+          const double* M = mat < 2 ? S : D;
+          const bool tr = mat & 1;
+          const int row = 4 * g + (i >> 2);
+          m[mat][g][k] = (on && row < n) ? (tr ? M[k * n + row] : M[row * n + k]) : 0.0;
+        }
+  }
+  template <int AX, bool TR, int MAT, bool ADD>
+  __device__ __forceinline__ void run(const double (&in)[n][n], double (&out)[n][n]) const {
+    constexpr int mi = 2 * MAT + (TR ? 1 : 0);
+#pragma unroll
+    for (int line = 0; line < n; ++line)
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        v4d acc;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int o = 4 * g + q;
+          acc[q] = (ADD && o < n) ? (AX == 0 ? out[o < n ? o : 0][line] : out[line][o < n ? o : 0]) : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < n; ++k)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(m[mi][g][k], AX == 0 ? in[k][line] : in[line][k],
+                                                    acc, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int o = 4 * g + q;
+          if (o < n) {
+            if (AX == 0) out[o][line] = acc[q];
+            else out[line][o] = acc[q];
+          }
+        }
+      }
+  }
+  template <int AX, bool TR, int MAT>
+  __device__ __forceinline__ void c(const double (&in)[n][n], double (&out)[n][n]) const {
+    run<AX, TR, MAT, false>(in, out);
+  }
+  template <int AX, bool TR, int MAT>
+  __device__ __forceinline__ void ca(const double (&in)[n][n], double (&acc)[n][n]) const {
+    run<AX, TR, MAT, true>(in, acc);
+  }
+};
+
 // Workgroup index -> item index so that each XCD (workgroups are dealt to
 // the 8 XCDs round robin) walks one contiguous, Hilbert-ordered range.
 __device__ __forceinline__ int64_t xcd_item(int64_t wg, int64_t nwg) {
@@ -513,14 +582,20 @@ __device__ __forceinline__ void batch_scatter(const ApplyParams& a, const R* __r
   }
 }
 
+// MF selects the matrix cores: fp32 (R = float) or fp64 (R = double).
 template <typename R, int P, bool MF>
-using Contractor = typename std::conditional<MF, MfmaCtr<P + 1>, ValuCtr<R, P + 1>>::type;
+using Contractor = typename std::conditional<
+    MF, typename std::conditional<std::is_same<R, float>::value, MfmaCtr<P + 1>, MfmaCtr64<P + 1>>::type,
+    ValuCtr<R, P + 1>>::type;
 
 template <typename R, int P, bool MF>
 __device__ __forceinline__ Contractor<R, P, MF> make_ctr(const ApplyParams& a) {
   Contractor<R, P, MF> c;
   if constexpr (MF) {
-    c.init(a.Sf, a.Df);
+    if constexpr (std::is_same<R, float>::value)
+      c.init(a.Sf, a.Df);
+    else
+      c.init(a.S, a.Dco);
   } else {
     c.S = tab_S<R>(a);
     c.D = tab_D<R>(a);
@@ -941,8 +1016,6 @@ __global__ __launch_bounds__(64) void tm_stage1_kernel(TmParams p, int64_t first
     p.part[U.part + lane] = acc[0];
   }
 }
-
-typedef double v4d __attribute__((ext_vector_type(4)));
 
 // Stage 1 for other widths (up to 16) on the fp64 matrix cores: the product
 // is a chain of 16x16x4 products over groups of 4 rows, zero-padded.  In
@@ -1957,6 +2030,9 @@ int device_cu_count() {
 int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t nvalues,
                  void* stream) {
   hipStream_t st = (hipStream_t)stream;
+  // refuse before anything is enqueued, so that a refused call leaves Y as it was
+  if (degree < 1 || degree > 4 || prec < 0 || prec > 3 || kernel < 0 || kernel > 7) return -2;
+  if (p.cG && kernel != 0 && kernel != 2 && kernel != 7) return -2;
   {
     const int64_t blocks = std::min<int64_t>(4096, std::max<int64_t>(1, (nvalues / 2 + 255) / 256));
     hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p.Y, nvalues,
@@ -1977,6 +2053,8 @@ int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t
   hipError_t e;
   if (prec == 0)
     e = by_degree([&](auto d) { return launch_apply_t<double, decltype(d)::value>(p, kernel, st); });
+  else if (prec == 1)
+    e = by_degree([&](auto d) { return launch_apply_t<double, decltype(d)::value, true>(p, kernel, st); });
   else if (prec == 3)
     e = by_degree([&](auto d) { return launch_apply_t<float, decltype(d)::value>(p, kernel, st); });
   else if (prec == 2)
@@ -1989,6 +2067,7 @@ int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t
 int launch_apply_op(const ApplyParams& p, int degree, int prec, int op, int64_t nvalues,
                     void* stream) {
   hipStream_t st = (hipStream_t)stream;
+  if (degree < 1 || degree > 4 || prec < 0 || prec > 3 || op < 0 || op > 1) return -2;
   {
     const int64_t blocks = std::min<int64_t>(4096, std::max<int64_t>(1, (nvalues / 2 + 255) / 256));
     hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p.Y, nvalues,
@@ -2013,6 +2092,11 @@ int launch_apply_op(const ApplyParams& p, int degree, int prec, int op, int64_t 
     e = by_degree([&](auto d) {
       constexpr int P = decltype(d)::value;
       return op == 0 ? launch_ws<double, P, false, 0>(p, 0, st) : launch_ws<double, P, false, 1>(p, 0, st);
+    });
+  else if (prec == 1)
+    e = by_degree([&](auto d) {
+      constexpr int P = decltype(d)::value;
+      return op == 0 ? launch_ws<double, P, true, 0>(p, 0, st) : launch_ws<double, P, true, 1>(p, 0, st);
     });
   else if (prec == 2)
     e = by_degree([&](auto d) {

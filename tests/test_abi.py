@@ -140,3 +140,54 @@ def test_curved_mesh_errors():
     with pytest.raises(MfbError) as e:
         m.set_nodes(x)                                   # after the potential
     assert e.value.code == N.MFB_ESTATE
+
+
+def test_create_like_sizes_and_global_marshalling_errors():
+    """mfb_create_like gives a handle with the same pattern (and the same
+    sizes); mfb_mv_sizes reports 8 nvalues and the plan bytes; a triplet
+    outside the pattern or out of range is refused by mfb_mv_set_global before
+    the device buffer is touched (a fake device pointer is never used)."""
+    m = Mesh(4, 4, 4, (4, 4, 4), 2)
+    c = np.random.default_rng(3).random((12, 3)) * 4
+    lay = Layout(m, c, 1.5, colblock_sizes=[5, 7])
+    like = lay.like()
+    assert like.info == lay.info
+    assert like.pattern()["colidx"].tolist() == lay.pattern()["colidx"].tolist()
+    vb, mb = lay.sizes()
+    assert vb == 8 * lay.nvalues and mb == lay.meta_bytes
+    assert like.sizes() == (vb, mb)
+    clo = lay.closure()
+    clo_like = clo.like()
+    assert clo_like.info == clo.info and clo_like.nvalues > lay.nvalues
+    # a destination like x is accepted by the pairing check of mfb_apply_op
+    # (the call then stops at the unbound metadata, before any HIP call)
+    fake, fake2 = C.c_void_p(4096), C.c_void_p(8192)
+    assert lib().mfb_apply_op(m.handle, lay.handle, like.handle, 0, fake, fake2, 0, None) == \
+        N.MFB_ESTATE
+    other = Layout(m, c, 1.5, colblock_sizes=[5, 7])   # same inputs, another pattern id
+    node, orb = lay.entry_coords()
+    stored = set(zip(node.tolist(), orb.tolist()))
+    out = next((g, a) for g in range(m.ndofs) for a in range(12) if (g, a) not in stored)
+    n64 = np.array([out[0]], dtype=np.int64)
+    o32 = np.array([out[1]], dtype=np.int32)
+    v = np.array([1.0])
+    P64, P32, PD = C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_double)
+    rc = lib().mfb_mv_set_global(lay.handle, 1, n64.ctypes.data_as(P64), o32.ctypes.data_as(P32),
+                                 v.ctypes.data_as(PD), fake, None)
+    assert rc == N.MFB_EPATTERN
+    n64[0] = m.ndofs
+    rc = lib().mfb_mv_set_global(lay.handle, 1, n64.ctypes.data_as(P64), o32.ctypes.data_as(P32),
+                                 v.ctypes.data_as(PD), fake, None)
+    assert rc == N.MFB_EINVAL
+    assert lib().mfb_mv_set_global(lay.handle, 0, None, None, None, None, None) == N.MFB_EINVAL
+    val = np.zeros(lay.nvalues)
+    nd = np.zeros(lay.nvalues, dtype=np.int64)
+    # node without orb
+    rc = lib().mfb_mv_get_global(lay.handle, fake, nd.ctypes.data_as(P64), None,
+                                 val.ctypes.data_as(PD), None)
+    assert rc == N.MFB_EINVAL
+    h = C.c_void_p()
+    assert lib().mfb_create_like(None, C.byref(h)) == N.MFB_EINVAL
+    vs, ms = C.c_size_t(), C.c_size_t()
+    assert lib().mfb_mv_sizes(lay.handle, None, C.byref(ms)) == N.MFB_EINVAL
+    del other

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import synth
-from helpers import device_problem, gpu_available, oracle_Y_at, rel_fro, say
+from helpers import device_problem, gate, gpu_available, oracle_full, rel_fro, say
 from oracle.workload import OracleProblem
 
 pytestmark = pytest.mark.gpu
@@ -124,48 +124,52 @@ def test_serving_results_same_alone_and_in_mix():
 
 
 @pytest.mark.parametrize("mesh_index", [0, 1])
-def test_uneven_blocks_640_orbitals_sampled(mesh_index):
-    """128x40x40 Q2 / 64x20x20 Q4, 640 orbitals in column blocks of 4-15."""
+def test_uneven_blocks_640_orbitals_full(mesh_index):
+    """128x40x40 Q2 / 64x20x20 Q4 (1686177 DoFs), 640 orbitals in uneven column
+    blocks: every stored entry of Y, all of S and the trace against one oracle
+    pass, after an fp64 and an fp32-MFMA apply; S bitwise on repeat; then the
+    autotuned 20-iteration hipGraph loop of apply_H + tmmult in both forms,
+    its replay's Y, S and trace against the same oracle result."""
+    import torch
     from paper_1907_01005_amd import FP32_MFMA, FP64
+    from paper_1907_01005_amd.autotune import GraphLoop, tune
     wl = synth.make_workload(4)
     say(f"640 orbitals mesh {mesh_index}")
     op = OracleProblem(wl, mesh_index)
     dp = device_problem(wl, mesh_index)
     dp.set_X_coo(op.node, op.orb, op.val)
     node, orb = dp.layout.entry_coords()
-    ncb = len(wl.colblock_sizes)
-    widths = wl.colblock_sizes
-    blocks = [int(np.argmax(widths)), int(np.argmin(widths)), ncb // 2]
-    sel_orbs = np.concatenate([op.block_orbitals(C) for C in blocks])
-    sel = np.isin(orb, sel_orbs)
-    Yo = oracle_Y_at(op, node[sel], orb[sel], blocks)
-    import scipy.sparse as sp
-    import torch
+    Yo, So, tro = oracle_full(op, node, orb)
+    say(f"640 orbitals mesh {mesh_index}: oracle done, {len(node)} stored entries")
+
+    def check(tag, tol):
+        Yg = dp.Y.cpu().numpy()[:dp.nvalues]
+        gate(Yg, Yo, tol, f"{tag} Y")
+        gate(dp.S_original_order(), So, tol, f"{tag} S")
+        et = abs(float(dp.trace.cpu()[0]) - tro) / abs(tro)
+        say(f"{tag} trace rel {et:.2e}")
+        assert et <= tol
+
     for prec, tol in ((FP64, 1e-12), (FP32_MFMA, 1e-5)):
         dp.apply(prec)
+        dp.overlap()
         torch.cuda.synchronize()
-        Yg = dp.Y.cpu().numpy()[:dp.nvalues]
-        e = rel_fro(Yg[sel], Yo)
-        say(f"640 orbitals mesh {mesh_index} prec={prec}: relY(sampled) {e:.2e}")
-        assert e <= tol
-    # S = X^T Y over the stored entries (Alg. 8), against a sparse product of
-    # the same device values: every block class of the overlap kernels
-    dp.overlap()
-    torch.cuda.synchronize()
-    S = dp.S_original_order()
-    tr = float(dp.trace.cpu()[0])
-    Xg = dp.X.cpu().numpy()[:dp.nvalues]
-    shape = (int(node.max()) + 1, wl.M)
-    Xs = sp.csc_matrix((Xg, (node, orb)), shape=shape)
-    Ys = sp.csc_matrix((Yg, (node, orb)), shape=shape)
-    Sr = (Xs.T @ Ys).toarray()
-    eS = rel_fro(S, Sr)
-    et = abs(tr - np.trace(Sr)) / abs(np.trace(Sr))
-    say(f"640 orbitals mesh {mesh_index}: relS {eS:.2e} relTr {et:.2e}")
-    assert eS <= 1e-12 and et <= 1e-12
-    Sa = dp.S.cpu().numpy().copy()
-    dp.overlap()
-    assert np.array_equal(Sa, dp.S.cpu().numpy())
+        check(f"640 orbitals mesh {mesh_index} prec={prec}", tol)
+        Sa = dp.S.clone()
+        dp.overlap()
+        torch.cuda.synchronize()
+        assert torch.equal(Sa, dp.S)
+    for prec, tol in ((FP64, 1e-12), (FP32_MFMA, 1e-5)):
+        choice = tune(dp, prec, iters=5, warmup=1)
+        say(f"mesh {mesh_index}: tuned {choice.describe()}")
+        loop = GraphLoop(dp, choice, n=20)
+        dp.Y.zero_()
+        dp.S.zero_()
+        dp.trace.zero_()
+        torch.cuda.synchronize()
+        loop.replay()
+        torch.cuda.synchronize()
+        check(f"640 orbitals mesh {mesh_index} graph of 20 prec={prec}", tol)
 
 
 def test_serving_orbital_minimisation_alone_and_in_mix():
