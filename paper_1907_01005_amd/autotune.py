@@ -24,7 +24,7 @@ from . import api
 
 KERNEL_NAMES = {0: "default-grid", 1: "default-queue", 2: "batch-grid", 3: "batch-queue",
                 4: "wave-grid", 5: "wave-queue", 6: "batch-pipelined",
-                7: "loader-pipelined"}
+                7: "loader-pipelined", 8: "register-waves"}
 
 
 @dataclass(frozen=True)
@@ -59,7 +59,14 @@ def layout_signature(dp, prec: int) -> str:
 CURVED_KERNELS = (0, 2, 7)
 
 
-def candidates(cu_count: int, curved: bool = False) -> List[tuple]:
+def reg_kernel_supported(degree: int, prec: int, curved: bool) -> bool:
+    """Kernel 8 (one wave per item, tensors in registers): p <= 2, box
+    cells, vector-ALU contractions."""
+    return degree <= 2 and prec in (api.FP64, api.FP32) and not curved
+
+
+def candidates(cu_count: int, curved: bool = False, degree: int = 2,
+               prec: int = api.FP64) -> List[tuple]:
     # kernel 0: own and shell items in one grid, grid = shell items checked
     # per wave; 4: one wave per unit; 6, 7 and odd: persistent (grid = workgroups)
     if curved:
@@ -74,6 +81,8 @@ def candidates(cu_count: int, curved: bool = False) -> List[tuple]:
     for k in (1, 3, 5):
         for per_cu in (0, 1, 2, 4):
             out.append((k, per_cu * cu_count))
+    if reg_kernel_supported(degree, prec, curved):
+        out.append((8, 0))
     return out
 
 
@@ -118,7 +127,7 @@ def tune(dp, prec: int, iters: int = 20, warmup: int = 3, cache_file: Optional[s
     scale = max(ref.abs().max().item(), 1e-300)
     tol = 1e-12 if prec in (api.FP64, api.FP64_MFMA) else 1e-5
     best: Optional[TuneChoice] = None
-    for kernel, grid in candidates(cus, bool(dp.mesh.curved)):
+    for kernel, grid in candidates(cus, bool(dp.mesh.curved), dp.mesh.degree, prec):
         us = _time_apply(dp, prec, kernel, grid, iters, warmup)
         dev = (dp.Y - ref).abs().max().item() / scale
         if verbose:

@@ -283,7 +283,7 @@ int mfb_create_bcsr_multivector(const mfb_mesh* mesh, const mfb_mv_desc* desc, m
                  desc->ncolblocks, desc->colblock_sizes, desc->B, desc->col_order);
     v->mesh = mesh;
     v->lay = mv_layout(v->plan);
-    v->work_bytes = kCounterBytes + sizeof(double) * (size_t)v->plan.part_doubles;
+    v->work_bytes = kCounterBytes + sizeof(double) * (size_t)(v->plan.part_doubles + v->plan.ndiag);
     v->pattern_id = g_next_pattern_id++;
   } catch (...) {
     delete v;
@@ -560,7 +560,13 @@ static void fill_apply_params(const mfb_mesh* mesh, const mfb_mv* mv, const doub
     a.Dco[i] = b.Dco[i];
     a.Sf[i] = (float)b.S[i];
     a.Df[i] = (float)b.Dco[i];
+    a.Dw[i] = b.wq[i / n] * b.Dco[i];
+    a.Dwf[i] = (float)a.Dw[i];
   }
+  const double det = m.h[0] * m.h[1] * m.h[2];
+  for (int d = 0; d < 3; ++d)
+    for (int q = 0; q < n * n; ++q)
+      a.gline[d][q] = 0.5 * det / (m.h[d] * m.h[d]) * b.wq[q % n] * b.wq[q / n];
 }
 
 // The same BCSR pattern: one handle, or layouts created like one another.
@@ -602,13 +608,15 @@ int mfb_apply_H_tuned(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X,
   check_apply_args(mesh, mv, d_X, d_Y);
   if (!tune) fail(MFB_EINVAL, "null tune");
   if (tune->prec < 0 || tune->prec > 3) fail(MFB_EINVAL, "unknown precision");
-  if (tune->kernel < 0 || tune->kernel > 7) fail(MFB_EINVAL, "kernel must be in 0..7");
+  if (tune->kernel < 0 || tune->kernel > 8) fail(MFB_EINVAL, "kernel must be in 0..8");
   if (tune->grid < 0) fail(MFB_EINVAL, "negative grid");
   if ((tune->kernel == 0 || tune->kernel == 2) &&
       (tune->grid > 64 || (tune->grid & (tune->grid - 1)) != 0))
     fail(MFB_EINVAL, "kernels 0 and 2 take grid = 0 or a power of two up to 64");
   if (mesh->plan.curved && tune->kernel != 0 && tune->kernel != 2 && tune->kernel != 7)
     fail(MFB_EUNSUPPORTED, "curved cells run the fused kernels only (0, 2 and 7)");
+  if (tune->kernel == 8 && !mfb::gpu::reg_kernel_supported(mesh->plan.p, tune->prec, mesh->plan.curved))
+    fail(MFB_EUNSUPPORTED, "kernel 8 takes p <= 2, box cells and the vector-ALU precisions");
   if ((tune->kernel & 1) && tune->kernel != 7 && !d_work)
     fail(MFB_EINVAL, "the queue kernels need the workspace");
   mfb::gpu::ApplyParams a;
@@ -634,7 +642,7 @@ int mfb_create_closure(const mfb_mv* x, mfb_mv** out) {
     v->mesh = x->mesh;
     v->source = x;
     v->lay = mv_layout(v->plan);
-    v->work_bytes = kCounterBytes + sizeof(double) * (size_t)v->plan.part_doubles;
+    v->work_bytes = kCounterBytes + sizeof(double) * (size_t)(v->plan.part_doubles + v->plan.ndiag);
     v->pattern_id = g_next_pattern_id++;
   } catch (...) {
     delete v;
@@ -778,6 +786,9 @@ int mfb_tmmult(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d
   t.task_part = (const int64_t*)(mb + mv->lay.off_task_part);
   for (int c = 0; c < 3; ++c) t.task_class_end[c] = p.task_class_end[c];
   t.part = (double*)((char*)d_work + kCounterBytes);
+  t.tdiag = t.part + p.part_doubles;
+  t.ndiag = p.ndiag;
+  t.fold_trace = p.tasks.empty() ? 1 : 0;
   t.pair_tab = (const int32_t*)(mb + mv->lay.off_pair_tab);
   t.pair_ptr = (const int32_t*)(mb + mv->lay.off_pair_ptr);
   t.pair_list = (const int64_t*)(mb + mv->lay.off_pair_list);

@@ -88,6 +88,13 @@ __device__ __forceinline__ const double* tab_D<double>(const ApplyParams& a) { r
 template <>
 __device__ __forceinline__ const float* tab_D<float>(const ApplyParams& a) { return a.Df; }
 
+template <typename R>
+__device__ __forceinline__ const R* reg_Dw(const ApplyParams& a);
+template <>
+__device__ __forceinline__ const double* reg_Dw<double>(const ApplyParams& a) { return a.Dw; }
+template <>
+__device__ __forceinline__ const float* reg_Dw<float>(const ApplyParams& a) { return a.Dwf; }
+
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 // Contractions on the vector ALUs; MAT selects S (0) or D (1).
@@ -888,6 +895,171 @@ struct RegProc {
   }
 };
 
+// -------------------------------------------------------------- register-resident apply
+// p <= 2 on box cells: one wave per work item and no LDS, no barrier.  Lane
+// l = 8 e + c holds the whole (p+1)^3 tensor of column c on cell e of the
+// batch, so that every 1D contraction runs inside the lane, in place, line
+// by line.  The gradient term of eq. fe_matrices takes each line's
+// derivative at the Gauss points with the weights folded into the matrix
+// (Dw = diag(w) D), scales it by the line's constant 1/2 hx hy hz / h_d^2
+// w_a w_b and integrates it back with D^T.  The eight cells of the batch
+// share nodes; their results are summed across lanes face by face (x, then
+// y, then z: cell e ^ 1 is lane l ^ 8, e ^ 2 is l ^ 16, e ^ 4 is l ^ 32), so
+// that each shared node ends in the lane of the cell with the smallest
+// child index containing it, which alone adds it into Y.
+
+// w += D^T (gl (.) Dw uq) along AXIS, line by line.
+template <int n, int AXIS, typename R>
+__device__ __forceinline__ void grad_line_pass(const R (&uq)[n * n * n], R (&w)[n * n * n],
+                                               const R* __restrict__ Dw, const R* __restrict__ Dm,
+                                               const double* __restrict__ gl) {
+  constexpr int S = AXIS == 0 ? 1 : (AXIS == 1 ? n : n * n);
+#pragma unroll
+  for (int l = 0; l < n * n; ++l) {
+    const int base = AXIS == 0 ? l * n : (AXIS == 1 ? (l % n) + (l / n) * n * n : l);
+    R gq[n];
+#pragma unroll
+    for (int o = 0; o < n; ++o) {
+      R s = 0;
+#pragma unroll
+      for (int k = 0; k < n; ++k) s = fma_r(Dw[o * n + k], uq[base + k * S], s);
+      gq[o] = (R)((double)s * gl[l]);
+    }
+#pragma unroll
+    for (int o = 0; o < n; ++o) {
+      R s = w[base + o * S];
+#pragma unroll
+      for (int k = 0; k < n; ++k) s = fma_r(Dm[k * n + o], gq[k], s);
+      w[base + o * S] = s;
+    }
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ R shfl_xor_r(R v, int m) {
+  return __shfl_xor(v, m, 64);
+}
+
+// Sums the face shared by cells e and e ^ (1 << AXIS) into the lower cell
+// (local index P along AXIS); the upper cell's copy (index 0) is left to be
+// dropped by the flush.
+template <int n, int AXIS, typename R>
+__device__ __forceinline__ void face_sum(R (&w)[n * n * n], int e) {
+  constexpr int S = AXIS == 0 ? 1 : (AXIS == 1 ? n : n * n), P = n - 1;
+  const bool hi = (e >> AXIS) & 1;
+#pragma unroll
+  for (int l = 0; l < n * n; ++l) {
+    const int base = AXIS == 0 ? l * n : (AXIS == 1 ? (l % n) + (l / n) * n * n : l);
+    const R v = shfl_xor_r(hi ? w[base] : w[base + P * S], 8 << AXIS);
+    if (!hi) w[base + P * S] += v;
+  }
+}
+
+template <typename R, int P, int OP, bool DEST>
+struct RegWave {
+  using D = Dims<P>;
+  static constexpr int n = D::n, n2 = D::n2, n3 = D::n3, NB = D::NB, NB3 = D::NB3;
+  static __device__ __forceinline__ int node(int e, int i, int j, int k) {
+    return ((e & 1) * P + i) + NB * ((((e >> 1) & 1) * P + j) + NB * ((e >> 2) * P + k));
+  }
+  static __device__ __forceinline__ void run(const ApplyParams& a, int64_t idx, int l) {
+    const int e = l >> 3, c = l & 7;
+    const int nc = a.items[idx].nc, rank = a.items[idx].rank;
+    const int32_t* __restrict__ ro = a.rowoff + idx * NB3;
+    R u[n3];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < n; ++k)
+#pragma unroll
+      for (int j = 0; j < n; ++j)
+#pragma unroll
+        for (int i = 0; i < n; ++i) {
+          // unconditional loads (absent rows read entry 0, then give 0):
+          // no branch between the loads
+          const int32_t r = ro[node(e, i, j, k)];
+          const bool ok = r >= 0 && c < nc;
+          const double x = ok ? a.X[ok ? (int64_t)r + c : 0] : 0.0;
+          u[i + n * j + n2 * k] = (R)x;
+          any |= (x != 0.0);
+        }
+    if (__ballot(any) == 0) return;
+    const R* __restrict__ Sm = tab_S<R>(a);
+    sweep<n, 0, false>(u, Sm);
+    sweep<n, 1, false>(u, Sm);
+    sweep<n, 2, false>(u, Sm);
+    R w[n3];
+    if constexpr (OP == 0) {
+      const double* __restrict__ cv = a.cV + ((int64_t)rank * 8 + e) * n3;
+#pragma unroll
+      for (int q = 0; q < n3; ++q) w[q] = (R)(cv[q] * (double)u[q]);
+      const R* __restrict__ Dm = tab_D<R>(a);
+      const R* __restrict__ Dw = reg_Dw<R>(a);
+      grad_line_pass<n, 0>(u, w, Dw, Dm, a.gline[0]);
+      grad_line_pass<n, 1>(u, w, Dw, Dm, a.gline[1]);
+      grad_line_pass<n, 2>(u, w, Dw, Dm, a.gline[2]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < n3; ++q) w[q] = (R)(a.jxw[q] * (double)u[q]);
+    }
+    sweep<n, 2, true>(w, Sm);
+    sweep<n, 1, true>(w, Sm);
+    sweep<n, 0, true>(w, Sm);
+    face_sum<n, 0>(w, e);
+    face_sum<n, 1>(w, e);
+    face_sum<n, 2>(w, e);
+    if (c >= nc) return;
+    const int32_t* __restrict__ rd = (DEST ? a.rowoff_out : a.rowoff) + idx * NB3;
+    const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
+#pragma unroll
+    for (int k = 0; k < n; ++k)
+#pragma unroll
+      for (int j = 0; j < n; ++j)
+#pragma unroll
+        for (int i = 0; i < n; ++i) {
+          if ((ex && i == 0) || (ey && j == 0) || (ez && k == 0)) continue;
+          const int32_t r = rd[node(e, i, j, k)];
+          if (r >= 0) unsafeAtomicAdd(a.Y + (int64_t)r + c, (double)w[i + n * j + n2 * k]);
+        }
+  }
+};
+
+// Grid: own_wg workgroups of four waves take the own items (XCD-contiguous
+// ranges, one item per wave); the workgroups after them check four shell
+// items per wave (16 lanes each, through their present rows) and run those
+// that hold a non-zero value.
+// fp64 at p = 2 holds two 27-value tensors per lane: three waves per SIMD
+// (168 registers) rather than the four the vector form would need to spill for.
+template <typename R, int P, int OP, bool DEST>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu((P == 2 && sizeof(R) == 8) ? 3 : 4, 8)))
+void apply_reg_kernel(ApplyParams a, int64_t own_wg) {
+  using W = RegWave<R, P, OP, DEST>;
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if ((int64_t)blockIdx.x < own_wg) {
+    const int64_t it = xcd_item(blockIdx.x, own_wg) * 4 + wv;
+    if (it < a.nitems) W::run(a, it, l);
+    return;
+  }
+  const int64_t g = ((int64_t)blockIdx.x - own_wg) * 4 + wv;
+  const int sub = l >> 4, ll = l & 15;
+  const int64_t k = g * 4 + sub;
+  bool any = false;
+  if (k < a.nshell) {
+    const int nc = a.items[a.nitems + k].nc;
+    const int32_t e1 = a.shell_ptr[k + 1];
+    for (int32_t q = a.shell_ptr[k] + ll; q < e1; q += 16) {
+      const double* __restrict__ xp = a.X + (int64_t)a.shell_ro[q];
+      for (int c = 0; c < nc; ++c) any |= (xp[c] != 0.0);
+    }
+  }
+  uint64_t hit = __ballot(any);
+  while (hit != 0) {
+    const int s2 = __builtin_ctzll(hit) >> 4;
+    hit &= ~(0xFFFFull << (16 * s2));
+    W::run(a, a.nitems + g * 4 + s2, l);
+  }
+}
+
 // One work unit per workgroup, units dealt to XCDs in contiguous ranges.
 template <class Proc>
 __global__ __launch_bounds__(Proc::NT) void apply_grid_kernel(ApplyParams a) {
@@ -934,86 +1106,75 @@ __global__ void fill_zero_kernel(double* __restrict__ p, int64_t n, int32_t* cou
 }
 
 // -------------------------------------------------------------- overlap
-// Stage 1 of Alg. 8: one workgroup per block product X_{r,C1}^T Y_{r,C2},
-// written to its own slot of the partial products.  The planner sorts the
-// units into four classes, one kernel each (own thread count, register
-// budget and occupancy).  Every sum is taken in a fixed order, so the result
-// is bitwise reproducible.
-//  * 8x8 blocks of at most 128 rows: lane (s, a) takes rows s, s+8, ... and
-//    column a, summed over s with an xor butterfly.
-//  * longer 8x8 blocks with even offsets: each lane takes every 64th row and
-//    keeps the 64 products of its rows in registers; a butterfly
-//    reduce-scatter across the wave leaves entry j of the product in lane j.
-//  * other widths: fp64 matrix-core products over groups of 4 rows, one
-//    wave up to 128 rows, four waves beyond.
+// Stage 1 of Alg. 8: every block product X_{r,C1}^T Y_{r,C2} is written to
+// its own slot of the partial products.  The planner sorts the products
+// into classes, one kernel each (own thread count, register budget and
+// occupancy).  Every sum is taken in a fixed order, so the result is
+// bitwise reproducible.  A product with C1 = C2 also writes its trace (the
+// sum over its diagonal) to its slot of the diagonal list, from which the
+// second stage sums tr S.
 __device__ __forceinline__ double shfl_xor_d(double v, int m) {
   return __shfl_xor(v, m, 64);
 }
 
-template <int CLASS>
-__global__ __launch_bounds__(64) void tm_stage1_kernel(TmParams p, int64_t first, int64_t count) {
-  const int lane = threadIdx.x;
-  const int64_t u = xcd_item(blockIdx.x, gridDim.x);
+// Fixed-order sum over the wave; lane 0's result is the one used.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += shfl_xor_d(v, m);
+  return v;
+}
+
+// Blocks at most 8 wide on both sides, one product per wave, on the fp64
+// matrix cores.  In v_mfma_f64_16x16x4f64 lane l supplies A(l % 16, l / 16)
+// and B(l / 16, l % 16) and receives rows l / 16 + 4 r (r = 0..3) of column
+// l % 16 of the result.  One product step covers 8 rows: lane l loads column
+// a = l % 8 of row 8 s + 4 h + l / 16 (h = bit 3 of l) of X and of Y, so
+// that a wave reads the 8 rows' contiguous bytes once and no value twice.
+// Then A(i, k) = X(8 s + 4 (i / 8) + k, i % 8) and B(k, j) = Y(8 s + 4 (j / 8)
+// + k, j % 8): the two diagonal 8x8 blocks of the 16x16 result (i / 8 = j / 8)
+// are X^T Y over rows 8 s + k and over rows 8 s + 4 + k, and their sum is the
+// block product (the other two blocks are never read).  Four waves, four
+// products per workgroup.  W8: both blocks exactly 8 wide (the row stride
+// is then a constant and the loads share one address).
+template <int STEPS, bool W8>
+__global__ __launch_bounds__(256) void tm_unit8_kernel(TmParams p, int64_t first, int64_t count) {
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t u = xcd_item(blockIdx.x, gridDim.x) * 4 + wv;
   if (u >= count) return;
   const TmUnit U = p.units[first + u];
-  const double* __restrict__ X = p.X + U.off1;
-  const double* __restrict__ Y = p.Y + U.off2;
-  if constexpr (CLASS == 0) {
-    // short 8x8 blocks: lane (s, a) takes rows s, s+8, ... and column a of
-    // X, keeping the 8 products with the columns of Y; sum over s by butterfly
-    const int s8 = lane >> 3, a8 = lane & 7;
-    double acc8[8];
+  const int a = l & 7, h = (l >> 3) & 1, k = l >> 4;
+  const int w1 = W8 ? 8 : U.w1, w2 = W8 ? 8 : U.w2, rows = U.rows;
+  const bool okx = a < w1, oky = a < w2;
+  const double* __restrict__ X = p.X + U.off1 + (okx ? a : 0);
+  const double* __restrict__ Y = p.Y + U.off2 + (oky ? a : 0);
+  const int r0 = 4 * h + k;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  for (int base = 0; base < rows; base += 8 * STEPS) {
+    double xa[STEPS], yb[STEPS];
 #pragma unroll
-    for (int b = 0; b < 8; ++b) acc8[b] = 0.0;
-#pragma unroll 4
-    for (int i = s8; i < U.rows; i += 8) {
-      const double x = X[(int64_t)i * 8 + a8];
-      const double* __restrict__ y = Y + (int64_t)i * 8;
-#pragma unroll
-      for (int b = 0; b < 8; ++b) acc8[b] = __builtin_fma(x, y[b], acc8[b]);
+    for (int s = 0; s < STEPS; ++s) {
+      const int i = base + 8 * s + r0;
+      xa[s] = (okx && i < rows) ? X[(int64_t)i * w1] : 0.0;
+      yb[s] = (oky && i < rows) ? Y[(int64_t)i * w2] : 0.0;
     }
 #pragma unroll
-    for (int m = 8; m <= 32; m <<= 1)
-#pragma unroll
-      for (int b = 0; b < 8; ++b) acc8[b] += shfl_xor_d(acc8[b], m);
-    double v = acc8[0];
-#pragma unroll
-    for (int b = 1; b < 8; ++b) v = (s8 == b) ? acc8[b] : v;
-    p.part[U.part + a8 * 8 + s8] = v;
-  } else if constexpr (CLASS == 1) {
-    // long 8x8 blocks with even offsets: lane i takes rows i, i + 64, ...
-    // with 16-byte loads and keeps all 64 products
-    double acc[64];
-#pragma unroll
-    for (int j = 0; j < 64; ++j) acc[j] = 0.0;
-    for (int i = lane; i < U.rows; i += 64) {
-      const double2* __restrict__ x2 = reinterpret_cast<const double2*>(X + (int64_t)i * 8);
-      const double2* __restrict__ y2 = reinterpret_cast<const double2*>(Y + (int64_t)i * 8);
-      double x[8], y[8];
-#pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const double2 a = x2[h], b = y2[h];
-        x[2 * h] = a.x; x[2 * h + 1] = a.y;
-        y[2 * h] = b.x; y[2 * h + 1] = b.y;
-      }
-#pragma unroll
-      for (int a = 0; a < 8; ++a)
-#pragma unroll
-        for (int b = 0; b < 8; ++b) acc[a * 8 + b] = __builtin_fma(x[a], y[b], acc[a * 8 + b]);
-    }
-    // reduce-scatter: after the step with mask m a lane keeps the m entries
-    // whose index bit log2(m) equals its own lane bit.
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-      const bool hi = (lane & m) != 0;
-#pragma unroll
-      for (int j = 0; j < m; ++j) {
-        const double keep = hi ? acc[j + m] : acc[j];
-        const double send = hi ? acc[j] : acc[j + m];
-        acc[j] = keep + shfl_xor_d(send, m);
-      }
-    }
-    p.part[U.part + lane] = acc[0];
+    for (int s = 0; s < STEPS; ++s)
+      if (base + 8 * s < rows) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[s], yb[s], acc, 0, 0, 0);
+  }
+  // lane l (column j = l % 16 < 8) holds P(k, j) and P(k + 4, j) of the
+  // first block at r = 0, 1; lane l + 8 holds those of the second block at
+  // r = 2, 3
+  const double v0 = acc[0] + shfl_xor_d(acc[2], 8);
+  const double v1 = acc[1] + shfl_xor_d(acc[3], 8);
+  const int j = l & 15;
+  if (j < 8 && j < w2) {
+    if (k < w1) p.part[U.part + k * w2 + j] = v0;
+    if (k + 4 < w1) p.part[U.part + (k + 4) * w2 + j] = v1;
+  }
+  if (U.tslot >= 0) {
+    const double d = j < 8 ? ((k == j ? v0 : 0.0) + (k + 4 == j ? v1 : 0.0)) : 0.0;
+    const double tr = wave_sum(d);
+    if (l == 0) p.tdiag[U.tslot] = tr;
   }
 }
 
@@ -1069,6 +1230,13 @@ __global__ __launch_bounds__(64 * NW) void tm_stage1_mfma_kernel(TmParams p, int
   for (int r = 0; r < 4; ++r) {
     const int a = kr + 4 * r;
     if (a < w1 && oky) p.part[U.part + a * w2 + col] = t[r];
+  }
+  if (U.tslot >= 0) {
+    double d = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) d += (kr + 4 * r == col && col < w1) ? t[r] : 0.0;
+    const double tr = wave_sum(d);
+    if (l == 0) p.tdiag[U.tslot] = tr;
   }
 }
 
@@ -1226,15 +1394,44 @@ __global__ __launch_bounds__(64 * NW) void tm_task_kernel(TmParams p, int64_t fi
   dispatch_count<0, kNT>(nt, main_loop);
 }
 
-// NT threads per block of S: 256, or 1024 where some pair has many partials.
+// Stage 2: one workgroup per block of S sums its pair's partial products in
+// a fixed order (NT / E thread groups, up to 32 loads in flight per thread,
+// then LDS); blocks outside the pattern write zeros.  With fold_trace the
+// first workgroup instead sums the diagonal products' traces (tdiag, in
+// order) into tr S, so that the trace needs no launch of its own.
 template <int NT>
 __global__ __launch_bounds__(NT) void tm_stage2_kernel(TmParams p) {
   __shared__ double red[NT];
   const int t = threadIdx.x;
-  const S2Desc d = p.s2[blockIdx.x];
+  int64_t blk = blockIdx.x;
+  if (p.fold_trace) {
+    if (blk == 0) {
+      double sum = 0.0;
+      for (int64_t i0 = t; i0 < p.ndiag; i0 += 8 * NT) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int64_t i = i0 + (int64_t)q * NT;
+          v[q] = i < p.ndiag ? p.tdiag[i] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sum += v[q];
+      }
+      red[t] = sum;
+      __syncthreads();
+      for (int hh = NT / 2; hh > 0; hh >>= 1) {
+        if (t < hh) red[t] += red[t + hh];
+        __syncthreads();
+      }
+      if (t == 0) *p.trace = red[0];
+      return;
+    }
+    --blk;
+  }
+  const S2Desc d = p.s2[blk];
   const int E = d.w1 * d.w2;
   if (d.n == 0) {  // block outside the product pattern
-    if (t < E) p.S[(int64_t)(d.c1 + t / d.w2) * p.M + (d.c2 + t % d.w2)] = 0.0;
+    for (int e = t; e < E; e += NT) p.S[(int64_t)(d.c1 + e / d.w2) * p.M + (d.c2 + e % d.w2)] = 0.0;
     return;
   }
   const int G = NT / E;
@@ -1242,19 +1439,19 @@ __global__ __launch_bounds__(NT) void tm_stage2_kernel(TmParams p) {
   double sum = 0.0;
   if (g < G) {
     // the pair's n partial products lie back to back: part[base + k E + e];
-    // thread group g takes k = g, g + G, ...: up to 16 loads are issued
+    // thread group g takes k = g, g + G, ...: up to 32 loads are issued
     // before the first add, then summed in order (fixed order overall)
     const int n = d.n;
     const double* __restrict__ src = p.part + d.base + e;
-    for (int k0 = g; k0 < n; k0 += 16 * G) {
-      double v[16];
+    for (int k0 = g; k0 < n; k0 += 32 * G) {
+      double v[32];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
+      for (int u = 0; u < 32; ++u) {
         const int k = k0 + u * G;
         v[u] = k < n ? src[(int64_t)k * E] : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < 16; ++u) sum += v[u];
+      for (int u = 0; u < 32; ++u) sum += v[u];
     }
   }
   red[t] = sum;
@@ -1793,10 +1990,25 @@ hipError_t launch_ws(const ApplyParams& p, int grid, hipStream_t st) {
   }
 }
 
+// Register-resident waves (p <= 2, box cells, vector-ALU contractions).
+template <typename R, int P, int OP, bool DEST>
+hipError_t launch_reg(const ApplyParams& p, hipStream_t st) {
+  if (p.nitems + p.nshell == 0) return hipSuccess;
+  const int64_t own_wg = (((p.nitems + 3) / 4 + 7) / 8) * 8;
+  const int64_t shell_wg = ((p.nshell + 3) / 4 + 3) / 4;
+  hipLaunchKernelGGL((apply_reg_kernel<R, P, OP, DEST>), dim3((unsigned)(own_wg + shell_wg)),
+                     dim3(256), 0, st, p, own_wg);
+  return hipGetLastError();
+}
+
 template <typename R, int P, bool MF = false>
 hipError_t launch_apply_t(const ApplyParams& p, int kernel, hipStream_t st) {
   // curved cells: the fused grid only (kernel 7 runs it too)
   if (p.cG && kernel != 0 && kernel != 2 && kernel != 7) return hipErrorNotSupported;
+  if (kernel == 8) {
+    if constexpr (P <= 2 && !MF) return launch_reg<R, P, 0, false>(p, st);
+    else return hipErrorNotSupported;
+  }
   if (kernel == 6) return launch_pipe<R, P, MF>(p, st);
   if (kernel == 7) return launch_ws<R, P, MF, 0>(p, p.grid, st);
   const bool queue = (kernel & 1) != 0;
@@ -2013,6 +2225,10 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateParams p) {
 
 }  // namespace
 
+bool reg_kernel_supported(int degree, int prec, bool curved) {
+  return degree <= 2 && (prec == 0 || prec == 3) && !curved;
+}
+
 int launch_update(const UpdateParams& p, void* stream) {
   if (p.nblocks == 0) return 0;
   hipLaunchKernelGGL(update_kernel, dim3((unsigned)p.nblocks), dim3(256), 0, (hipStream_t)stream, p);
@@ -2031,8 +2247,9 @@ int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t
                  void* stream) {
   hipStream_t st = (hipStream_t)stream;
   // refuse before anything is enqueued, so that a refused call leaves Y as it was
-  if (degree < 1 || degree > 4 || prec < 0 || prec > 3 || kernel < 0 || kernel > 7) return -2;
+  if (degree < 1 || degree > 4 || prec < 0 || prec > 3 || kernel < 0 || kernel > 8) return -2;
   if (p.cG && kernel != 0 && kernel != 2 && kernel != 7) return -2;
+  if (kernel == 8 && !reg_kernel_supported(degree, prec, p.cG != nullptr)) return -2;
   {
     const int64_t blocks = std::min<int64_t>(4096, std::max<int64_t>(1, (nvalues / 2 + 255) / 256));
     hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p.Y, nvalues,
@@ -2174,8 +2391,14 @@ int launch_tmmult(const TmParams& p, void* stream) {
     const int64_t nwg = ((n + 7) / 8) * 8;
     hipLaunchKernelGGL(kernel, dim3((unsigned)nwg), dim3(threads), 0, st, p, lo, n);
   };
-  launch(tm_stage1_kernel<0>, 0, 64);
-  launch(tm_stage1_kernel<1>, 1, 64);
+  auto launch4 = [&](auto kernel, int c) {  // four products per workgroup
+    const int64_t lo = c ? ce[c - 1] : 0, n = ce[c] - lo;
+    if (n <= 0) return;
+    const int64_t nwg = (((n + 3) / 4 + 7) / 8) * 8;
+    hipLaunchKernelGGL(kernel, dim3((unsigned)nwg), dim3(256), 0, st, p, lo, n);
+  };
+  launch4(tm_unit8_kernel<16, true>, 0);
+  launch4(tm_unit8_kernel<8, false>, 1);
   launch(tm_stage1_mfma_kernel<1, 2>, 2, 64);
   launch(tm_stage1_mfma_kernel<4, 2>, 3, 256);
   {
@@ -2194,13 +2417,17 @@ int launch_tmmult(const TmParams& p, void* stream) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
   }
-  const int64_t nblk = (int64_t)p.ncb * p.ncb;
-  if (p.max_pair_parts > 512)
+  const int64_t nblk = (int64_t)p.ncb * p.ncb + (p.fold_trace ? 1 : 0);
+  if (p.max_pair_parts > 1024)
     hipLaunchKernelGGL(tm_stage2_kernel<1024>, dim3((unsigned)nblk), dim3(1024), 0, st, p);
+  else if (p.max_pair_parts > 128)
+    hipLaunchKernelGGL(tm_stage2_kernel<512>, dim3((unsigned)nblk), dim3(512), 0, st, p);
   else
     hipLaunchKernelGGL(tm_stage2_kernel<256>, dim3((unsigned)nblk), dim3(256), 0, st, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
+  if (p.fold_trace) return 0;
+  // with tasks the trace is summed from S's diagonal by a kernel of its own
   hipLaunchKernelGGL(tm_trace_kernel, dim3(1), dim3(64), 0, st, p);
   return (int)hipGetLastError();
 }

@@ -37,6 +37,13 @@ struct ApplyParams {
   // and JxW [ (p+1)^3 ]
   const double* cG;
   const double* cJ;
+  // box cells, register-resident kernel: Dw[o*n + k] = w_o Dco[o*n + k] (w the
+  // Gauss weights), and per direction d the scale of each line along d,
+  // gline[d][a + n b] = 1/2 hx hy hz / h_d^2 w_a w_b with (a, b) the indices
+  // of the line along the other two axes in increasing axis order
+  double Dw[25];
+  float Dwf[25];
+  double gline[3][25];
 };
 
 struct TmParams {
@@ -57,6 +64,10 @@ struct TmParams {
   const int32_t* cb_start;   // [ncb+1]
   const S2Desc* s2;          // [ncb*ncb] blocks of S for the second stage
   int64_t max_pair_parts;    // most partial products of one pair
+  double* tdiag;             // [ndiag] traces of the products with C1 = C2
+  int64_t ndiag;
+  int32_t fold_trace;        // 1: the trace is summed from tdiag in the second stage
+  int32_t pad2;
   int32_t M, ncb;
   double* S;
   double* trace;
@@ -69,6 +80,9 @@ struct TmParams {
 int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t nvalues,
                  void* stream);
 int launch_tmmult(const TmParams& p, void* stream);
+// kernel 8 (register-resident waves): p <= 2, vector-ALU contractions
+// (fp64 or fp32), box cells.
+bool reg_kernel_supported(int degree, int prec, bool curved);
 // op: 0 Hamiltonian, 1 mass; default kernel; destination nvalues for the fill.
 int launch_apply_op(const ApplyParams& p, int degree, int prec, int op, int64_t nvalues,
                     void* stream);

@@ -626,7 +626,7 @@ void plan_overlap(MvPlan& mv, const MvPlan& A, const MvPlan& B, const MeshPlan& 
         u.rows = (int32_t)rows;
         u.w1 = w[C1];
         u.w2 = w[C2];
-        u.pad = 0;
+        u.tslot = C1 == C2 ? -2 : -1;  // a diagonal block of S: slot assigned below
         mv.units.push_back(u);
       }
     ++r;
@@ -651,7 +651,8 @@ void plan_overlap(MvPlan& mv, const MvPlan& A, const MvPlan& B, const MeshPlan& 
   // register budget
   auto tm_class = [](const TmUnit& u) {
     const bool shortb = u.rows <= 128;
-    if (u.w1 == 8 && u.w2 == 8 && (shortb || ((u.off1 | u.off2) & 1) == 0)) return shortb ? 0 : 1;
+    if (u.w1 == 8 && u.w2 == 8 && shortb) return 0;
+    if (u.w1 <= 8 && u.w2 <= 8) return 1;
     return shortb ? 2 : 3;
   };
   std::stable_sort(mv.units.begin(), mv.units.end(),
@@ -659,6 +660,10 @@ void plan_overlap(MvPlan& mv, const MvPlan& A, const MvPlan& B, const MeshPlan& 
   mv.tm_class_end.fill(0);
   for (const TmUnit& u : mv.units)
     for (int c = tm_class(u); c < 4; ++c) ++mv.tm_class_end[c];
+  // the products with C1 = C2 (same column block on both sides: A and B
+  // share the column blocks) carry the trace; one slot each, in unit order
+  mv.ndiag = 0;
+  for (TmUnit& u : mv.units) u.tslot = u.tslot == -2 ? (int32_t)mv.ndiag++ : -1;
   // tasks by register tile: 4, 6 or 8 columns of each block product per thread
   auto task_class = [](const TmTask& T) {
     const int wmax = T.wa > T.wb ? T.wa : T.wb;

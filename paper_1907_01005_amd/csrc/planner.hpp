@@ -100,9 +100,11 @@ struct ApplyItem {
 static_assert(sizeof(ApplyItem) == 232, "ApplyItem layout");
 
 // One block product of Alg. 8: X_{r,C1}^T Y_{r,C2} into partial[part].
+// tslot >= 0 for the products with C1 = C2: the slot of its own trace
+// (sum over the block's diagonal) in the overlap's diagonal list.
 struct TmUnit {
   int64_t off1, off2, part;
-  int32_t rows, w1, w2, pad;
+  int32_t rows, w1, w2, tslot;
 };
 static_assert(sizeof(TmUnit) == 40, "TmUnit layout");
 
@@ -155,8 +157,8 @@ struct MvPlan {
   std::vector<int32_t> shell_ro;     // present row offsets of the shell items
   int64_t apply_pairs = 0, apply_pairs_own = 0;
   std::vector<TmUnit> units;         // Alg. 8 block products, sorted by kernel class:
-  // 0: 8x8 blocks of at most 128 rows, 1: longer 8x8 blocks with even
-  // offsets, 2: other blocks of at most 128 rows, 3: the rest
+  // 0: 8x8 blocks of at most 128 rows, 1: other blocks at most 8 wide on
+  // both sides, 2: wider blocks of at most 128 rows, 3: the rest
   std::array<int64_t, 4> tm_class_end{};  // cumulative unit counts per class
   std::vector<TmTask> tasks;         // dense row blocks, by tile class (widths <= 64, 96, 128)
   std::array<int64_t, 3> task_class_end{};
@@ -164,6 +166,7 @@ struct MvPlan {
   std::vector<int64_t> task_part;
   std::vector<S2Desc> s2;            // [ncb*ncb] blocks of S, most partials first
   int64_t part_doubles = 0;
+  int64_t ndiag = 0;                 // units with C1 = C2 (one trace slot each)
   std::vector<int32_t> pair_tab;     // ncb*ncb -> pair id or -1
   std::vector<int32_t> pair_ptr;     // npairs + 1: prefix count of partial products per pair
   std::vector<int64_t> pair_list;    // npairs: offset of the pair's contiguous partials

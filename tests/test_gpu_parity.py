@@ -96,6 +96,15 @@ def test_generic_values_ragged_blocks(degree):
         _check_full(wl, op, dp, 0, TOL64, tuned=kernel, ref=ref)
         _check_full(wl, op, dp, 1, TOL64, tuned=kernel, ref=ref)
         _check_full(wl, op, dp, 2, TOL32, tuned=kernel, ref=ref)
+    if degree <= 2:   # register-resident waves: vector-ALU forms at p <= 2
+        _check_full(wl, op, dp, 0, TOL64, tuned=8, ref=ref)
+        _check_full(wl, op, dp, 3, TOL32, tuned=8, ref=ref)
+    else:
+        from paper_1907_01005_amd import MfbError
+        import paper_1907_01005_amd._native as N
+        with pytest.raises(MfbError) as e:
+            dp.apply_tuned(0, kernel=8)
+        assert e.value.code == N.MFB_EUNSUPPORTED
     for spw in (1, 4, 64):
         _check_full(wl, op, dp, 0, TOL64, tuned=(0, spw), ref=ref)
 
@@ -126,6 +135,8 @@ def test_few_nonzero_shell_items(degree):
         _check_full(wl, op, dp, 0, TOL64, tuned=(0, spw))
     _check_full(wl, op, dp, 2, TOL32, tuned=(0, 4))
     _check_full(wl, op, dp, 0, TOL64, tuned=1)
+    if degree <= 2:
+        _check_full(wl, op, dp, 0, TOL64, tuned=8)
 
 
 def test_natural_bc_lexicographic_free_faces():
@@ -202,7 +213,7 @@ def test_repeat_determinism_and_queue_kernel():
     Y2, S2, _ = _run(dp, 0)
     scale = np.abs(Y1).max()
     assert np.abs(Y1 - Y2).max() <= 1e-14 * scale
-    for kernel in range(1, 8):
+    for kernel in range(1, 9):
         Y3, S3, _ = _run(dp, 0, tuned=kernel)
         assert np.abs(Y1 - Y3).max() <= 1e-14 * scale, kernel
     # the overlap reduction has a fixed order: bitwise repeatable for equal inputs
@@ -235,6 +246,9 @@ def test_paper_scale_full(cfg):
     say(f"config{cfg}: oracle done, {len(node)} stored entries")
     for prec, tol in PRECS:
         _check_full(wl, op, dp, prec, tol, ref=ref)
+    if wl.mesh.degree <= 2:
+        _check_full(wl, op, dp, 0, TOL64, tuned=8, ref=ref)
+        _check_full(wl, op, dp, 3, TOL32, tuned=8, ref=ref)
 
 
 @pytest.mark.parametrize("degree", [1, 2, 3, 4])

@@ -157,8 +157,9 @@ def test_dense_row_blocks_become_tasks(radius, closure):
     (64, 96, 128 columns) of its widest member, and costs at most 1.25 times
     the members' own products.  Every other
     (row block, C1, C2) product is a unit.  One partial per unit and per
-    (run, pair meeting in one of its row blocks): the task count, the unit
-    count and the workspace follow from the pattern."""
+    (run, pair meeting in one of its row blocks), and one trace slot per unit
+    with C1 = C2: the task count, the unit count and the workspace follow from
+    the pattern."""
     sizes = [8, 5, 12, 4, 16, 7, 9, 3, 11, 6, 10, 9, 14, 2, 13, 11]
     ms = synth.MeshSpec(8, 6, 4, (8.0, 6.0, 4.0), 2, 0x3F)
     wl = synth.custom_workload(ms, sum(sizes), radius, 5, potential="wells", name="dense")
@@ -182,12 +183,13 @@ def test_dense_row_blocks_become_tasks(radius, closure):
                 and rows[r] <= 128)
 
     tasks = units = 0
-    parts = 0
+    parts = diag = 0
     r = 0
     while r < nr:
         if not qualifies(r):
             units += len(A[r]) * len(B[r])
             parts += sum(w[a] * w[b] for a in A[r] for b in B[r])
+            diag += len(A[r] & B[r])     # products with C1 = C2 keep a trace slot each
             r += 1
             continue
         ua, ub, nrows = set(A[r]), set(B[r]), int(rows[r])
@@ -210,7 +212,7 @@ def test_dense_row_blocks_become_tasks(radius, closure):
         r += n
     assert tasks > 0
     assert y.info["tm_tasks"] == tasks and y.info["tm_units"] == units
-    assert y.info["work_bytes"] == 256 + 8 * parts
+    assert y.info["work_bytes"] == 256 + 8 * (parts + diag)
 
 
 @pytest.mark.parametrize("cfg", [1, 2, 3])
