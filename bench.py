@@ -395,10 +395,10 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--prec", default="fp64", choices=sorted(PRECS))
     ap.add_argument("--config", type=int, default=2, choices=[2, 3])
-    ap.add_argument("--kernel", type=int, default=0, choices=[0, 1, 7, 8],
+    ap.add_argument("--kernel", type=int, default=0, choices=[0, 1, 2, 7, 8],
                     help="0: the library's default apply; otherwise an explicit kernel of "
-                         "mfb_apply_H_tuned (1: persistent queue, 7: loader-pipelined, "
-                         "8: register-resident waves)")
+                         "mfb_apply_H_tuned (1: persistent queue, 2: batch grid, "
+                         "7: loader-pipelined, 8: register-resident waves)")
     ap.add_argument("--radius", type=float, default=0.0,
                     help="replace the support radius (e.g. 16: the paper's density, ~575 MB "
                          "of X at config 2; not the baseline workload)")
@@ -480,7 +480,7 @@ def main(argv=None):
         "config": {"workload": wl.name, "dofs": dp.mesh.ndofs, "orbitals": dp.M,
                    "colblocks": int(len(wl.colblock_sizes)), "radius": wl.radius,
                    "degree": degree, "stored_entries": alg["E"], "prec": args.prec,
-                   "kernel": {0: "default", 1: "queue", 7: "loader-pipelined",
+                   "kernel": {0: "default", 1: "queue", 2: "batch-grid", 7: "loader-pipelined",
                               8: "register-waves"}[args.kernel]},
         "launch": "the K timed steps as one hipGraph (apply_H: zero fill + apply; tmmult: "
                   "stage-1 classes present in the layout, stage 2, trace); eager loop below",

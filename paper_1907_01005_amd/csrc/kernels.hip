@@ -401,6 +401,140 @@ __device__ __forceinline__ void plane_operator(const Ctr& ctr, R* __restrict__ T
   ctr.template c<0, true, 0>(B, out);
 }
 
+// In place along one index of a plane: p[o][line] <- sum_k M(o, k) p[k][line]
+// (AX = 0) or p[line][o] <- sum_k M(o, k) p[line][k] (AX = 1), M(o, k) =
+// M[o n + k], or M[k n + o] when TR; n temporaries per line.
+template <int n, int AX, bool TR, typename R>
+__device__ __forceinline__ void contract_ip(const R* __restrict__ M, R (&p)[n][n]) {
+#pragma unroll
+  for (int line = 0; line < n; ++line) {
+    R t[n];
+#pragma unroll
+    for (int o = 0; o < n; ++o) {
+      R s = 0;
+#pragma unroll
+      for (int k = 0; k < n; ++k)
+        s = fma_r(TR ? M[k * n + o] : M[o * n + k], AX == 0 ? p[k][line] : p[line][k], s);
+      t[o] = s;
+    }
+#pragma unroll
+    for (int o = 0; o < n; ++o) {
+      if (AX == 0) p[o][line] = t[o];
+      else p[line][o] = t[o];
+    }
+  }
+}
+
+// The gradient term along index AX of a plane, line by line: g = gl(line)
+// (.) Dw u_line (the derivative at the Gauss points with the weights folded
+// into Dw = diag(w) D, times the line's constant), then D^T g is stored into
+// w (ADD: added to w).  IP: w is u itself (each line is overwritten after
+// its derivative is taken).
+template <int n, int AX, bool ADD, typename R, class GL>
+__device__ __forceinline__ void grad_plane(const R (&u)[n][n], R (&w)[n][n], const R* __restrict__ Dw,
+                                           const R* __restrict__ Dm, GL gl) {
+#pragma unroll
+  for (int line = 0; line < n; ++line) {
+    R g[n];
+    const double sc = gl(line);
+#pragma unroll
+    for (int o = 0; o < n; ++o) {
+      R s = 0;
+#pragma unroll
+      for (int k = 0; k < n; ++k) s = fma_r(Dw[o * n + k], AX == 0 ? u[k][line] : u[line][k], s);
+      g[o] = (R)((double)s * sc);
+    }
+#pragma unroll
+    for (int o = 0; o < n; ++o) {
+      R s = ADD ? (AX == 0 ? w[o][line] : w[line][o]) : (R)0;
+#pragma unroll
+      for (int k = 0; k < n; ++k) s = fma_r(Dm[k * n + o], g[k], s);
+      if (AX == 0) w[o][line] = s;
+      else w[line][o] = s;
+    }
+  }
+}
+
+// The box-cell operator of plane_operator with at most two planes live per
+// thread: contractions in place, the gradient terms line by line (derivative,
+// the line's scale and the transpose derivative in one pass, the weights
+// folded into Dw), so the quadrature values and the accumulated result are
+// the only planes held across a layout switch.  Same layouts, barriers and
+// calling convention as plane_operator; u is overwritten.
+template <typename R, int P, class Hook>
+__device__ __forceinline__ void plane_operator_lean(const ApplyParams& a, R* __restrict__ Tc, int pl,
+                                                    const double* cv, R (&u)[P + 1][P + 1],
+                                                    R (&out)[P + 1][P + 1], Hook after_first_barrier) {
+  constexpr int n = P + 1, n2 = n * n;
+  const R* __restrict__ Sm = tab_S<R>(a);
+  const R* __restrict__ Dm = tab_D<R>(a);
+  const R* __restrict__ Dw = reg_Dw<R>(a);
+  // layout A (z = pl): interpolate along x and y
+  contract_ip<n, 0, false>(Sm, u);
+  contract_ip<n, 1, false>(Sm, u);
+#pragma unroll
+  for (int j = 0; j < n; ++j)
+#pragma unroll
+    for (int i = 0; i < n; ++i) Tc[i + n * j + n2 * pl] = u[i][j];
+  __syncthreads();
+  after_first_barrier();
+  // the potential's coefficients are read here, where they are used: the
+  // empty asm keeps their loads from being hoisted (and held in registers)
+  // across the first phase
+  asm volatile("" : "+v"(cv));
+  // layout B (y = pl): along z, then the x and z gradient terms and V
+  R uq[n][n], w[n][n];
+#pragma unroll
+  for (int k = 0; k < n; ++k)
+#pragma unroll
+    for (int i = 0; i < n; ++i) uq[i][k] = Tc[i + n * pl + n2 * k];
+  contract_ip<n, 1, false>(Sm, uq);
+  grad_plane<n, 0, false>(uq, w, Dw, Dm, [&](int k) { return a.gline[0][pl + n * k]; });
+  grad_plane<n, 1, true>(uq, w, Dw, Dm, [&](int i) { return a.gline[2][i + n * pl]; });
+#pragma unroll
+  for (int i = 0; i < n; ++i)
+#pragma unroll
+    for (int k = 0; k < n; ++k)
+      w[i][k] = (R)((double)w[i][k] + cv[i + n * pl + n2 * k] * (double)uq[i][k]);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < n; ++k)
+#pragma unroll
+    for (int i = 0; i < n; ++i) Tc[i + n * pl + n2 * k] = uq[i][k];
+  __syncthreads();
+  // layout A: the y gradient term, in place
+#pragma unroll
+  for (int j = 0; j < n; ++j)
+#pragma unroll
+    for (int i = 0; i < n; ++i) u[i][j] = Tc[i + n * j + n2 * pl];
+  grad_plane<n, 1, false>(u, u, Dw, Dm, [&](int i) { return a.gline[1][i + n * pl]; });
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < n; ++j)
+#pragma unroll
+    for (int i = 0; i < n; ++i) Tc[i + n * j + n2 * pl] = u[i][j];
+  __syncthreads();
+  // layout B: add the y part, integrate back along z
+#pragma unroll
+  for (int k = 0; k < n; ++k)
+#pragma unroll
+    for (int i = 0; i < n; ++i) w[i][k] += Tc[i + n * pl + n2 * k];
+  contract_ip<n, 1, true>(Sm, w);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < n; ++k)
+#pragma unroll
+    for (int i = 0; i < n; ++i) Tc[i + n * pl + n2 * k] = w[i][k];
+  __syncthreads();
+  // layout A: integrate back along y and x
+#pragma unroll
+  for (int j = 0; j < n; ++j)
+#pragma unroll
+    for (int i = 0; i < n; ++i) out[i][j] = Tc[i + n * j + n2 * pl];
+  contract_ip<n, 1, true>(Sm, out);
+  contract_ip<n, 0, true>(Sm, out);
+}
+
 // The operator on curved cells.  The metric c(q) = 1/2 JxW_q J^{-1} J^{-T}
 // (six planes per cell: 00, 11, 22, 01, 02, 12) couples the three reference
 // gradients at every quadrature point, so they must meet there.  D_y
@@ -697,6 +831,8 @@ struct BatchProc {
       if constexpr (GEO && OP == 0)
         plane_operator_geo<R, P>(make_ctr<R, P, MF>(a), Tc, tile2(sm) + (t & 63) * D::n3, pl, cv,
                                  a.cG + cell * 6 * D::n3, u, out, hook);
+      else if constexpr (OP == 0 && !MF)
+        plane_operator_lean<R, P>(a, Tc, pl, cv, u, out, hook);
       else if constexpr (OP == 0)
         plane_operator<R, P>(make_ctr<R, P, MF>(a), Tc, pl, cv, wg, true, u, out, hook);
       else if constexpr (GEO)
@@ -719,11 +855,24 @@ struct BatchProc {
 #pragma unroll
       for (int i = 0; i < n; ++i) unsafeAtomicAdd(&G[base + (i + NB * j) * 8], (double)out[i][j]);
     __syncthreads();
-    if constexpr (!DEST) {
+    if constexpr (!DEST && P <= 2) {
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         if (ro[k] < 0) continue;
         unsafeAtomicAdd(a.Y + (int64_t)ro[k] + ((t + k * NT) & 7), G[t + k * NT]);
+      }
+    } else if constexpr (!DEST) {
+      // p >= 3: the row offsets are read again here rather than held in
+      // registers through the operator
+      const int32_t* r2 = a.rowoff + idx * D::NB3;
+      asm volatile("" : "+s"(r2));  // a fresh read, not the gather's values kept live
+      const int nc = a.items[idx].nc;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int e2 = t + k * NT;
+        if (e2 >= NV || (e2 & 7) >= nc) continue;
+        const int32_t o = r2[e2 >> 3];
+        if (o >= 0) unsafeAtomicAdd(a.Y + (int64_t)o + (e2 & 7), G[e2]);
       }
     } else {
       const int32_t* __restrict__ r2 = a.rowoff_out + idx * D::NB3;
@@ -1525,8 +1674,11 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-template <typename R, int P, bool MF, int OP = 0, bool DEST = false, bool GEO = false>
-__global__ __launch_bounds__(64 * (P + 1)) void apply_fused_kernel(ApplyParams a, int spw) {
+// OCC > 0: at least OCC waves per SIMD (a register budget of 512 / OCC);
+// 0 leaves the budget to the compiler.
+template <typename R, int P, bool MF, int OP = 0, bool DEST = false, bool GEO = false, int OCC = 0>
+__global__ __launch_bounds__(64 * (P + 1)) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1, 8)))
+void apply_fused_kernel(ApplyParams a, int spw) {
   using Proc = BatchProc<R, P, MF, OP, DEST, GEO>;
   constexpr int NW = Proc::NT / 64;
   __shared__ typename Proc::Smem sm;
@@ -1718,7 +1870,9 @@ struct LoaderPipe {
         if (t + k * NTC < NV) G[t + k * NTC] = 0.0;
     };
     R out[n][n];
-    if constexpr (OP == 0)
+    if constexpr (OP == 0 && !MF)
+      plane_operator_lean<R, P>(a, T + (t & 63) * n3, pl, cur.cv + e * n3, u, out, zero_sums);
+    else if constexpr (OP == 0)
       plane_operator<R, P>(make_ctr<R, P, MF>(a), T + (t & 63) * n3, pl, cur.cv + e * n3, wg,
                            true, u, out, zero_sums);
     else
@@ -1933,7 +2087,7 @@ hipError_t launch_pipe(const ApplyParams& p, hipStream_t st) {
 
 // Own and shell items in one grid; spw = shell items checked per wave (a
 // power of two up to 64; 0 = 2).
-template <typename R, int P, bool MF, int OP>
+template <typename R, int P, bool MF, int OP, int OCC = 0>
 hipError_t launch_fused(const ApplyParams& p, int spw, hipStream_t st) {
   using Proc = BatchProc<R, P, MF, OP>;
   if (spw <= 0) spw = 2;
@@ -1949,9 +2103,9 @@ hipError_t launch_fused(const ApplyParams& p, int spw, hipStream_t st) {
     else
       hipLaunchKernelGGL((apply_fused_kernel<R, P, MF, OP, true, true>), grid, block, 0, st, p, spw);
   } else if (!dest) {
-    hipLaunchKernelGGL((apply_fused_kernel<R, P, MF, OP, false>), grid, block, 0, st, p, spw);
+    hipLaunchKernelGGL((apply_fused_kernel<R, P, MF, OP, false, false, OCC>), grid, block, 0, st, p, spw);
   } else {
-    hipLaunchKernelGGL((apply_fused_kernel<R, P, MF, OP, true>), grid, block, 0, st, p, spw);
+    hipLaunchKernelGGL((apply_fused_kernel<R, P, MF, OP, true, false, OCC>), grid, block, 0, st, p, spw);
   }
   return hipGetLastError();
 }
@@ -2017,6 +2171,10 @@ hipError_t launch_apply_t(const ApplyParams& p, int kernel, hipStream_t st) {
   // for p = 4)
   const int proc = kernel >> 1;
   const bool batch = proc <= 1;
+  // kernel 2 at p = 4 (fp64, vector ALUs): the fused grid held to three waves
+  // per SIMD (168 registers), so that two 320-thread workgroups share a CU
+  if constexpr (P == 4 && !MF && std::is_same<R, double>::value)
+    if (kernel == 2) return launch_fused<R, P, MF, 0, 3>(p, p.grid, st);
   if (batch && !queue) return launch_fused<R, P, MF, 0>(p, p.grid, st);
   hipError_t e;
   if (batch) {
