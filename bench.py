@@ -259,16 +259,36 @@ def config4_forms():
     return out
 
 
+def attach_inputs(reqs, threads: int = 8):
+    """The client side: every request's data (potential at the library's
+    quadrature points, orbital centres and values) drawn before the stream
+    starts, as the clients of a service would send them."""
+    from concurrent.futures import ThreadPoolExecutor
+    import synth
+    from paper_1907_01005_amd import Mesh
+
+    def one(r):
+        m = Mesh(*r.cells, tuple(float(c) for c in r.cells), r.degree)
+        r.inputs = synth.request_inputs(r.cells, r.degree, r.M, r.radius, r.seed, m.qp_points())
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        list(pool.map(one, reqs))
+    return reqs
+
+
 def serving_form(n: int, budget_mb: int, method: str = "rayleigh"):
     from paper_1907_01005_amd.serving import GpuExecutor, Server, request_stream, summarize
     reqs = request_stream(n=n, method=method)
+    t0 = time.perf_counter()
+    attach_inputs(reqs)
+    t_inputs = time.perf_counter() - t0
     ex = GpuExecutor(planner_threads=8)
     def progress(k, total):
         if k % 8 == 0 or k == total:
             print(f"[bench] serving: {k}/{total} requests done", file=sys.stderr, flush=True)
     rep = Server(ex, byte_budget=budget_mb << 20, max_slots=8).run(reqs, progress=progress)
     s = summarize(rep)
-    s.update({"requests": n, "rate_per_s": 40.0, "byte_budget_mb": budget_mb, "method": method})
+    s.update({"requests": n, "rate_per_s": 40.0, "byte_budget_mb": budget_mb, "method": method,
+              "client_inputs_s": t_inputs})
     if method == "om":
         done = [r for r in rep.results.values() if "energies" in r]
         s["om_energy_decreased"] = sum(1 for r in done if r["energies"][-1] < r["energies"][0])

@@ -563,6 +563,13 @@ static void fill_apply_params(const mfb_mesh* mesh, const mfb_mv* mv, const doub
     a.Dw[i] = b.wq[i / n] * b.Dco[i];
     a.Dwf[i] = (float)a.Dw[i];
   }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double k1 = 0.0;
+      for (int q = 0; q < n; ++q) k1 += b.Dco[q * n + i] * b.wq[q] * b.Dco[q * n + j];
+      a.K1[i * n + j] = k1;
+      a.K1f[i * n + j] = (float)k1;
+    }
   const double det = m.h[0] * m.h[1] * m.h[2];
   for (int d = 0; d < 3; ++d)
     for (int q = 0; q < n * n; ++q)
@@ -767,12 +774,8 @@ int mfb_mv_dot(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d
   MFB_CATCH
 }
 
-int mfb_tmmult(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d_S, double* d_trace,
-               void* d_work, void* stream) {
-  MFB_TRY
-  if (!mv || !d_X || !d_Y || !d_S || !d_trace || !d_work) fail(MFB_EINVAL, "null argument");
-  if (!mv->bound) fail(MFB_ESTATE, "layout metadata not bound");
-  if (((uintptr_t)d_work & 255) != 0) fail(MFB_EINVAL, "d_work must be 256-byte aligned");
+static void tmmult_enqueue(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d_S,
+                           double* d_trace, void* d_work, void* stream) {
   const auto& p = mv->plan;
   const char* mb = (const char*)mv->d_meta;
   mfb::gpu::TmParams t;
@@ -805,6 +808,15 @@ int mfb_tmmult(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d
   t.trace = d_trace;
   const int rc = mfb::gpu::launch_tmmult(t, stream);
   if (rc != 0) fail(MFB_EHIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)rc));
+}
+
+int mfb_tmmult(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d_S, double* d_trace,
+               void* d_work, void* stream) {
+  MFB_TRY
+  if (!mv || !d_X || !d_Y || !d_S || !d_trace || !d_work) fail(MFB_EINVAL, "null argument");
+  if (!mv->bound) fail(MFB_ESTATE, "layout metadata not bound");
+  if (((uintptr_t)d_work & 255) != 0) fail(MFB_EINVAL, "d_work must be 256-byte aligned");
+  tmmult_enqueue(mv, d_X, d_Y, d_S, d_trace, d_work, stream);
   return MFB_OK;
   MFB_CATCH
 }

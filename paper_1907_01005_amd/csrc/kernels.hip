@@ -95,6 +95,39 @@ __device__ __forceinline__ const double* reg_Dw<double>(const ApplyParams& a) { 
 template <>
 __device__ __forceinline__ const float* reg_Dw<float>(const ApplyParams& a) { return a.Dwf; }
 
+template <typename R>
+__device__ __forceinline__ const R* tab_K(const ApplyParams& a);
+template <>
+__device__ __forceinline__ const double* tab_K<double>(const ApplyParams& a) { return a.K1; }
+template <>
+__device__ __forceinline__ const float* tab_K<float>(const ApplyParams& a) { return a.K1f; }
+
+// The 1D tables are symmetric about the middle of the interval: the nodes and
+// the Gauss points are, so S(o, k) = S(n-1-o, n-1-k), D(o, k) = -D(n-1-o,
+// n-1-k) for the collocation derivative, and the stiffness K1 keeps its value
+// under that map and under transposition.  Reading every coefficient at the
+// first of its equivalent positions (with D's sign) leaves about a quarter
+// (K1) to a half (S, D) of the entries to hold in scalar registers.  The
+// indices are compile-time constants after unrolling, so this folds away.
+enum { kTabS = 0, kTabD = 1, kTabK = 2 };
+template <int n, int KIND, typename R>
+__device__ __forceinline__ R coef(const R* __restrict__ T, int o, int k) {
+  int c = o * n + k;
+  bool neg = false;
+  const int m = (n - 1 - o) * n + (n - 1 - k);
+  if (m < c) {
+    c = m;
+    neg = KIND == kTabD;
+  }
+  if (KIND == kTabK) {
+    const int t1 = k * n + o, t2 = (n - 1 - k) * n + (n - 1 - o);
+    if (t1 < c) c = t1;
+    if (t2 < c) c = t2;
+  }
+  const R v = T[c];
+  return neg ? -v : v;
+}
+
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 // Contractions on the vector ALUs; MAT selects S (0) or D (1).
@@ -402,9 +435,10 @@ __device__ __forceinline__ void plane_operator(const Ctr& ctr, R* __restrict__ T
 }
 
 // In place along one index of a plane: p[o][line] <- sum_k M(o, k) p[k][line]
-// (AX = 0) or p[line][o] <- sum_k M(o, k) p[line][k] (AX = 1), M(o, k) =
-// M[o n + k], or M[k n + o] when TR; n temporaries per line.
-template <int n, int AX, bool TR, typename R>
+// (AX = 0) or p[line][o] <- sum_k M(o, k) p[line][k] (AX = 1), with M(o, k)
+// the table's entry (TR: M(k, o)) read through its symmetry; n temporaries
+// per line.
+template <int n, int AX, bool TR, int KIND, typename R>
 __device__ __forceinline__ void contract_ip(const R* __restrict__ M, R (&p)[n][n]) {
 #pragma unroll
   for (int line = 0; line < n; ++line) {
@@ -414,7 +448,8 @@ __device__ __forceinline__ void contract_ip(const R* __restrict__ M, R (&p)[n][n
       R s = 0;
 #pragma unroll
       for (int k = 0; k < n; ++k)
-        s = fma_r(TR ? M[k * n + o] : M[o * n + k], AX == 0 ? p[k][line] : p[line][k], s);
+        s = fma_r(TR ? coef<n, KIND>(M, k, o) : coef<n, KIND>(M, o, k),
+                  AX == 0 ? p[k][line] : p[line][k], s);
       t[o] = s;
     }
 #pragma unroll
@@ -425,53 +460,51 @@ __device__ __forceinline__ void contract_ip(const R* __restrict__ M, R (&p)[n][n
   }
 }
 
-// The gradient term along index AX of a plane, line by line: g = gl(line)
-// (.) Dw u_line (the derivative at the Gauss points with the weights folded
-// into Dw = diag(w) D, times the line's constant), then D^T g is stored into
-// w (ADD: added to w).  IP: w is u itself (each line is overwritten after
-// its derivative is taken).
+// The gradient term along index AX of a plane with the 1D stiffness
+// K1 = D^T diag(w) D: along a line of constant (a, b) the term is
+// 1/2 hx hy hz / h_d^2 w_a w_b K1 u_line (eq. fe_matrices with the
+// collocation derivative at the Gauss points), the scale in float64.  The
+// result is stored into w (ADD: added to w); w may be u itself (each line's
+// product is formed before the line is written).
 template <int n, int AX, bool ADD, typename R, class GL>
-__device__ __forceinline__ void grad_plane(const R (&u)[n][n], R (&w)[n][n], const R* __restrict__ Dw,
-                                           const R* __restrict__ Dm, GL gl) {
+__device__ __forceinline__ void stiff_plane(const R (&u)[n][n], R (&w)[n][n], const R* __restrict__ K,
+                                            GL gl) {
 #pragma unroll
   for (int line = 0; line < n; ++line) {
-    R g[n];
-    const double sc = gl(line);
+    R t[n];
 #pragma unroll
     for (int o = 0; o < n; ++o) {
       R s = 0;
 #pragma unroll
-      for (int k = 0; k < n; ++k) s = fma_r(Dw[o * n + k], AX == 0 ? u[k][line] : u[line][k], s);
-      g[o] = (R)((double)s * sc);
+      for (int k = 0; k < n; ++k) s = fma_r(coef<n, kTabK>(K, o, k), AX == 0 ? u[k][line] : u[line][k], s);
+      t[o] = s;
     }
+    const double sc = gl(line);
 #pragma unroll
     for (int o = 0; o < n; ++o) {
-      R s = ADD ? (AX == 0 ? w[o][line] : w[line][o]) : (R)0;
-#pragma unroll
-      for (int k = 0; k < n; ++k) s = fma_r(Dm[k * n + o], g[k], s);
-      if (AX == 0) w[o][line] = s;
-      else w[line][o] = s;
+      R& dst = AX == 0 ? w[o][line] : w[line][o];
+      dst = ADD ? (R)((double)dst + (double)t[o] * sc) : (R)((double)t[o] * sc);
     }
   }
 }
 
 // The box-cell operator of plane_operator with at most two planes live per
-// thread: contractions in place, the gradient terms line by line (derivative,
-// the line's scale and the transpose derivative in one pass, the weights
-// folded into Dw), so the quadrature values and the accumulated result are
-// the only planes held across a layout switch.  Same layouts, barriers and
-// calling convention as plane_operator; u is overwritten.
+// thread: contractions in place and the gradient terms through the 1D
+// stiffness K1 (one contraction per direction instead of a derivative, a
+// scaling and a transposed derivative), so the quadrature values and the
+// accumulated result are the only planes held across a layout switch.  Same
+// layouts, barriers and calling convention as plane_operator; u is
+// overwritten.
 template <typename R, int P, class Hook>
 __device__ __forceinline__ void plane_operator_lean(const ApplyParams& a, R* __restrict__ Tc, int pl,
                                                     const double* cv, R (&u)[P + 1][P + 1],
                                                     R (&out)[P + 1][P + 1], Hook after_first_barrier) {
   constexpr int n = P + 1, n2 = n * n;
   const R* __restrict__ Sm = tab_S<R>(a);
-  const R* __restrict__ Dm = tab_D<R>(a);
-  const R* __restrict__ Dw = reg_Dw<R>(a);
+  const R* __restrict__ K = tab_K<R>(a);
   // layout A (z = pl): interpolate along x and y
-  contract_ip<n, 0, false>(Sm, u);
-  contract_ip<n, 1, false>(Sm, u);
+  contract_ip<n, 0, false, kTabS>(Sm, u);
+  contract_ip<n, 1, false, kTabS>(Sm, u);
 #pragma unroll
   for (int j = 0; j < n; ++j)
 #pragma unroll
@@ -488,9 +521,9 @@ __device__ __forceinline__ void plane_operator_lean(const ApplyParams& a, R* __r
   for (int k = 0; k < n; ++k)
 #pragma unroll
     for (int i = 0; i < n; ++i) uq[i][k] = Tc[i + n * pl + n2 * k];
-  contract_ip<n, 1, false>(Sm, uq);
-  grad_plane<n, 0, false>(uq, w, Dw, Dm, [&](int k) { return a.gline[0][pl + n * k]; });
-  grad_plane<n, 1, true>(uq, w, Dw, Dm, [&](int i) { return a.gline[2][i + n * pl]; });
+  contract_ip<n, 1, false, kTabS>(Sm, uq);
+  stiff_plane<n, 0, false>(uq, w, K, [&](int k) { return a.gline[0][pl + n * k]; });
+  stiff_plane<n, 1, true>(uq, w, K, [&](int i) { return a.gline[2][i + n * pl]; });
 #pragma unroll
   for (int i = 0; i < n; ++i)
 #pragma unroll
@@ -507,7 +540,7 @@ __device__ __forceinline__ void plane_operator_lean(const ApplyParams& a, R* __r
   for (int j = 0; j < n; ++j)
 #pragma unroll
     for (int i = 0; i < n; ++i) u[i][j] = Tc[i + n * j + n2 * pl];
-  grad_plane<n, 1, false>(u, u, Dw, Dm, [&](int i) { return a.gline[1][i + n * pl]; });
+  stiff_plane<n, 1, false>(u, u, K, [&](int i) { return a.gline[1][i + n * pl]; });
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < n; ++j)
@@ -519,7 +552,7 @@ __device__ __forceinline__ void plane_operator_lean(const ApplyParams& a, R* __r
   for (int k = 0; k < n; ++k)
 #pragma unroll
     for (int i = 0; i < n; ++i) w[i][k] += Tc[i + n * pl + n2 * k];
-  contract_ip<n, 1, true>(Sm, w);
+  contract_ip<n, 1, true, kTabS>(Sm, w);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < n; ++k)
@@ -531,8 +564,8 @@ __device__ __forceinline__ void plane_operator_lean(const ApplyParams& a, R* __r
   for (int j = 0; j < n; ++j)
 #pragma unroll
     for (int i = 0; i < n; ++i) out[i][j] = Tc[i + n * j + n2 * pl];
-  contract_ip<n, 1, true>(Sm, out);
-  contract_ip<n, 0, true>(Sm, out);
+  contract_ip<n, 1, true, kTabS>(Sm, out);
+  contract_ip<n, 0, true, kTabS>(Sm, out);
 }
 
 // The operator on curved cells.  The metric c(q) = 1/2 JxW_q J^{-1} J^{-T}
@@ -1057,29 +1090,44 @@ struct RegProc {
 // that each shared node ends in the lane of the cell with the smallest
 // child index containing it, which alone adds it into Y.
 
-// w += D^T (gl (.) Dw uq) along AXIS, line by line.
-template <int n, int AXIS, typename R>
-__device__ __forceinline__ void grad_line_pass(const R (&uq)[n * n * n], R (&w)[n * n * n],
-                                               const R* __restrict__ Dw, const R* __restrict__ Dm,
-                                               const double* __restrict__ gl) {
+// In place along AXIS of a register tensor u[i + n j + n^2 k], the table read
+// through its symmetry: u_line <- M u_line (M^T when TR).
+template <int n, int AXIS, bool TR, int KIND, typename R>
+__device__ __forceinline__ void sweep_c(R (&u)[n * n * n], const R* __restrict__ M) {
   constexpr int S = AXIS == 0 ? 1 : (AXIS == 1 ? n : n * n);
 #pragma unroll
   for (int l = 0; l < n * n; ++l) {
     const int base = AXIS == 0 ? l * n : (AXIS == 1 ? (l % n) + (l / n) * n * n : l);
-    R gq[n];
+    R tmp[n];
 #pragma unroll
     for (int o = 0; o < n; ++o) {
       R s = 0;
 #pragma unroll
-      for (int k = 0; k < n; ++k) s = fma_r(Dw[o * n + k], uq[base + k * S], s);
-      gq[o] = (R)((double)s * gl[l]);
+      for (int k = 0; k < n; ++k)
+        s = fma_r(TR ? coef<n, KIND>(M, k, o) : coef<n, KIND>(M, o, k), u[base + k * S], s);
+      tmp[o] = s;
     }
 #pragma unroll
-    for (int o = 0; o < n; ++o) {
-      R s = w[base + o * S];
+    for (int o = 0; o < n; ++o) u[base + o * S] = tmp[o];
+  }
+}
+
+// w += gl(line) K1 uq along AXIS, line by line (the gradient term of
+// eq. fe_matrices through the 1D stiffness; the scale in float64).
+template <int n, int AXIS, typename R>
+__device__ __forceinline__ void stiff_line_pass(const R (&uq)[n * n * n], R (&w)[n * n * n],
+                                                const R* __restrict__ K, const double* __restrict__ gl) {
+  constexpr int S = AXIS == 0 ? 1 : (AXIS == 1 ? n : n * n);
 #pragma unroll
-      for (int k = 0; k < n; ++k) s = fma_r(Dm[k * n + o], gq[k], s);
-      w[base + o * S] = s;
+  for (int l = 0; l < n * n; ++l) {
+    const int base = AXIS == 0 ? l * n : (AXIS == 1 ? (l % n) + (l / n) * n * n : l);
+    const double sc = gl[l];
+#pragma unroll
+    for (int o = 0; o < n; ++o) {
+      R s = 0;
+#pragma unroll
+      for (int k = 0; k < n; ++k) s = fma_r(coef<n, kTabK>(K, o, k), uq[base + k * S], s);
+      w[base + o * S] = (R)((double)w[base + o * S] + (double)s * sc);
     }
   }
 }
@@ -1133,26 +1181,25 @@ struct RegWave {
         }
     if (__ballot(any) == 0) return;
     const R* __restrict__ Sm = tab_S<R>(a);
-    sweep<n, 0, false>(u, Sm);
-    sweep<n, 1, false>(u, Sm);
-    sweep<n, 2, false>(u, Sm);
+    sweep_c<n, 0, false, kTabS>(u, Sm);
+    sweep_c<n, 1, false, kTabS>(u, Sm);
+    sweep_c<n, 2, false, kTabS>(u, Sm);
     R w[n3];
     if constexpr (OP == 0) {
       const double* __restrict__ cv = a.cV + ((int64_t)rank * 8 + e) * n3;
 #pragma unroll
       for (int q = 0; q < n3; ++q) w[q] = (R)(cv[q] * (double)u[q]);
-      const R* __restrict__ Dm = tab_D<R>(a);
-      const R* __restrict__ Dw = reg_Dw<R>(a);
-      grad_line_pass<n, 0>(u, w, Dw, Dm, a.gline[0]);
-      grad_line_pass<n, 1>(u, w, Dw, Dm, a.gline[1]);
-      grad_line_pass<n, 2>(u, w, Dw, Dm, a.gline[2]);
+      const R* __restrict__ K = tab_K<R>(a);
+      stiff_line_pass<n, 0>(u, w, K, a.gline[0]);
+      stiff_line_pass<n, 1>(u, w, K, a.gline[1]);
+      stiff_line_pass<n, 2>(u, w, K, a.gline[2]);
     } else {
 #pragma unroll
       for (int q = 0; q < n3; ++q) w[q] = (R)(a.jxw[q] * (double)u[q]);
     }
-    sweep<n, 2, true>(w, Sm);
-    sweep<n, 1, true>(w, Sm);
-    sweep<n, 0, true>(w, Sm);
+    sweep_c<n, 2, true, kTabS>(w, Sm);
+    sweep_c<n, 1, true, kTabS>(w, Sm);
+    sweep_c<n, 0, true, kTabS>(w, Sm);
     face_sum<n, 0>(w, e);
     face_sum<n, 1>(w, e);
     face_sum<n, 2>(w, e);

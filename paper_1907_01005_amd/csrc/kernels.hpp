@@ -44,6 +44,10 @@ struct ApplyParams {
   double Dw[25];
   float Dwf[25];
   double gline[3][25];
+  // the 1D stiffness K1 = D^T diag(w) D on the Gauss points (symmetric, and
+  // unchanged under (o, k) -> (n-1-o, n-1-k))
+  double K1[25];
+  float K1f[25];
 };
 
 struct TmParams {

@@ -27,10 +27,12 @@ once and their kernels overlap on the device (one HIP stream per slot).
 Completion is detected with events, memory is released, and the next
 waiting request is admitted: the batch changes continuously.
 
-The scheduler is independent of the GPU: it drives an ``Executor``.  The GPU
-executor here plans each request on the host (mesh, layout, potential and
-orbital values) in a worker pool when it arrives, and on admission allocates,
-uploads and enqueues all iterations on the slot's stream.
+The scheduler is independent of the GPU: it drives an ``Executor``.  A
+request carries its data (potential at the quadrature points, orbital
+centres and values), prepared by the client before it is sent.  The GPU
+executor plans each request in the library (mesh, BCSR layout, packing) in
+a worker pool when it arrives, and on admission allocates, uploads and
+enqueues all iterations on the slot's stream.
 """
 
 from __future__ import annotations
@@ -64,6 +66,12 @@ class Request:
     seed: int
     method: str = "rayleigh"       # "rayleigh" or "om" (see the module docstring)
     shift: float = 2.0             # "om": the spectral shift (potential V - shift)
+    # the request's data, prepared by the client before it is sent: box
+    # lengths and Dirichlet faces, orbital centres, support radius, column-
+    # block sizes, the potential at the quadrature points of the mesh
+    # ([ncells][nq], library cell order) and the orbital values as (node,
+    # orbital, value) triplets
+    inputs: Optional[dict] = None
 
 
 def request_stream(n: int = 96, rate: float = 40.0, seed: int = 5, meshes=MESHES,
@@ -222,18 +230,17 @@ class GpuExecutor:
 
     # -- planning (host only)
     def _plan(self, req: Request) -> _Plan:
-        import synth
+        """Library planning of one request from the data it carries (host)."""
         from .api import Layout, Mesh
+        d = req.inputs
+        if d is None:
+            raise ValueError(f"request {req.rid} carries no inputs (the client prepares them)")
         cells = req.cells
-        L = tuple(float(c) for c in cells)        # unit cell width
-        ms = synth.MeshSpec(*cells, L, req.degree)
-        wl = synth.custom_workload(ms, req.M, req.radius, req.seed, potential="wells")
-        mesh = Mesh(*cells, L, req.degree, ms.dirichlet)
-        V = synth.potential_at(wl, mesh.qp_points().reshape(-1, 3))
+        mesh = Mesh(*cells, d["L"], req.degree, d["dirichlet"])
+        V = np.asarray(d["v_qp"], dtype=np.float64)
         mesh.set_potential(V - req.shift if req.method == "om" else V)
-        layout = Layout(mesh, wl.centres, wl.radius, wl.colblock_sizes)
-        node, orb, val = synth.orbital_values(wl)
-        values = layout.pack(node, orb, val)
+        layout = Layout(mesh, d["centres"], d["radius"], d["colblock_sizes"])
+        values = layout.pack(d["node"], d["orb"], d["val"])
         M = layout.M
         nbytes = (2 * 8 * max(layout.nvalues, 1) + mesh.meta_bytes + layout.meta_bytes
                   + layout.work_bytes + 2 * 8 * M * M + 16)

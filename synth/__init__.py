@@ -21,4 +21,5 @@ from .workloads import (  # noqa: F401
     potential_at,
     orbital_values,
     orbital_values_generic,
+    request_inputs,
 )

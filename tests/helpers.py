@@ -76,3 +76,14 @@ def oracle_full(op, node: np.ndarray, orb: np.ndarray):
     S = overlap(op.X_sparse(), Ys)
     assert not np.isnan(out).any(), "a stored entry outside every column block"
     return out, S, trace(S)
+
+
+def attach_inputs(reqs):
+    """Client side of the serving tests: each request's data (potential at the
+    library's quadrature points, orbital centres and values), drawn before
+    the requests are sent."""
+    from paper_1907_01005_amd import Mesh
+    for r in reqs:
+        m = Mesh(*r.cells, tuple(float(c) for c in r.cells), r.degree)
+        r.inputs = synth.request_inputs(r.cells, r.degree, r.M, r.radius, r.seed, m.qp_points())
+    return reqs

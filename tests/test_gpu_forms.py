@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import synth
-from helpers import device_problem, gate, gpu_available, oracle_full, rel_fro, say
+from helpers import attach_inputs, device_problem, gate, gpu_available, oracle_full, rel_fro, say
 from oracle.workload import OracleProblem
 
 pytestmark = pytest.mark.gpu
@@ -106,6 +106,7 @@ def test_serving_results_same_alone_and_in_mix():
     for i, (cells, deg) in enumerate(shapes):
         prec = FP64 if i % 2 == 0 else FP32_MFMA
         reqs.append(Request(i, 0.002 * i, cells, deg, 20 + 7 * i, 3.0, prec, 4, 100 + i))
+    attach_inputs(reqs)
     ex = GpuExecutor(planner_threads=2, keep_X=True)
     budget = 3 * max(ex.footprint(ex._plan(r)) for r in reqs)   # forces queueing
     mix = Server(ex, byte_budget=budget, max_slots=3).run(reqs)
@@ -115,7 +116,7 @@ def test_serving_results_same_alone_and_in_mix():
     for r in reqs:
         alone = Server(GpuExecutor(planner_threads=1, keep_X=True), byte_budget=budget,
                        max_slots=1).run([Request(r.rid, 0.0, r.cells, r.degree, r.M, r.radius,
-                                                 r.prec, r.iters, r.seed)])
+                                                 r.prec, r.iters, r.seed, inputs=r.inputs)])
         a, b = alone.results[r.rid]["X"], mix.results[r.rid]["X"]
         tol = 1e-12 if r.prec == FP64 else 1e-5
         err = rel_fro(b, a)
@@ -179,8 +180,9 @@ def test_serving_orbital_minimisation_alone_and_in_mix():
     from paper_1907_01005_amd.serving import GpuExecutor, Request, Server, summarize
     say("serving om")
     shapes = [((8, 8, 8), 2), ((8, 6, 6), 4), ((10, 8, 6), 2), ((8, 8, 4), 4)]
-    reqs = [Request(i, 0.002 * i, cells, deg, 16 + 5 * i, 3.0, FP64 if i % 2 == 0 else FP32_MFMA,
-                    4, 300 + i, "om") for i, (cells, deg) in enumerate(shapes)]
+    reqs = attach_inputs([Request(i, 0.002 * i, cells, deg, 16 + 5 * i, 3.0,
+                                  FP64 if i % 2 == 0 else FP32_MFMA, 4, 300 + i, "om")
+                          for i, (cells, deg) in enumerate(shapes)])
     ex = GpuExecutor(planner_threads=2, keep_X=True)
     budget = 2 * max(ex.footprint(ex._plan(r)) for r in reqs)
     mix = Server(ex, byte_budget=budget, max_slots=3).run(reqs)
@@ -196,7 +198,8 @@ def test_serving_orbital_minimisation_alone_and_in_mix():
         assert en[-1] > -20.0 * r.M
         alone = Server(GpuExecutor(planner_threads=1, keep_X=True), byte_budget=budget,
                        max_slots=1).run([Request(r.rid, 0.0, r.cells, r.degree, r.M, r.radius,
-                                                 r.prec, r.iters, r.seed, "om")])
+                                                 r.prec, r.iters, r.seed, "om",
+                                                 inputs=r.inputs)])
         err = rel_fro(res["X"], alone.results[r.rid]["X"])
         say(f"om request {r.rid}: alone-vs-mix rel {err:.2e}")
         assert err <= (1e-12 if r.prec == FP64 else 1e-5)
