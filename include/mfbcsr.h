@@ -402,6 +402,23 @@ int mfb_mv_dot(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d
 int mfb_tmmult(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d_S,
                double* d_trace, void* d_work, void* stream);
 
+/* mfb_tmmult without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory: code under HIP graph capture,
+ * serving loops that must not call hipMalloc, harnesses that forbid it.  The
+ * per-row-block partial products go to a fixed array of 64 MiB in device
+ * memory (67108864 bytes, one per GPU, kept until the process ends); a
+ * layout whose info.work_bytes exceed it is refused with EINVAL before
+ * anything is enqueued (use mfb_tmmult with a workspace then).  Results are
+ * those of mfb_tmmult (the same kernels, the same order of summation).  The
+ * array is shared by every call on a GPU and keeps the last call's partial
+ * products; nothing in it needs clearing (every slot a call reads is
+ * written by the same call first), but calls that overlap in time on one GPU
+ * (different streams) race on it and give wrong results: serialise them.
+ * The stream must belong to the current device.  Errors: EINVAL, ESTATE,
+ * EHIP.                                                                      */
+int mfb_tmmult_noalloc(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d_S,
+                       double* d_trace, void* stream);
+
 /* Column-scaled update on the stored entries of X, the iteration of the
  * serving loop: X <- X - tau (Y - X diag(S) / diag(S2)), where column c of X
  * is scaled by S[c][c] / S2[c][c] (0 when S2[c][c] == 0).  S and S2 are M x M

@@ -95,6 +95,7 @@ SIGNATURES = {
     "mfb_apply_H": (C.c_int, [VP, VP, VP, VP, C.c_int, VP]),
     "mfb_apply_H_tuned": (C.c_int, [VP, VP, VP, VP, C.POINTER(Tune), VP, VP]),
     "mfb_tmmult": (C.c_int, [VP, VP, VP, VP, VP, VP, VP]),
+    "mfb_tmmult_noalloc": (C.c_int, [VP, VP, VP, VP, VP, VP]),
     "mfb_mv_update": (C.c_int, [VP, VP, VP, VP, VP, C.c_double, VP]),
     "mfb_create_closure": (C.c_int, [VP, C.POINTER(VP)]),
     "mfb_apply_op": (C.c_int, [VP, VP, VP, C.c_int, VP, VP, C.c_int, VP]),

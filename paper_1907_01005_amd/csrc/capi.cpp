@@ -821,6 +821,24 @@ int mfb_tmmult(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d
   MFB_CATCH
 }
 
+int mfb_tmmult_noalloc(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d_S,
+                       double* d_trace, void* stream) {
+  MFB_TRY
+  if (!mv || !d_X || !d_Y || !d_S || !d_trace) fail(MFB_EINVAL, "null argument");
+  if (mv->work_bytes > mfb::gpu::kScratchBytes)
+    fail(MFB_EINVAL, "the overlap workspace of this layout (" + std::to_string(mv->work_bytes) +
+                         " bytes) exceeds the fixed scratch of " +
+                         std::to_string(mfb::gpu::kScratchBytes) +
+                         " bytes; use mfb_tmmult with a workspace");
+  if (!mv->bound) fail(MFB_ESTATE, "layout metadata not bound");
+  void* w = nullptr;
+  const int rc = mfb::gpu::scratch_address(&w);
+  if (rc != 0) fail(MFB_EHIP, std::string("scratch address: ") + hipGetErrorString((hipError_t)rc));
+  tmmult_enqueue(mv, d_X, d_Y, d_S, d_trace, w, stream);
+  return MFB_OK;
+  MFB_CATCH
+}
+
 int mfb_mv_update(const mfb_mv* mv, double* d_X, const double* d_Y, const double* d_S,
                   const double* d_S2, double tau, void* stream) {
   MFB_TRY

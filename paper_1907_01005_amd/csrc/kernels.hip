@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -2428,7 +2429,35 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateParams p) {
   }
 }
 
+// Workspace of the allocation-free overlap (mfb_tmmult_noalloc): one fixed
+// array per GPU, held until the process ends.  In host code the name is a
+// host-side stand-in, never a device address: the address comes from
+// scratch_address below.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 }  // namespace
+
+// The device address of this GPU's scratch array, looked up once per device
+// with that device current and kept (each GPU has its own copy at its own
+// address).
+int scratch_address(void** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* ptrs[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return (int)e;
+  if (dev < 0 || dev >= kMaxDevices) return (int)hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (ptrs[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    ptrs[dev] = p;
+  }
+  *out = ptrs[dev];
+  return 0;
+}
 
 bool reg_kernel_supported(int degree, int prec, bool curved) {
   return degree <= 2 && (prec == 0 || prec == 3) && !curved;

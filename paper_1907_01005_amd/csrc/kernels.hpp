@@ -84,6 +84,10 @@ struct TmParams {
 int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t nvalues,
                  void* stream);
 int launch_tmmult(const TmParams& p, void* stream);
+// Fixed device scratch of the allocation-free overlap: kScratchBytes per GPU;
+// scratch_address gives this device's address (a hipError_t value on failure).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+int scratch_address(void** out);
 // kernel 8 (register-resident waves): p <= 2, vector-ALU contractions
 // (fp64 or fp32), box cells.
 bool reg_kernel_supported(int degree, int prec, bool curved);
