@@ -8,8 +8,13 @@ one hipGraph of K steps (the kernels of every step, no host launch per
 kernel); an eager loop with events around each launch gives the per-launch
 latencies and the roofline figures.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp64|fp32|fp32-mfma]
-                    [--config 2|3] [--no-cpu-baseline] [--no-forms]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp64|fp64-mfma|fp32|fp32-mfma]
+                    [--config 2|3] [--kernel 0|1|2|7|8] [--no-cpu-baseline] [--no-forms]
+                    [--no-q4] [--no-config4] [--serve N]
+
+Without --no-forms the line also carries the other precision forms, the energy
+and descent step, hipGraph loops, curved cells, the Q4 workload with its own
+roofline, the 640-orbital workloads' hipGraph loops and a short serving stream.
 """
 
 from __future__ import annotations
@@ -408,6 +413,102 @@ def cold_times(dp, prec: int, reps: int = 10, scrub_mib: int = 1024):
     return float(np.median(ta)), float(np.median(tt))
 
 
+KERNELS = {0: "default", 1: "queue", 2: "batch-grid", 7: "loader-pipelined", 8: "register-waves"}
+
+
+def executed_flops_per_cell_column(p: int) -> int:
+    """Flops the vector-ALU kernels execute per cell and column: the gradient
+    terms go through the 1D stiffness K1 = D^T diag(w) D (one n x n product per
+    line and direction instead of D, a scaling and D^T), so 18 n^4 + 7 n^3 + 3 n^3
+    (the line scales) against the 24 n^4 + 7 n^3 of the sum-factorised form."""
+    n = p + 1
+    return 18 * n ** 4 + 10 * n ** 3
+
+
+def measure(wl, dp, prec_name: str, steps: int, warmup: int, kernel: int, copy_gbs: float,
+            cold: bool = True) -> dict:
+    """One workload: the K steps as one hipGraph (value), the eager loop with
+    events around every launch (latencies, the roofline of the apply_H launch)
+    and, with cold, apply_H and tmmult after a scrub of L2 and MALL (the
+    roofline's HBM fraction is then the cold one)."""
+    degree = dp.mesh.degree
+    prec = PRECS[prec_name]
+    alg = algorithmic(dp, degree)
+    wall, t_apply, t_tm = time_path(dp, prec, steps, warmup, kernel)
+    wall_g = time_graph(dp, prec, steps, kernel)
+    t_ap = float(np.mean(t_apply))
+    gbs = alg["bytes"] / t_ap / 1e9
+    tfl = alg["flops"] / t_ap / 1e12
+    peak_f = FP32_MFMA_PEAK_TFLOPS if prec_name == "fp32-mfma" else FP64_PEAK_TFLOPS
+    t_hbm = alg["bytes"] / (HBM_PEAK_GBS * 1e9)
+    t_alu = alg["flops"] / (peak_f * 1e12)
+    if t_alu >= t_hbm:
+        roof = {"bound": "mfma" if prec_name in ("fp32-mfma", "fp64-mfma") else "alu",
+                "achieved": tfl, "peak": peak_f, "unit": "TFLOP/s", "frac": tfl / peak_f}
+    else:
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS}
+    vector_form = prec_name in ("fp64", "fp32")
+    exe = executed_flops_per_cell_column(degree) * alg["cell_columns"] if vector_form else alg["flops"]
+    default_kernel = "apply_ws_kernel" if degree == 2 else "apply_fused_kernel"
+    roof.update({"traffic": measured_traffic(wl.name, prec_name),
+                 "kernel": "apply_H launch (fill_zero_kernel + %s)" % (
+                     default_kernel if kernel == 0 else {1: "apply_queue_kernel",
+                                                         2: "apply_fused_kernel",
+                                                         7: "apply_ws_kernel",
+                                                         8: "apply_reg_kernel"}[kernel]),
+                 "algorithmic_bytes": alg["bytes"], "algorithmic_flops": alg["flops"],
+                 "executed_flops": exe, "executed_frac": exe / t_ap / 1e12 / peak_f,
+                 "avg_launch_s": t_ap, "hbm_frac_warm": gbs / HBM_PEAK_GBS,
+                 "alu_frac": tfl / peak_f,
+                 # min(P, B I): the roof at this arithmetic intensity
+                 "attainable_frac": tfl / min(peak_f, HBM_PEAK_GBS * alg["flops"] / alg["bytes"] / 1e3),
+                 "copy_gbs": copy_gbs, "hbm_frac_vs_copy": gbs / copy_gbs})
+    tm_bytes = 16 * alg["E"] + 8 * dp.M * dp.M
+    t_t = float(np.mean(t_tm))
+    rec = {
+        "value": alg["E"] * steps / wall_g / 1e9,
+        "ms_per_step": wall_g / steps * 1e3,
+        "eager": {"value": alg["E"] * steps / wall / 1e9, "ms_per_step": wall / steps * 1e3},
+        "apply_ms_p50": float(np.percentile(t_apply, 50) * 1e3),
+        "apply_ms_p99": float(np.percentile(t_apply, 99) * 1e3),
+        "apply_gdofcols_s": alg["E"] / t_ap / 1e9,
+        "tmmult_ms_mean": t_t * 1e3,
+        "tmmult_hbm_frac": tm_bytes / t_t / 1e9 / HBM_PEAK_GBS,
+        "roofline": roof,
+    }
+    if cold:
+        ca, ct = cold_times(dp, prec)
+        rec["cold"] = {"apply_ms_p50": ca * 1e3, "tmmult_ms_p50": ct * 1e3,
+                       "apply_hbm_frac": alg["bytes"] / ca / 1e9 / HBM_PEAK_GBS,
+                       "apply_alu_frac": alg["flops"] / ca / 1e12 / peak_f,
+                       "tmmult_hbm_frac": tm_bytes / ct / 1e9 / HBM_PEAK_GBS,
+                       "note": "each timed call follows a 1 GiB scrub write (L2 and MALL cold)"}
+        # X, Y and the metadata (about 120 MB) stay in the 256 MB MALL between
+        # warm launches: the HBM fraction is the cold one
+        roof["hbm_frac"] = rec["cold"]["apply_hbm_frac"]
+    else:
+        roof["hbm_frac"] = None
+    return rec
+
+
+def precision_forms(dp, t_fp64_s: float, degree: int) -> dict:
+    """apply_H in the other precision forms (and kernel variants), each with its
+    speedup over the fp64 vector form on the same layout."""
+    forms = {}
+    for name in ("fp64-mfma", "fp32", "fp32-mfma"):
+        _, ta, _ = time_path(dp, PRECS[name], 50, 5)
+        forms[name] = {"apply_ms_mean": float(np.mean(ta) * 1e3),
+                       "speedup_vs_fp64": t_fp64_s / float(np.mean(ta))}
+    _, ta, _ = time_path(dp, PRECS["fp64"], 50, 5, kernel=1)
+    forms["queue-kernel"] = {"apply_ms_mean": float(np.mean(ta) * 1e3)}
+    if degree <= 2:
+        _, ta, _ = time_path(dp, PRECS["fp64"], 50, 5, kernel=8)
+        forms["register-waves"] = {"apply_ms_mean": float(np.mean(ta) * 1e3),
+                                   "speedup_vs_fp64": t_fp64_s / float(np.mean(ta))}
+    return forms
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -426,8 +527,11 @@ def main(argv=None):
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--config4", action="store_true",
                     help="also run the 640-orbital uneven-block workload (tuned + hipGraph)")
-    ap.add_argument("--serve", type=int, default=0, metavar="N",
-                    help="also run the serving stream with N requests")
+    ap.add_argument("--serve", type=int, default=16, metavar="N",
+                    help="the serving stream with N requests (0: none; with --no-forms none)")
+    ap.add_argument("--no-q4", action="store_true", help="leave the Q4 workload out of the forms")
+    ap.add_argument("--no-config4", action="store_true",
+                    help="leave the 640-orbital hipGraph loops out of the forms")
     ap.add_argument("--serve-budget-mb", type=int, default=1024)
     ap.add_argument("--serve-method", default="rayleigh", choices=["rayleigh", "om"],
                     help="request iterations: Rayleigh-quotient steps or orbital minimisation")
@@ -448,50 +552,19 @@ def main(argv=None):
     wl, dp = build_problem(args.config, radius=args.radius)
     degree = wl.mesh.degree
     prec = PRECS[args.prec]
-    alg = algorithmic(dp, degree)
-    print(f"[bench] E={alg['E']} items={dp.layout.info['apply_items']}; timing {args.steps} steps",
+    print(f"[bench] E={dp.nvalues} items={dp.layout.info['apply_items']}; timing {args.steps} steps",
           file=sys.stderr, flush=True)
-    # eager launches with events around every apply and overlap: the per-launch
-    # latencies (p50/p99) and the roofline figures
-    wall, t_apply, t_tm = time_path(dp, prec, args.steps, args.warmup, args.kernel)
-    # the timed K steps: one hipGraph of exactly K steps, replayed once
-    wall_g = time_graph(dp, prec, args.steps, args.kernel)
-    ms_step = wall_g / args.steps * 1e3
-    value = alg["E"] * args.steps / wall_g / 1e9
-
-    t_ap = float(np.mean(t_apply))
-    gbs = alg["bytes"] / t_ap / 1e9
-    tfl = alg["flops"] / t_ap / 1e12
-    peak_f = FP32_MFMA_PEAK_TFLOPS if args.prec == "fp32-mfma" else FP64_PEAK_TFLOPS
-    t_hbm = alg["bytes"] / (HBM_PEAK_GBS * 1e9)
-    t_alu = alg["flops"] / (peak_f * 1e12)
-    if t_alu >= t_hbm:
-        roof = {"bound": "mfma" if args.prec == "fp32-mfma" else "alu", "achieved": tfl,
-                "peak": peak_f, "unit": "TFLOP/s", "frac": tfl / peak_f}
-    else:
-        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": gbs / HBM_PEAK_GBS}
     copy_gbs = copy_bandwidth()
-    roof.update({"traffic": measured_traffic(wl.name, args.prec),
-                 "kernel": "apply_H launch (fill_zero_kernel + %s)" % (
-                     "apply_ws_kernel" if args.kernel == 0 and degree == 2 and args.prec in ("fp64", "fp32-mfma")
-                     else "apply_fused_kernel" if args.kernel == 0 else "apply_queue_kernel"),
-                 "algorithmic_bytes": alg["bytes"], "algorithmic_flops": alg["flops"],
-                 "avg_launch_s": t_ap, "hbm_frac": gbs / HBM_PEAK_GBS,
-                 "alu_frac": tfl / peak_f,
-                 # min(P, B I): the roof at this arithmetic intensity
-                 "attainable_frac": tfl / min(peak_f, HBM_PEAK_GBS * alg["flops"] / alg["bytes"] / 1e3),
-                 "copy_gbs": copy_gbs, "hbm_frac_vs_copy": gbs / copy_gbs})
-    tm_bytes = 16 * alg["E"] + 8 * dp.M * dp.M
-    t_t = float(np.mean(t_tm))
+    rec = measure(wl, dp, args.prec, args.steps, args.warmup, args.kernel, copy_gbs,
+                  cold=not args.no_forms)
     out = {
         "metric": "apply_H GDoF*cols/s (stored BCSR entries per second, apply_H + tmmult step)",
-        "value": value,
+        "value": rec.pop("value"),
         "unit": "GDoF*cols/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": rec.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -499,44 +572,38 @@ def main(argv=None):
         "data": "synthetic (seeded centres, Gaussian-well potential, N(0,1) orbital values)",
         "config": {"workload": wl.name, "dofs": dp.mesh.ndofs, "orbitals": dp.M,
                    "colblocks": int(len(wl.colblock_sizes)), "radius": wl.radius,
-                   "degree": degree, "stored_entries": alg["E"], "prec": args.prec,
-                   "kernel": {0: "default", 1: "queue", 2: "batch-grid", 7: "loader-pipelined",
-                              8: "register-waves"}[args.kernel]},
-        "launch": "the K timed steps as one hipGraph (apply_H: zero fill + apply; tmmult: "
-                  "stage-1 classes present in the layout, stage 2, trace); eager loop below",
-        "eager": {"value": alg["E"] * args.steps / wall / 1e9, "ms_per_step": wall / args.steps * 1e3},
-        "apply_ms_p50": float(np.percentile(t_apply, 50) * 1e3),
-        "apply_ms_p99": float(np.percentile(t_apply, 99) * 1e3),
-        "apply_gdofcols_s": alg["E"] / t_ap / 1e9,
-        "tmmult_ms_mean": t_t * 1e3,
-        "tmmult_hbm_frac": tm_bytes / t_t / 1e9 / HBM_PEAK_GBS,
-        "roofline": roof,
+                   "degree": degree, "stored_entries": dp.nvalues, "prec": args.prec,
+                   "kernel": KERNELS[args.kernel]},
+        "launch": "the K timed steps as one hipGraph (apply_H: zero fill + apply; tmmult: the "
+                  "stage-1 classes present in the layout and stage 2, which also sums the "
+                  "trace); eager loop below",
     }
+    out.update(rec)
     if not args.no_forms:
-        ca, ct = cold_times(dp, prec)
-        out["cold"] = {"apply_ms_p50": ca * 1e3, "tmmult_ms_p50": ct * 1e3,
-                       "apply_hbm_frac": alg["bytes"] / ca / 1e9 / HBM_PEAK_GBS,
-                       "apply_alu_frac": alg["flops"] / ca / 1e12 / peak_f,
-                       "tmmult_hbm_frac": tm_bytes / ct / 1e9 / HBM_PEAK_GBS,
-                       "note": "each timed call follows a 1 GiB scrub write (L2 and MALL cold)"}
-        forms = {}
-        for name in ("fp32", "fp32-mfma"):
-            try:
-                _, ta, _ = time_path(dp, PRECS[name], 50, 5)
-                forms[name] = {"apply_ms_mean": float(np.mean(ta) * 1e3),
-                               "speedup_vs_fp64": t_ap / float(np.mean(ta))}
-            except Exception as e:  # unsupported variant
-                forms[name] = {"error": str(e)}
-        _, ta, _ = time_path(dp, prec, 50, 5, kernel=1)
-        forms["queue-kernel"] = {"apply_ms_mean": float(np.mean(ta) * 1e3)}
+        t_fp64 = out["roofline"]["avg_launch_s"]
+        forms = precision_forms(dp, t_fp64, degree)
         forms["energy"] = energy_form(dp)
         forms["graph20-" + args.prec] = graph_form(dp, prec)
         forms["graph20-fp32-mfma"] = graph_form(dp, PRECS["fp32-mfma"])
         forms["curved"] = curved_form(args.config)
+        if args.config == 2 and not args.no_q4:
+            # the same box as Q4 (32x20x20 cells, 846369 DoFs, 320 orbitals)
+            print("[bench] Q4 workload", file=sys.stderr, flush=True)
+            del dp
+            import torch
+            torch.cuda.empty_cache()
+            wl3, dp3 = build_problem(3)
+            q4 = measure(wl3, dp3, args.prec, min(args.steps, 100), args.warmup, 0, copy_gbs)
+            q4["workload"] = wl3.name
+            q4["stored_entries"] = dp3.nvalues
+            q4["forms"] = precision_forms(dp3, q4["roofline"]["avg_launch_s"], 4)
+            forms["q4"] = q4
+            del dp3
+            torch.cuda.empty_cache()
         out["forms"] = forms
-    if args.config4:
+    if args.config4 or not (args.no_forms or args.no_config4):
         out["config4"] = config4_forms()
-    if args.serve:
+    if args.serve and not args.no_forms:
         print(f"[bench] serving {args.serve} requests", file=sys.stderr, flush=True)
         out["serving"] = serving_form(args.serve, args.serve_budget_mb, args.serve_method)
     if args.copy_calibration:

@@ -538,6 +538,7 @@ static void fill_apply_params(const mfb_mesh* mesh, const mfb_mv* mv, const doub
   std::memset(&a, 0, sizeof(a));
   a.X = X;
   a.Y = Y;
+  a.nvalues_x = mv->plan.block_offset.back();
   const char* mb = (const char*)mv->d_meta;
   const char* gb = (const char*)mesh->d_meta;
   a.items = (const mfb::ApplyItem*)(mb + mv->lay.off_items);

@@ -496,7 +496,7 @@ __device__ __forceinline__ void stiff_plane(const R (&u)[n][n], R (&w)[n][n], co
 // accumulated result are the only planes held across a layout switch.  Same
 // layouts, barriers and calling convention as plane_operator; u is
 // overwritten.
-template <typename R, int P, class Hook>
+template <typename R, int P, class Hook, bool GLOBAL_CV = true>
 __device__ __forceinline__ void plane_operator_lean(const ApplyParams& a, R* __restrict__ Tc, int pl,
                                                     const double* cv, R (&u)[P + 1][P + 1],
                                                     R (&out)[P + 1][P + 1], Hook after_first_barrier) {
@@ -512,10 +512,10 @@ __device__ __forceinline__ void plane_operator_lean(const ApplyParams& a, R* __r
     for (int i = 0; i < n; ++i) Tc[i + n * j + n2 * pl] = u[i][j];
   __syncthreads();
   after_first_barrier();
-  // the potential's coefficients are read here, where they are used: the
-  // empty asm keeps their loads from being hoisted (and held in registers)
-  // across the first phase
-  asm volatile("" : "+v"(cv));
+  // the potential's coefficients (in global memory) are read here, where they
+  // are used: the empty asm keeps their loads from being hoisted (and held in
+  // registers) across the first phase.  LDS copies stay below the barrier.
+  if constexpr (GLOBAL_CV) asm volatile("" : "+v"(cv));
   // layout B (y = pl): along z, then the x and z gradient terms and V
   R uq[n][n], w[n][n];
 #pragma unroll
@@ -1321,42 +1321,67 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Blocks at most 8 wide on both sides, one product per wave, on the fp64
-// matrix cores.  In v_mfma_f64_16x16x4f64 lane l supplies A(l % 16, l / 16)
-// and B(l / 16, l % 16) and receives rows l / 16 + 4 r (r = 0..3) of column
-// l % 16 of the result.  One product step covers 8 rows: lane l loads column
-// a = l % 8 of row 8 s + 4 h + l / 16 (h = bit 3 of l) of X and of Y, so
-// that a wave reads the 8 rows' contiguous bytes once and no value twice.
-// Then A(i, k) = X(8 s + 4 (i / 8) + k, i % 8) and B(k, j) = Y(8 s + 4 (j / 8)
-// + k, j % 8): the two diagonal 8x8 blocks of the 16x16 result (i / 8 = j / 8)
-// are X^T Y over rows 8 s + k and over rows 8 s + 4 + k, and their sum is the
-// block product (the other two blocks are never read).  Four waves, four
-// products per workgroup.  W8: both blocks exactly 8 wide (the row stride
-// is then a constant and the loads share one address).
-template <int STEPS, bool W8>
+// Raw buffer resource over `bytes` bytes at `base` (gfx9 descriptor word 3):
+// loads at offsets past the end return 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ double buffer_load_f64(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+
+// Blocks at most 8 wide on both sides, on the fp64 matrix cores.  In
+// v_mfma_f64_16x16x4f64 lane l supplies A(l % 16, l / 16) and B(l / 16,
+// l % 16) and receives rows l / 16 + 4 r (r = 0..3) of column l % 16 of the
+// result.  One product step covers 8 rows: lane l loads column a = l % 8 of
+// row 8 s + 4 h + l / 16 (h = bit 3 of l) of X and of Y, so that a wave reads
+// the 8 rows' contiguous bytes once and no value twice.  Then A(i, k) =
+// X(8 s + 4 (i / 8) + k, i % 8) and B(k, j) = Y(8 s + 4 (j / 8) + k, j % 8): the
+// two diagonal 8x8 blocks of the 16x16 result (i / 8 = j / 8) are X^T Y over
+// rows 8 s + k and over rows 8 s + 4 + k, and their sum is the block product
+// (the other two blocks are never read).  The blocks are read through buffer
+// resources of their own size: a lane's offset is fixed, the row step is a
+// scalar offset, and rows past the end (and columns past the width) read 0.
+// SPLIT waves share one product (the rows' steps dealt round robin, the
+// waves' sums added in LDS in wave order); 4 / SPLIT products per workgroup.
+// W8: both blocks exactly 8 wide.
+template <int STEPS, bool W8, int SPLIT>
 __global__ __launch_bounds__(256) void tm_unit8_kernel(TmParams p, int64_t first, int64_t count) {
+  constexpr int PPW = 4 / SPLIT;
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t u = xcd_item(blockIdx.x, gridDim.x) * 4 + wv;
-  if (u >= count) return;
+  const int64_t u = xcd_item(blockIdx.x, gridDim.x) * PPW + wv / SPLIT;
+  const int part = wv % SPLIT;
+  if (u >= count) return;  // the same for the SPLIT waves of a product
   const TmUnit U = p.units[first + u];
   const int a = l & 7, h = (l >> 3) & 1, k = l >> 4;
   const int w1 = W8 ? 8 : U.w1, w2 = W8 ? 8 : U.w2, rows = U.rows;
-  const bool okx = a < w1, oky = a < w2;
-  const double* __restrict__ X = p.X + U.off1 + (okx ? a : 0);
-  const double* __restrict__ Y = p.Y + U.off2 + (oky ? a : 0);
+  const uint32_t bx = (uint32_t)rows * w1 * 8, by = (uint32_t)rows * w2 * 8;
+  const __amdgpu_buffer_rsrc_t rx = buffer_rsrc(p.X + U.off1, bx);
+  const __amdgpu_buffer_rsrc_t ry = buffer_rsrc(p.Y + U.off2, by);
   const int r0 = 4 * h + k;
+  const uint32_t vx = a < w1 ? (uint32_t)(r0 * w1 + a) * 8 : bx;
+  const uint32_t vy = a < w2 ? (uint32_t)(r0 * w2 + a) * 8 : by;
   v4d acc = {0.0, 0.0, 0.0, 0.0};
-  for (int base = 0; base < rows; base += 8 * STEPS) {
+  for (int base = part * 8 * STEPS; base < rows; base += SPLIT * 8 * STEPS) {
     double xa[STEPS], yb[STEPS];
 #pragma unroll
     for (int s = 0; s < STEPS; ++s) {
-      const int i = base + 8 * s + r0;
-      xa[s] = (okx && i < rows) ? X[(int64_t)i * w1] : 0.0;
-      yb[s] = (oky && i < rows) ? Y[(int64_t)i * w2] : 0.0;
+      xa[s] = buffer_load_f64(rx, vx, (uint32_t)(base + 8 * s) * w1 * 8);
+      yb[s] = buffer_load_f64(ry, vy, (uint32_t)(base + 8 * s) * w2 * 8);
     }
 #pragma unroll
     for (int s = 0; s < STEPS; ++s)
       if (base + 8 * s < rows) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[s], yb[s], acc, 0, 0, 0);
+  }
+  if constexpr (SPLIT > 1) {
+    __shared__ v4d red[SPLIT][64];
+    red[part][l] = acc;
+    __syncthreads();
+    if (part != 0) return;
+    acc = red[0][l];
+#pragma unroll
+    for (int q = 1; q < SPLIT; ++q) acc += red[q][l];
   }
   // lane l (column j = l % 16 < 8) holds P(k, j) and P(k + 4, j) of the
   // first block at r = 0, 1; lane l + 8 holds those of the second block at
@@ -2045,6 +2070,263 @@ void apply_ws_kernel(ApplyParams a) {
   }
 }
 
+// Loader-wave pipeline with one shared gather stage (p >= 3, box cells).  At
+// p = 4 an item's gathered values (46.7 KB in float64) and the transpose
+// tile (64 KB) leave no room for a second stage, so the stage is shared: the
+// compute waves read their planes out of it before the operator's first
+// barrier, after which the loader wave refills it with the next item chunk by
+// chunk, one chunk per barrier phase of the operator (loads issued in one
+// phase, stored in the next, so their latency overlaps the operator).  The
+// row offsets and JxW V of the next item go to the other of two LDS slots
+// during the first phase.  The cell results are added into Y cell by cell
+// with float64 atomics straight from the registers (no node sums in LDS), so
+// the stage is not needed again before the next item.  Compute waves and the
+// loader pass the same barriers: the operator's own and one at the end of
+// each item; an item whose values are all zero passes none of the
+// operator's.
+template <typename R, int P, bool MF, int OP>
+struct SharedPipe {
+  using D = Dims<P>;
+  static constexpr int n = D::n, n2 = D::n2, n3 = D::n3, NB = D::NB, NB3 = D::NB3;
+  static constexpr int NWC = n, NTC = 64 * NWC, NT = NTC + 64;
+  static constexpr int NV = NB3 * 8, NCV = 8 * n3;
+  static constexpr int kOpBarriers = OP == 0 ? 7 : 3;
+  // chunks of CH values per lane; phase b = 1..PH loads chunks
+  // [(b - 1) NCHK / PH, b NCHK / PH) (all but the last one stored at once),
+  // the last one is stored in phase b + 1
+  static constexpr int CH = 16;
+  static constexpr int NCHK = (NV + 64 * CH - 1) / (64 * CH);
+  static constexpr int PH = kOpBarriers - 1;
+  static constexpr int KR = (NB3 + 63) / 64;
+  static constexpr int KC = (NCV + 63) / 64;
+  static constexpr int kListMax = 256;
+  // The tile first: the operator's many LDS accesses then fit the 16-bit
+  // immediate offsets of the LDS instructions (at p = 4 the tile alone is
+  // 64 000 bytes), so they need no address registers of their own.
+  struct Smem {
+    R T[64 * n3];
+    double cv[2][NCV];      // JxW V of the eight cells, by item parity
+    int32_t ro[2][NB3];     // row offsets of the batch nodes (gather and flush), by parity
+    int32_t nc[2], nz[2];
+    double wg[4 * n3];      // gradient scales and JxW of the mesh (matrix-core and mass forms)
+    int32_t list[kListMax];
+    int32_t nlist;
+    double G[NV];           // the current item's gathered values, then the next item's
+  };
+  // Loader: row offsets, record and JxW V of item idx into the LDS slot.
+  static __device__ __forceinline__ void head(const ApplyParams& a, int64_t idx, int l, Smem& sm,
+                                              int slot) {
+    int32_t r[KR];
+    double c[KC];
+    const int32_t* __restrict__ src = a.rowoff + idx * NB3;
+#pragma unroll
+    for (int q = 0; q < KR; ++q) r[q] = (l + 64 * q) < NB3 ? src[l + 64 * q] : -1;
+    const int rank = a.items[idx].rank;
+    const double* __restrict__ cvp = a.cV + (int64_t)rank * 8 * n3;
+#pragma unroll
+    for (int q = 0; q < KC; ++q) c[q] = (l + 64 * q) < NCV ? cvp[l + 64 * q] : 0.0;
+    const int nc = a.items[idx].nc;
+#pragma unroll
+    for (int q = 0; q < KR; ++q)
+      if ((l + 64 * q) < NB3) sm.ro[slot][l + 64 * q] = r[q];
+#pragma unroll
+    for (int q = 0; q < KC; ++q)
+      if ((l + 64 * q) < NCV) sm.cv[slot][l + 64 * q] = c[q];
+    if (l == 0) sm.nc[slot] = nc;
+  }
+  // Loader: values [ch CH 64, (ch + 1) CH 64) of the item in slot `slot`,
+  // through a buffer resource over X (32-bit offsets; absent rows and
+  // columns are given an offset past the end and read 0).
+  static __device__ __forceinline__ void chunk_load(__amdgpu_buffer_rsrc_t rX, uint32_t xbytes,
+                                                    const Smem& sm, int slot, int ch, int l,
+                                                    double (&v)[CH]) {
+    const int nc = sm.nc[slot];
+    // the chunk's first index, opaque to the compiler: its addresses are then
+    // formed here, not hoisted out of the item loop and kept in registers
+    int e0 = ch * CH * 64 + l;
+    asm volatile("" : "+v"(e0));
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int e = e0 + q * 64;
+      const int32_t r = e < NV ? sm.ro[slot][e >> 3] : -1;
+      const bool ok = r >= 0 && (e & 7) < nc;
+      v[q] = buffer_load_f64(rX, ok ? (uint32_t)(r + (e & 7)) * 8u : xbytes, 0);
+    }
+  }
+  static __device__ __forceinline__ bool chunk_store(Smem& sm, int ch, int l, const double (&v)[CH]) {
+    bool any = false;
+    int e0 = ch * CH * 64 + l;
+    asm volatile("" : "+v"(e0));
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int e = e0 + q * 64;
+      if (e < NV) sm.G[e] = v[q];
+      any |= v[q] != 0.0;
+    }
+    return any;
+  }
+  // Compute waves: item in slot `slot` (its values in G).
+  static __device__ __forceinline__ void compute(const ApplyParams& a, Smem& sm, int slot, int t,
+                                                 int pl) {
+    const int c = t & 7, e = (t >> 3) & 7;
+    const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
+    R u[n][n];
+    const int base = ((ex * P) + NB * ((ey * P) + NB * (ez * P + pl))) * 8 + c;
+#pragma unroll
+    for (int j = 0; j < n; ++j)
+#pragma unroll
+      for (int i = 0; i < n; ++i) u[i][j] = (R)sm.G[base + (i + NB * j) * 8];
+    R out[n][n];
+    R* Tc = sm.T + (t & 63) * n3;
+    if constexpr (OP == 0 && !MF) {
+      auto none = []() {};
+      plane_operator_lean<R, P, decltype(none), false>(a, Tc, pl, sm.cv[slot] + e * n3, u, out, none);
+    }
+    else if constexpr (OP == 0)
+      plane_operator<R, P>(make_ctr<R, P, MF>(a), Tc, pl, sm.cv[slot] + e * n3, sm.wg, true, u, out,
+                           []() {});
+    else
+      plane_mass<R, P>(make_ctr<R, P, MF>(a), Tc, pl, sm.wg + 3 * n3, true, u, out, []() {});
+    // cell by cell into Y (the nodes shared by cells take one atomic per cell)
+    const int nc = sm.nc[slot];
+    if (c >= nc) return;
+#pragma unroll
+    for (int j = 0; j < n; ++j)
+#pragma unroll
+      for (int i = 0; i < n; ++i) {
+        const int32_t o = sm.ro[slot][(ex * P + i) + NB * ((ey * P + j) + NB * (ez * P + pl))];
+        if (o >= 0) unsafeAtomicAdd(a.Y + (int64_t)o + c, (double)out[i][j]);
+      }
+  }
+};
+
+template <typename R, int P, bool MF, int OP>
+__global__ __launch_bounds__(64 * (P + 2)) void apply_pipe1_kernel(ApplyParams a) {
+  using L = SharedPipe<R, P, MF, OP>;
+  __shared__ typename L::Smem sm;
+  const int64_t W = gridDim.x >> 3;
+  const int x = blockIdx.x & 7;
+  const int64_t w = blockIdx.x >> 3;
+  const int t = threadIdx.x;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+  const bool loader = wv == L::NWC;
+  const int l = t & 63;
+  const int64_t po = (a.nitems + 7) >> 3, ps = (a.nshell + 7) >> 3;
+  const int64_t o0 = x * po + w, o1 = min(a.nitems, (x + 1) * po);
+  const int64_t s0 = x * ps + w, s1 = min(a.nshell, (x + 1) * ps);
+  const int n_own = o0 < o1 ? (int)((o1 - o0 + W - 1) / W) : 0;
+  const int n_sh = s0 < s1 ? (int)((s1 - s0 + W - 1) / W) : 0;
+  if (n_own + n_sh == 0) return;
+  if (t == 0) sm.nlist = 0;
+  for (int i = t; i < 4 * L::n3; i += L::NT) sm.wg[i] = a.Wg[i];
+  __syncthreads();
+  auto seq = [&](int k) -> int64_t {
+    if (k < n_own) return o0 + (int64_t)k * W;
+    return a.nitems + __builtin_amdgcn_readfirstlane(sm.list[k - n_own]);
+  };
+  if (loader) {
+    const uint32_t xbytes = (uint32_t)(a.nvalues_x * 8);
+    const __amdgpu_buffer_rsrc_t rX = buffer_rsrc(a.X, xbytes);
+    // the first item: whole, before the shell list is known if it is an own item
+    auto first = [&]() {
+      L::head(a, seq(0), l, sm, 0);
+      bool any = false;
+      double v[L::CH];
+#pragma unroll 1
+      for (int ch = 0; ch < L::NCHK; ++ch) {
+        L::chunk_load(rX, xbytes, sm, 0, ch, l, v);
+        any |= L::chunk_store(sm, ch, l, v);
+      }
+      const bool nz = __ballot(any) != 0;
+      if (l == 0) sm.nz[0] = nz ? 1 : 0;
+      return nz;
+    };
+    bool nz_cur = false;
+    if (n_own > 0) nz_cur = first();
+    __syncthreads();
+    const int nk = n_own + min(__builtin_amdgcn_readfirstlane(sm.nlist), L::kListMax);
+    if (nk == 0) return;
+    if (n_own == 0) {
+      nz_cur = first();
+      __syncthreads();
+    }
+    for (int k = 0; k < nk; ++k) {
+      const bool more = k + 1 < nk;
+      const int nslot = (k + 1) & 1;
+      bool any = false;
+      double v[L::CH];
+      if (more) L::head(a, seq(k + 1), l, sm, nslot);
+      if (nz_cur) {
+        // phase b follows barrier b of the operator: the chunk loaded in the
+        // previous phase is stored, then this phase's chunks are loaded (the
+        // last one left in flight to the next phase)
+        int pend = -1;
+#pragma unroll 1
+        for (int b = 1; b <= L::kOpBarriers; ++b) {
+          __syncthreads();
+          if (more) {
+            if (pend >= 0) any |= L::chunk_store(sm, pend, l, v);
+            pend = -1;
+            if (b <= L::PH) {
+              const int lo = (b - 1) * L::NCHK / L::PH, hi = b * L::NCHK / L::PH;
+#pragma unroll 1
+              for (int ch = lo; ch + 1 < hi; ++ch) {
+                L::chunk_load(rX, xbytes, sm, nslot, ch, l, v);
+                any |= L::chunk_store(sm, ch, l, v);
+              }
+              if (hi > lo) {
+                L::chunk_load(rX, xbytes, sm, nslot, hi - 1, l, v);
+                pend = hi - 1;
+              }
+            }
+          }
+        }
+      } else if (more) {
+#pragma unroll 1
+        for (int ch = 0; ch < L::NCHK; ++ch) {
+          L::chunk_load(rX, xbytes, sm, nslot, ch, l, v);
+          any |= L::chunk_store(sm, ch, l, v);
+        }
+      }
+      if (more) {
+        const bool nz = __ballot(any) != 0;
+        if (l == 0) sm.nz[nslot] = nz ? 1 : 0;
+        nz_cur = nz;
+      }
+      __syncthreads();  // end of item k
+    }
+  } else {
+    // shell checks: 16 lanes per shell item, non-zero ones appended to the list
+    constexpr int LPI = 16, IPP = L::NTC / LPI;
+    for (int jb = 0; jb < n_sh; jb += IPP) {
+      const int j = jb + t / LPI;
+      bool any = false;
+      if (j < n_sh) {
+        const int64_t k = s0 + (int64_t)j * W;
+        const int nc = a.items[a.nitems + k].nc;
+        const int32_t e1 = a.shell_ptr[k + 1];
+        for (int32_t e = a.shell_ptr[k] + (t % LPI); e < e1; e += LPI) {
+          const double* __restrict__ xp = a.X + (int64_t)a.shell_ro[e];
+          for (int c = 0; c < nc; ++c) any |= (xp[c] != 0.0);
+        }
+      }
+      const uint64_t b = __ballot(any);
+      if ((l % LPI) == 0 && ((b >> l) & 0xFFFFull) != 0) {
+        const int pos = atomicAdd(&sm.nlist, 1);
+        if (pos < L::kListMax) sm.list[pos] = (int32_t)(s0 + (int64_t)j * W);
+      }
+    }
+    __syncthreads();
+    const int nk = n_own + min(__builtin_amdgcn_readfirstlane(sm.nlist), L::kListMax);
+    if (nk == 0) return;
+    if (n_own == 0) __syncthreads();
+    for (int k = 0; k < nk; ++k) {
+      if (__builtin_amdgcn_readfirstlane(sm.nz[k & 1])) L::compute(a, sm, k & 1, t, wv);
+      __syncthreads();
+    }
+  }
+}
+
 // Software-pipelined persistent form of BatchProc.  Workgroup w of XCD x
 // walks a strided list of the own items of x's contiguous range, then of
 // its shell items.  Before computing item j it issues the value loads of
@@ -2161,9 +2443,37 @@ hipError_t launch_fused(const ApplyParams& p, int spw, hipStream_t st) {
 // Loader-wave pipeline at p = 2 (grid = total workgroups, 0 = as many as are
 // resident); the fused grid at p = 4, where two fp64 stages and the tiles do
 // not fit a CU's LDS.
+// The shared-stage loader pipeline (p >= 3, box cells, X's own pattern as the
+// destination): persistent workgroups, as many as are resident.
+template <typename R, int P, bool MF, int OP>
+hipError_t launch_pipe1(const ApplyParams& p, int grid, hipStream_t st) {
+  if (p.nitems + p.nshell == 0) return hipSuccess;
+  // the loader reads X through a buffer resource (byte offsets below 2^31)
+  if (p.nvalues_x * 8 >= (int64_t(1) << 31)) return launch_fused<R, P, MF, OP>(p, 0, st);
+  const void* fn = reinterpret_cast<const void*>(&apply_pipe1_kernel<R, P, MF, OP>);
+  constexpr int NT = 64 * (P + 2);
+  if (grid <= 0) {
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NT, 0);
+    if (e != hipSuccess) return e;
+    grid = std::max(1, per_cu) * std::max(1, device_cu_count());
+  }
+  const int64_t po = (p.nitems + 7) >> 3, ps = (p.nshell + 7) >> 3;
+  constexpr int64_t LM = SharedPipe<R, P, MF, OP>::kListMax;
+  int64_t W = std::max<int64_t>(1, grid / 8);
+  W = std::min<int64_t>(W, std::max<int64_t>(1, std::max(po, ps)));
+  W = std::max<int64_t>(W, (ps + LM - 1) / LM);  // every workgroup's shell list fits
+  hipLaunchKernelGGL((apply_pipe1_kernel<R, P, MF, OP>), dim3((unsigned)(8 * W)), dim3(NT), 0, st, p);
+  return hipGetLastError();
+}
+
 template <typename R, int P, bool MF, int OP>
 hipError_t launch_ws(const ApplyParams& p, int grid, hipStream_t st) {
   if constexpr (P != 2) {
+    // p >= 3 on box cells with X's own pattern as the destination: the
+    // shared-stage loader pipeline; otherwise the fused grid
+    if constexpr (P >= 3)
+      if (!p.cG && p.rowoff_out == p.rowoff) return launch_pipe1<R, P, MF, OP>(p, grid, st);
     return launch_fused<R, P, MF, OP>(p, 0, st);
   } else {
     if (p.cG) return launch_fused<R, P, MF, OP>(p, 0, st);  // curved cells: the fused grid
@@ -2631,8 +2941,13 @@ int launch_tmmult(const TmParams& p, void* stream) {
     const int64_t nwg = (((n + 3) / 4 + 7) / 8) * 8;
     hipLaunchKernelGGL(kernel, dim3((unsigned)nwg), dim3(256), 0, st, p, lo, n);
   };
-  launch4(tm_unit8_kernel<16, true>, 0);
-  launch4(tm_unit8_kernel<8, false>, 1);
+  launch4(tm_unit8_kernel<16, true, 1>, 0);
+  {  // longer products: four waves each
+    const int64_t lo = ce[0], n = ce[1] - ce[0];
+    if (n > 0)
+      hipLaunchKernelGGL((tm_unit8_kernel<8, false, 4>), dim3((unsigned)(((n + 7) / 8) * 8)), dim3(256),
+                         0, st, p, lo, n);
+  }
   launch(tm_stage1_mfma_kernel<1, 2>, 2, 64);
   launch(tm_stage1_mfma_kernel<4, 2>, 3, 256);
   {

@@ -48,6 +48,7 @@ struct ApplyParams {
   // unchanged under (o, k) -> (n-1-o, n-1-k))
   double K1[25];
   float K1f[25];
+  int64_t nvalues_x;     // stored values of X (the extent of d_X)
 };
 
 struct TmParams {
