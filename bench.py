@@ -280,9 +280,9 @@ def attach_inputs(reqs, threads: int = 8):
     return reqs
 
 
-def serving_form(n: int, budget_mb: int, method: str = "rayleigh"):
+def serving_form(n: int, budget_mb: int, method: str = "rayleigh", rate: float = 40.0):
     from paper_1907_01005_amd.serving import GpuExecutor, Server, request_stream, summarize
-    reqs = request_stream(n=n, method=method)
+    reqs = request_stream(n=n, rate=rate, method=method)
     t0 = time.perf_counter()
     attach_inputs(reqs)
     t_inputs = time.perf_counter() - t0
@@ -292,12 +292,55 @@ def serving_form(n: int, budget_mb: int, method: str = "rayleigh"):
             print(f"[bench] serving: {k}/{total} requests done", file=sys.stderr, flush=True)
     rep = Server(ex, byte_budget=budget_mb << 20, max_slots=8).run(reqs, progress=progress)
     s = summarize(rep)
-    s.update({"requests": n, "rate_per_s": 40.0, "byte_budget_mb": budget_mb, "method": method,
+    s.update({"requests": n, "rate_per_s": rate, "byte_budget_mb": budget_mb, "method": method,
               "client_inputs_s": t_inputs})
     if method == "om":
         done = [r for r in rep.results.values() if "energies" in r]
         s["om_energy_decreased"] = sum(1 for r in done if r["energies"][-1] < r["energies"][0])
     return s
+
+
+def trace_overlap(path: str, prefix: str = "mfb::") -> dict:
+    """Device-side overlap of the library's kernels across streams, from a
+    rocprofv3 kernel trace (csv): the busy time (union of the kernels'
+    intervals), the sum of their durations, the time during which kernels on
+    two or more streams run at once, and the most streams active together."""
+    import csv
+    spans = []
+    for r in csv.DictReader(open(path)):
+        name = r["Kernel_Name"]
+        if prefix not in name:
+            continue
+        spans.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Stream_Id"]))
+    if not spans:
+        return {"kernels": 0}
+    ev = sorted([(a, 1, s) for a, b, s in spans] + [(b, -1, s) for a, b, s in spans])
+    active: dict = {}
+    union = multi = 0
+    most = 0
+    last = None
+    for t, d, sid in ev:
+        if last is not None and active:
+            union += t - last
+            if len(active) >= 2:
+                multi += t - last
+        active[sid] = active.get(sid, 0) + d
+        if active[sid] == 0:
+            del active[sid]
+        most = max(most, len(active))
+        last = t
+    total = sum(b - a for a, b, _ in spans)
+    per_stream = {}
+    for a, b, sid in spans:
+        per_stream[sid] = per_stream.get(sid, 0) + (b - a)
+    return {"kernels": len(spans), "streams": len(per_stream),
+            "window_ms": (max(b for _, b, _ in spans) - min(a for a, _, _ in spans)) * 1e-6,
+            "busy_union_ms": union * 1e-6, "kernel_sum_ms": total * 1e-6,
+            "concurrent_ms": multi * 1e-6,
+            "concurrent_frac_of_busy": multi / union if union else 0.0,
+            "sum_over_union": total / union if union else 0.0,
+            "most_streams_at_once": most,
+            "per_stream_ms": {k: v * 1e-6 for k, v in sorted(per_stream.items())}}
 
 
 def time_path(dp, prec: int, steps: int, warmup: int, kernel: int = 0):
@@ -532,6 +575,13 @@ def main(argv=None):
     ap.add_argument("--no-q4", action="store_true", help="leave the Q4 workload out of the forms")
     ap.add_argument("--no-config4", action="store_true",
                     help="leave the 640-orbital hipGraph loops out of the forms")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving stream (--serve N requests) and print its summary")
+    ap.add_argument("--trace-overlap", metavar="CSV",
+                    help="summarise the cross-stream overlap of the library's kernels in a "
+                         "rocprofv3 kernel trace (no GPU needed) and exit")
+    ap.add_argument("--serve-rate", type=float, default=40.0,
+                    help="mean arrival rate of the serving stream (requests per second)")
     ap.add_argument("--serve-budget-mb", type=int, default=1024)
     ap.add_argument("--serve-method", default="rayleigh", choices=["rayleigh", "om"],
                     help="request iterations: Rayleigh-quotient steps or orbital minimisation")
@@ -539,6 +589,9 @@ def main(argv=None):
                     help="also run one device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args(argv)
 
+    if args.trace_overlap:
+        print(json.dumps(trace_overlap(args.trace_overlap)), flush=True)
+        return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the path is not sharded across GPUs "
               "(run with --gpus 1)", file=sys.stderr)
@@ -548,6 +601,12 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
+    if args.serve_only:
+        n = args.serve or 16
+        print(f"[bench] serving {n} requests", file=sys.stderr, flush=True)
+        print(json.dumps({"serving": serving_form(n, args.serve_budget_mb, args.serve_method,
+                                                  args.serve_rate)}), flush=True)
+        return 0
     print(f"[bench] building config {args.config}", file=sys.stderr, flush=True)
     wl, dp = build_problem(args.config, radius=args.radius)
     degree = wl.mesh.degree
@@ -605,7 +664,8 @@ def main(argv=None):
         out["config4"] = config4_forms()
     if args.serve and not args.no_forms:
         print(f"[bench] serving {args.serve} requests", file=sys.stderr, flush=True)
-        out["serving"] = serving_form(args.serve, args.serve_budget_mb, args.serve_method)
+        out["serving"] = serving_form(args.serve, args.serve_budget_mb, args.serve_method,
+                                      args.serve_rate)
     if args.copy_calibration:
         src = torch.ones(args.copy_calibration << 17, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)

@@ -793,7 +793,6 @@ static void tmmult_enqueue(const mfb_mv* mv, const double* d_X, const double* d_
   t.tdiag = t.part + p.part_doubles;
   t.ndiag = p.ndiag;
   t.fold_trace = p.tasks.empty() ? 1 : 0;
-  t.nstored_pairs = (int32_t)(p.pair_ptr.size() - 1);
   t.pair_tab = (const int32_t*)(mb + mv->lay.off_pair_tab);
   t.pair_ptr = (const int32_t*)(mb + mv->lay.off_pair_ptr);
   t.pair_list = (const int64_t*)(mb + mv->lay.off_pair_list);

@@ -1616,10 +1616,9 @@ __global__ __launch_bounds__(64 * NW) void tm_task_kernel(TmParams p, int64_t fi
   dispatch_count<0, kNT>(nt, main_loop);
 }
 
-// Stage 2: one workgroup per stored block of S sums its pair's partial
-// products in a fixed order (NT / E thread groups, up to 32 loads in flight
-// per thread, then LDS); the workgroups also write the zeros of the blocks
-// outside the pattern, a few each.  With fold_trace the
+// Stage 2: one workgroup per block of S sums its pair's partial products in
+// a fixed order (NT / E thread groups, up to 32 loads in flight per thread,
+// then LDS); blocks outside the pattern write zeros.  With fold_trace the
 // first workgroup instead sums the diagonal products' traces (tdiag, in
 // order) into tr S, so that the trace needs no launch of its own.
 template <int NT>
@@ -1651,18 +1650,12 @@ __global__ __launch_bounds__(NT) void tm_stage2_kernel(TmParams p) {
     }
     --blk;
   }
-  // the blocks outside the product pattern (after the stored ones in the
-  // descriptor order) are written as zeros, dealt round robin over the
-  // workgroups of the stored blocks
-  const int64_t nblk = (int64_t)p.ncb * p.ncb, nst = p.nstored_pairs;
-  for (int64_t z = nst + blk; z < nblk; z += (nst > 0 ? nst : 1)) {
-    const S2Desc dz = p.s2[z];
-    const int Ez = dz.w1 * dz.w2;
-    for (int e = t; e < Ez; e += NT) p.S[(int64_t)(dz.c1 + e / dz.w2) * p.M + (dz.c2 + e % dz.w2)] = 0.0;
-  }
-  if (blk >= nst) return;
   const S2Desc d = p.s2[blk];
   const int E = d.w1 * d.w2;
+  if (d.n == 0) {  // block outside the product pattern
+    for (int e = t; e < E; e += NT) p.S[(int64_t)(d.c1 + e / d.w2) * p.M + (d.c2 + e % d.w2)] = 0.0;
+    return;
+  }
   const int G = NT / E;
   const int g = t / E, e = t - g * E;
   double sum = 0.0;
@@ -1951,7 +1944,11 @@ struct LoaderPipe {
     };
     R out[n][n];
     if constexpr (OP == 0 && !MF)
-      plane_operator_lean<R, P>(a, T + (t & 63) * n3, pl, cur.cv + e * n3, u, out, zero_sums);
+      // JxW V sits in the LDS stage: read as LDS (the operator's opaque
+      // pointer form would turn the reads into flat loads that wait for the
+      // previous item's atomics)
+      plane_operator_lean<R, P, decltype(zero_sums), false>(a, T + (t & 63) * n3, pl, cur.cv + e * n3,
+                                                            u, out, zero_sums);
     else if constexpr (OP == 0)
       plane_operator<R, P>(make_ctr<R, P, MF>(a), T + (t & 63) * n3, pl, cur.cv + e * n3, wg,
                            true, u, out, zero_sums);
@@ -2084,7 +2081,7 @@ void apply_ws_kernel(ApplyParams a) {
 // compute waves read their planes out of it before the operator's first
 // barrier, after which the loader wave refills it with the next item chunk by
 // chunk, one chunk per barrier phase of the operator (loads issued in one
-// phase, stored two phases later, so their latency overlaps the operator).  The
+// phase, stored in the next, so their latency overlaps the operator).  The
 // row offsets and JxW V of the next item go to the other of two LDS slots
 // during the first phase.  The cell results are added into Y cell by cell
 // with float64 atomics straight from the registers (no node sums in LDS), so
@@ -2100,12 +2097,12 @@ struct SharedPipe {
   static constexpr int NWC = n, NTC = 64 * NWC, NT = NTC + 64;
   static constexpr int NV = NB3 * 8, NCV = 8 * n3;
   static constexpr int kOpBarriers = 7;  // the Hamiltonian's operator
-  // chunks of CH values per lane: chunk c is loaded in phase c + 1 and stored
-  // in phase c + 3, two register buffers in flight, so that each chunk has
-  // two of the operator's phases to arrive
-  static constexpr int CH = 24;
+  // chunks of CH values per lane; phase b = 1..PH loads chunks
+  // [(b - 1) NCHK / PH, b NCHK / PH) (all but the last one stored at once),
+  // the last one is stored in phase b + 1
+  static constexpr int CH = 16;
   static constexpr int NCHK = (NV + 64 * CH - 1) / (64 * CH);
-  static_assert(NCHK + 2 <= kOpBarriers, "the chunks must fit the operator's phases");
+  static constexpr int PH = kOpBarriers - 1;
   static constexpr int KR = (NB3 + 63) / 64;
   static constexpr int KC = (NCV + 63) / 64;
   static constexpr int kListMax = 256;
@@ -2264,22 +2261,27 @@ __global__ __launch_bounds__(64 * (P + 2)) void apply_pipe1_kernel(ApplyParams a
       double v[L::CH];
       if (more) L::head(a, seq(k + 1), l, sm, nslot);
       if (nz_cur) {
-        // phase b follows barrier b of the operator: chunk b - 3 (loaded two
-        // phases ago) is stored, then chunk b - 1 is loaded; even chunks
-        // travel in v, odd ones in v2
-        double v2[L::CH];
+        // phase b follows barrier b of the operator: the chunk loaded in the
+        // previous phase is stored, then this phase's chunks are loaded (the
+        // last one left in flight to the next phase)
+        int pend = -1;
 #pragma unroll 1
         for (int b = 1; b <= L::kOpBarriers; ++b) {
           __syncthreads();
           if (more) {
-            const int sc = b - 3, lc = b - 1;
-            if (sc >= 0 && sc < L::NCHK) {
-              if (sc & 1) any |= L::chunk_store(sm, sc, l, v2);
-              else any |= L::chunk_store(sm, sc, l, v);
-            }
-            if (lc < L::NCHK) {
-              if (lc & 1) L::chunk_load(rX, xbytes, sm, nslot, lc, l, v2);
-              else L::chunk_load(rX, xbytes, sm, nslot, lc, l, v);
+            if (pend >= 0) any |= L::chunk_store(sm, pend, l, v);
+            pend = -1;
+            if (b <= L::PH) {
+              const int lo = (b - 1) * L::NCHK / L::PH, hi = b * L::NCHK / L::PH;
+#pragma unroll 1
+              for (int ch = lo; ch + 1 < hi; ++ch) {
+                L::chunk_load(rX, xbytes, sm, nslot, ch, l, v);
+                any |= L::chunk_store(sm, ch, l, v);
+              }
+              if (hi > lo) {
+                L::chunk_load(rX, xbytes, sm, nslot, hi - 1, l, v);
+                pend = hi - 1;
+              }
             }
           }
         }
@@ -2968,7 +2970,7 @@ int launch_tmmult(const TmParams& p, void* stream) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
   }
-  const int64_t nblk = std::max<int64_t>(1, p.nstored_pairs) + (p.fold_trace ? 1 : 0);
+  const int64_t nblk = (int64_t)p.ncb * p.ncb + (p.fold_trace ? 1 : 0);
   if (p.max_pair_parts > 1024)
     hipLaunchKernelGGL(tm_stage2_kernel<1024>, dim3((unsigned)nblk), dim3(1024), 0, st, p);
   else if (p.max_pair_parts > 128)

@@ -72,7 +72,6 @@ struct TmParams {
   double* tdiag;             // [ndiag] traces of the products with C1 = C2
   int64_t ndiag;
   int32_t fold_trace;        // 1: the trace is summed from tdiag in the second stage
-  int32_t nstored_pairs;     // blocks of S inside the product pattern (first in s2)
   int32_t M, ncb;
   double* S;
   double* trace;

@@ -180,6 +180,29 @@ class Server:
         return rep
 
 
+def apply_overlap(spans) -> dict:
+    """Device time the applies of different requests run together: spans are
+    (start, end, request) on one device timeline.  Returns the union of the
+    apply intervals, the sum of their lengths, the time during which applies
+    of two or more requests run at once, and its fraction of the union."""
+    ev = sorted([(t0, 1, rid) for t0, t1, rid in spans] + [(t1, -1, rid) for t0, t1, rid in spans])
+    active: Dict[int, int] = {}
+    union = multi = 0.0
+    last = None
+    for t, d, rid in ev:
+        if last is not None and active:
+            union += t - last
+            if len(active) >= 2:
+                multi += t - last
+        active[rid] = active.get(rid, 0) + d
+        if active[rid] == 0:
+            del active[rid]
+        last = t
+    total = sum(t1 - t0 for t0, t1, _ in spans)
+    return {"apply_union_s": union, "apply_sum_s": total, "apply_concurrent_s": multi,
+            "apply_concurrent_frac": multi / union if union > 0 else 0.0}
+
+
 def summarize(rep: ServeReport) -> dict:
     done = [r for r in rep.results.values() if not r.get("rejected")]
     applies = [t for r in done for t in r.get("apply_s", [])]
@@ -193,6 +216,10 @@ def summarize(rep: ServeReport) -> dict:
         "max_concurrent": rep.max_concurrent,
         "max_bytes_in_use": rep.max_bytes_in_use,
     }
+    spans = [(t0, t1, rid) for rid, r in rep.results.items() if not r.get("rejected")
+             for t0, t1 in r.get("apply_spans", [])]
+    if spans:
+        out.update(apply_overlap(spans))
     if applies:
         out.update({
             "apply_ms_p50": 1e3 * statistics.median(applies),
@@ -227,6 +254,7 @@ class GpuExecutor:
         self.tau_scale = tau_scale
         self.keep_X = keep_X
         self._lock = threading.Lock()
+        self._t0 = None  # a device event every apply interval is measured from
 
     # -- planning (host only)
     def _plan(self, req: Request) -> _Plan:
@@ -264,9 +292,12 @@ class GpuExecutor:
 
     # -- execution
     def start(self, plan: _Plan):
+        import torch
+        if self._t0 is None:
+            self._t0 = torch.cuda.Event(enable_timing=True)
+            self._t0.record()
         if plan.req.method == "om":
             return self._start_om(plan)
-        import torch
         from .api import mv_update, apply_H, tmmult
         stream = torch.cuda.Stream(device=self.device)
         with torch.cuda.stream(stream):
@@ -396,15 +427,21 @@ class GpuExecutor:
         else:
             tok["end"].synchronize()
         apply_s = [a.elapsed_time(b) * 1e-3 for a, b in tok["evs"]]
+        # each apply's interval on the device timeline (seconds from the
+        # executor's reference event): overlap across slot streams
+        spans = [(self._t0.elapsed_time(a) * 1e-3, self._t0.elapsed_time(b) * 1e-3)
+                 for a, b in tok["evs"]] if self._t0 is not None else []
         if plan.req.method == "om":
             X = tok["bufs"][0]
-            out = {"apply_s": apply_s, "entries": plan.layout.nvalues, "tau": tok["tau"],
+            out = {"apply_s": apply_s, "apply_spans": spans, "entries": plan.layout.nvalues,
+                   "tau": tok["tau"],
                    "energies": tok["energies"], "prec": plan.req.prec,
                    "bytes": plan.nbytes, "method": "om"}
         else:
             X, Y, work, S, S2, tr = tok["bufs"]
             trs = tr.cpu().numpy()
-            out = {"apply_s": apply_s, "entries": plan.layout.nvalues, "trace": float(trs[0]),
+            out = {"apply_s": apply_s, "apply_spans": spans, "entries": plan.layout.nvalues,
+                   "trace": float(trs[0]),
                    "trace_xx": float(trs[1]),
                    "x_norm2": float((X[:plan.layout.nvalues] ** 2).sum()),
                    "prec": plan.req.prec, "bytes": plan.nbytes}

@@ -1,5 +1,7 @@
 """Scheduler of the serving loop, on the CPU with a fake byte-counting executor."""
 
+import pytest
+
 from paper_1907_01005_amd.serving import FakeExecutor, Request, Server, request_stream, summarize
 
 
@@ -51,3 +53,39 @@ def test_request_stream_recipe():
     assert all(32 <= r.M <= 640 for r in rs)
     assert all(3.0 <= r.radius <= 5.0 for r in rs)
     assert {r.degree for r in rs} == {2, 4}
+
+
+def test_apply_overlap_intervals():
+    """Overlap of apply intervals: union, sum and the time two requests run
+    together, on hand-made intervals."""
+    from paper_1907_01005_amd.serving import apply_overlap
+    r = apply_overlap([(0.0, 2.0, 1), (1.0, 3.0, 2), (5.0, 6.0, 1), (5.5, 5.75, 1)])
+    assert r["apply_union_s"] == pytest.approx(4.0)
+    assert r["apply_sum_s"] == pytest.approx(5.25)
+    # request 1's two intervals overlapping each other are not concurrency
+    assert r["apply_concurrent_s"] == pytest.approx(1.0)
+    assert r["apply_concurrent_frac"] == pytest.approx(0.25)
+
+
+def test_trace_overlap_csv(tmp_path):
+    """The kernel-trace summary of the bench: library kernels only, overlap
+    counted across streams."""
+    import importlib.util
+    import os
+    spec = importlib.util.spec_from_file_location(
+        "bench_mod", os.path.join(os.path.dirname(__file__), "..", "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    rows = [("mfb::gpu::a", 0, 100, 1), ("mfb::gpu::b", 50, 150, 2), ("other", 0, 1000, 3),
+            ("mfb::gpu::c", 120, 130, 2), ("mfb::gpu::d", 200, 300, 1)]
+    p = tmp_path / "kernel_trace.csv"
+    with open(p, "w") as f:
+        f.write("Kernel_Name,Stream_Id,Start_Timestamp,End_Timestamp\n")
+        for n, a, b, sid in rows:
+            f.write(f"{n},{sid},{a},{b}\n")
+    r = bench.trace_overlap(str(p))
+    assert r["kernels"] == 4 and r["streams"] == 2
+    assert r["busy_union_ms"] == pytest.approx(250e-6)
+    assert r["kernel_sum_ms"] == pytest.approx(310e-6)
+    assert r["concurrent_ms"] == pytest.approx(50e-6)
+    assert r["most_streams_at_once"] == 2
