@@ -379,7 +379,8 @@ __device__ __forceinline__ void plane_operator(const Ctr& ctr, R* __restrict__ T
       for (int k = 0; k < n; ++k)
         wB[i][k] = (R)((double)wB[i][k] + cv[i + n * pl + n2 * k] * (double)uq[i][k]);
   }
-  __syncthreads();
+  // each thread writes back the very positions it read above, and no other
+  // thread reads them in this phase: no barrier before the write
   if (act) {
 #pragma unroll
     for (int k = 0; k < n; ++k)
@@ -400,7 +401,6 @@ __device__ __forceinline__ void plane_operator(const Ctr& ctr, R* __restrict__ T
 #pragma unroll
     for (int j = 0; j < n; ++j) B[i][j] = (R)((double)B[i][j] * wg[n3 + i + n * j + n2 * pl]);
   ctr.template c<1, true, 1>(B, A);
-  __syncthreads();
   if (act) {
 #pragma unroll
     for (int j = 0; j < n; ++j)
@@ -416,7 +416,6 @@ __device__ __forceinline__ void plane_operator(const Ctr& ctr, R* __restrict__ T
       for (int i = 0; i < n; ++i) wB[i][k] += Tc[i + n * pl + n2 * k];
   }
   ctr.template c<1, true, 0>(wB, A);
-  __syncthreads();
   if (act) {
 #pragma unroll
     for (int k = 0; k < n; ++k)
@@ -530,7 +529,9 @@ __device__ __forceinline__ void plane_operator_lean(const ApplyParams& a, R* __r
 #pragma unroll
     for (int k = 0; k < n; ++k)
       w[i][k] = (R)((double)w[i][k] + cv[i + n * pl + n2 * k] * (double)uq[i][k]);
-  __syncthreads();
+  // each thread writes back the very positions it read (its own plane of the
+  // other layout), which no other thread reads in this phase: a barrier is
+  // needed only before each read of the other layout
 #pragma unroll
   for (int k = 0; k < n; ++k)
 #pragma unroll
@@ -542,7 +543,6 @@ __device__ __forceinline__ void plane_operator_lean(const ApplyParams& a, R* __r
 #pragma unroll
     for (int i = 0; i < n; ++i) u[i][j] = Tc[i + n * j + n2 * pl];
   stiff_plane<n, 1, false>(u, u, K, [&](int i) { return a.gline[1][i + n * pl]; });
-  __syncthreads();
 #pragma unroll
   for (int j = 0; j < n; ++j)
 #pragma unroll
@@ -554,7 +554,6 @@ __device__ __forceinline__ void plane_operator_lean(const ApplyParams& a, R* __r
 #pragma unroll
     for (int i = 0; i < n; ++i) w[i][k] += Tc[i + n * pl + n2 * k];
   contract_ip<n, 1, true, kTabS>(Sm, w);
-  __syncthreads();
 #pragma unroll
   for (int k = 0; k < n; ++k)
 #pragma unroll
@@ -580,7 +579,7 @@ __device__ __forceinline__ void plane_operator_lean(const ApplyParams& a, R* __r
 //   w   = c_V (.) u_q + D_x^T g'_x + D_z^T g'_z,
 //   out = S_x^T S_y^T (S_z^T w + D_y^T S_z^T g'_y).
 // With a diagonal metric this is the box operator (plane_operator) taken in
-// another order: three barriers, fourteen 1D contractions.
+// another order: two barriers, fourteen 1D contractions.
 template <typename R, int P, class Ctr, class Hook>
 __device__ __forceinline__ void plane_operator_geo(const Ctr& ctr, R* __restrict__ T1,
                                                    R* __restrict__ T2, int pl,
@@ -640,7 +639,7 @@ __device__ __forceinline__ void plane_operator_geo(const Ctr& ctr, R* __restrict
       w[i][k] = (R)((double)w[i][k] + cv[i + n * pl + n2 * k] * (double)uq[i][k]);
   ctr.template c<1, true, 0>(w, X1);
   ctr.template c<1, true, 0>(B, X2);
-  __syncthreads();
+  // written back to the positions this thread read: no barrier before it
 #pragma unroll
   for (int k = 0; k < n; ++k)
 #pragma unroll
@@ -696,7 +695,7 @@ __device__ __forceinline__ void plane_mass(const Ctr& ctr, R* __restrict__ Tc, i
 #pragma unroll
     for (int k = 0; k < n; ++k) B[i][k] = (R)((double)B[i][k] * jxw[i + n * pl + n2 * k]);
   ctr.template c<1, true, 0>(B, A);
-  __syncthreads();
+  // written back to the positions this thread read: no barrier needed
   if (act) {
 #pragma unroll
     for (int k = 0; k < n; ++k)
@@ -1825,8 +1824,8 @@ void apply_fused_kernel(ApplyParams a, int spw) {
 // destination row offsets, JxW V of the cells) and already holds the row
 // offsets of item k + 2, so the compute waves never wait on global memory.
 // The loader passes the same barriers as the compute waves: the operator's
-// own (7 for H, 3 for M), the one before the flush and the one that ends
-// the item.
+// own (4 for H, 2 for M: one before each read of the other layout), the one
+// before the flush and the one that ends the item.
 template <int P>
 struct Stage {
   using D = Dims<P>;
@@ -1847,7 +1846,7 @@ struct LoaderPipe {
   static constexpr int KC = (8 * n3 + 63) / 64;    // JxW V entries per loader lane
   static constexpr int KR = (NB3 + 63) / 64;       // destination row offsets per loader lane
   static constexpr int KS = (NV + NTC - 1) / NTC;  // node sums per compute thread
-  static constexpr int kOpBarriers = OP == 0 ? 7 : 3;
+  static constexpr int kOpBarriers = OP == 0 ? 4 : 2;
   static constexpr int kListMax = 256;
   struct Smem {
     Stage<P> st[2];
@@ -2096,11 +2095,12 @@ struct SharedPipe {
   static constexpr int n = D::n, n2 = D::n2, n3 = D::n3, NB = D::NB, NB3 = D::NB3;
   static constexpr int NWC = n, NTC = 64 * NWC, NT = NTC + 64;
   static constexpr int NV = NB3 * 8, NCV = 8 * n3;
-  static constexpr int kOpBarriers = 7;  // the Hamiltonian's operator
+  static constexpr int kOpBarriers = 4;  // the Hamiltonian's operator
   // chunks of CH values per lane; phase b = 1..PH loads chunks
   // [(b - 1) NCHK / PH, b NCHK / PH) (all but the last one stored at once),
-  // the last one is stored in phase b + 1
-  static constexpr int CH = 16;
+  // the last one is stored in phase b + 1 (at p = 4 three chunks, one per
+  // phase)
+  static constexpr int CH = 32;
   static constexpr int NCHK = (NV + 64 * CH - 1) / (64 * CH);
   static constexpr int PH = kOpBarriers - 1;
   static constexpr int KR = (NB3 + 63) / 64;
