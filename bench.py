@@ -459,6 +459,25 @@ def cold_times(dp, prec: int, reps: int = 10, scrub_mib: int = 1024):
 KERNELS = {0: "default", 1: "queue", 2: "batch-grid", 7: "loader-pipelined", 8: "register-waves"}
 
 
+def default_apply_kernel(dp, degree: int, prec_name: str) -> str:
+    """The kernel mfb_apply_H launches after the zero fill on box cells (the
+    library's rule: at p = 2 the fused grid for fp64 below 64 own items per CU,
+    else the loader pipeline; at p = 3, 4 the shared-stage pipeline while X's
+    byte offsets fit 31 bits)."""
+    import torch
+    if prec_name in ("fp32", "fp64-mfma"):
+        return "apply_fused_kernel"
+    if degree == 2:
+        cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+        own = dp.layout.info["apply_items_own"]
+        if prec_name == "fp64" and own < 64 * cus:
+            return "apply_fused_kernel"
+        return "apply_ws_kernel"
+    if degree >= 3 and dp.nvalues * 8 < 2 ** 31:
+        return "apply_pipe1_kernel"
+    return "apply_fused_kernel"
+
+
 def executed_flops_per_cell_column(p: int) -> int:
     """Flops the vector-ALU kernels execute per cell and column: the gradient
     terms go through the 1D stiffness K1 = D^T diag(w) D (one n x n product per
@@ -493,7 +512,7 @@ def measure(wl, dp, prec_name: str, steps: int, warmup: int, kernel: int, copy_g
                 "frac": gbs / HBM_PEAK_GBS}
     vector_form = prec_name in ("fp64", "fp32")
     exe = executed_flops_per_cell_column(degree) * alg["cell_columns"] if vector_form else alg["flops"]
-    default_kernel = "apply_ws_kernel" if degree == 2 else "apply_fused_kernel"
+    default_kernel = default_apply_kernel(dp, degree, prec_name)
     roof.update({"traffic": measured_traffic(wl.name, prec_name),
                  "kernel": "apply_H launch (fill_zero_kernel + %s)" % (
                      default_kernel if kernel == 0 else {1: "apply_queue_kernel",

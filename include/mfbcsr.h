@@ -206,6 +206,8 @@ typedef struct {
   int64_t s_pairs;          /* stored (C1, C2) blocks of S                     */
   int64_t tm_tasks;         /* densely populated row blocks whose products of
                                Alg. 8 run as one task each (not in tm_units)   */
+  int64_t apply_items_own;  /* apply items whose batch's own block is stored
+                               (the rest are shell items)                      */
 } mfb_mv_info;
 
 /* Table-1-style statistics of a layout (Sec. 4.1, Table 1).                   */

@@ -40,7 +40,8 @@ class MvInfo(C.Structure):
                 ("nblocks", C.c_int64), ("nvalues", C.c_int64), ("meta_bytes", C.c_size_t),
                 ("work_bytes", C.c_size_t), ("apply_items", C.c_int64),
                 ("apply_pairs", C.c_int64), ("apply_pairs_own", C.c_int64),
-                ("tm_units", C.c_int64), ("s_pairs", C.c_int64), ("tm_tasks", C.c_int64)]
+                ("tm_units", C.c_int64), ("s_pairs", C.c_int64), ("tm_tasks", C.c_int64),
+                ("apply_items_own", C.c_int64)]
 
 
 class Stats(C.Structure):

@@ -306,6 +306,7 @@ int mfb_mv_get_info(const mfb_mv* mv, mfb_mv_info* out) {
   out->meta_bytes = mv->lay.bytes;
   out->work_bytes = mv->work_bytes;
   out->apply_items = (int64_t)p.items.size();
+  out->apply_items_own = p.n_own_items;
   out->apply_pairs = p.apply_pairs;
   out->apply_pairs_own = p.apply_pairs_own;
   out->tm_units = (int64_t)p.units.size();
@@ -598,10 +599,11 @@ int mfb_apply_H(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X, doubl
   if (prec < 0 || prec > 3) fail(MFB_EINVAL, "unknown precision");
   mfb::gpu::ApplyParams a;
   fill_apply_params(mesh, mv, d_X, d_Y, a);
-  // the loader-pipelined kernel (7) for the fp64 and fp32-MFMA forms (it runs
-  // the fused grid itself at p != 2 and on curved cells), the fused grid (0)
-  // for the fp32 VALU form
-  const int kernel = (prec == MFB_FP64 || prec == MFB_FP32_MFMA) ? 7 : 0;
+  // the library's choice (-1) for the fp64 and fp32-MFMA forms: at p = 2 the
+  // loader pipeline, or the fused grid when there are few items per CU (fp64);
+  // at p = 3, 4 the shared-stage pipeline on box cells; the fused grid on
+  // curved cells.  The fused grid (0) for the fp64-MFMA and fp32 VALU forms.
+  const int kernel = (prec == MFB_FP64 || prec == MFB_FP32_MFMA) ? -1 : 0;
   const int rc =
       mfb::gpu::launch_apply(a, mesh->plan.p, prec, kernel, mv->plan.block_offset.back(), stream);
   if (rc == -2) fail(MFB_EUNSUPPORTED, "precision not implemented by the library");

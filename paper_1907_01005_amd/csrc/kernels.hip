@@ -35,6 +35,16 @@ namespace {
 __device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// Raw buffer resource over `bytes` bytes at `base` (gfx9 descriptor word 3):
+// loads at offsets past the end return 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ double buffer_load_f64(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+
 // out[o0][o1] = sum_k M(o_AX, k) in[...k...]; M(o,k) = M[o*n+k], or M[k*n+o]
 // when TR (the transposed matrix).  AX = index of `in` that is contracted.
 template <int n, int AX, bool TR, typename R>
@@ -494,12 +504,15 @@ __device__ __forceinline__ void stiff_plane(const R (&u)[n][n], R (&w)[n][n], co
 // scaling and a transposed derivative), so the quadrature values and the
 // accumulated result are the only planes held across a layout switch.  Same
 // layouts, barriers and calling convention as plane_operator; u is
-// overwritten.
+// overwritten.  JxW V: with GLOBAL_CV, cv is the (wave-uniform) start of the
+// batch's eight cells in global memory and cv_lane the element offset of the
+// thread's cell; otherwise cv points at the thread's cell in LDS.
 template <typename R, int P, class Hook, bool GLOBAL_CV = true>
 __device__ __forceinline__ void plane_operator_lean(const ApplyParams& a, R* __restrict__ Tc, int pl,
                                                     const double* cv, R (&u)[P + 1][P + 1],
-                                                    R (&out)[P + 1][P + 1], Hook after_first_barrier) {
-  constexpr int n = P + 1, n2 = n * n;
+                                                    R (&out)[P + 1][P + 1], Hook after_first_barrier,
+                                                    int cv_lane = 0) {
+  constexpr int n = P + 1, n2 = n * n, n3 = n2 * n;
   const R* __restrict__ Sm = tab_S<R>(a);
   const R* __restrict__ K = tab_K<R>(a);
   // layout A (z = pl): interpolate along x and y
@@ -511,10 +524,19 @@ __device__ __forceinline__ void plane_operator_lean(const ApplyParams& a, R* __r
     for (int i = 0; i < n; ++i) Tc[i + n * j + n2 * pl] = u[i][j];
   __syncthreads();
   after_first_barrier();
-  // the potential's coefficients (in global memory) are read here, where they
-  // are used: the empty asm keeps their loads from being hoisted (and held in
-  // registers) across the first phase.  LDS copies stay below the barrier.
-  if constexpr (GLOBAL_CV) asm volatile("" : "+v"(cv));
+  // the potential's coefficients in global memory are read here, where they
+  // are used, through a buffer resource over the batch's cells: vector-memory
+  // loads only (a flat load would also hold up every LDS wait until it
+  // returns), and the empty asm on the offset keeps them from being hoisted
+  // (and held in registers) across the first phase.
+  uint32_t cvo = (uint32_t)(cv_lane + n * pl) * 8u;
+  if constexpr (GLOBAL_CV) asm volatile("" : "+v"(cvo));
+  auto cv_at = [&](int i, int k) -> double {
+    if constexpr (GLOBAL_CV)
+      return buffer_load_f64(buffer_rsrc(cv, 8u * n3 * 8u), cvo + (uint32_t)(i + n2 * k) * 8u, 0);
+    else
+      return cv[i + n * pl + n2 * k];
+  };
   // layout B (y = pl): along z, then the x and z gradient terms and V
   R uq[n][n], w[n][n];
 #pragma unroll
@@ -528,7 +550,7 @@ __device__ __forceinline__ void plane_operator_lean(const ApplyParams& a, R* __r
   for (int i = 0; i < n; ++i)
 #pragma unroll
     for (int k = 0; k < n; ++k)
-      w[i][k] = (R)((double)w[i][k] + cv[i + n * pl + n2 * k] * (double)uq[i][k]);
+      w[i][k] = (R)((double)w[i][k] + cv_at(i, k) * (double)uq[i][k]);
   // each thread writes back the very positions it read (its own plane of the
   // other layout), which no other thread reads in this phase: a barrier is
   // needed only before each read of the other layout
@@ -865,7 +887,8 @@ struct BatchProc {
         plane_operator_geo<R, P>(make_ctr<R, P, MF>(a), Tc, tile2(sm) + (t & 63) * D::n3, pl, cv,
                                  a.cG + cell * 6 * D::n3, u, out, hook);
       else if constexpr (OP == 0 && !MF)
-        plane_operator_lean<R, P>(a, Tc, pl, cv, u, out, hook);
+        plane_operator_lean<R, P>(a, Tc, pl, a.cV + (int64_t)__builtin_amdgcn_readfirstlane(rank) * 8 * D::n3,
+                                  u, out, hook, e * D::n3);
       else if constexpr (OP == 0)
         plane_operator<R, P>(make_ctr<R, P, MF>(a), Tc, pl, cv, wg, true, u, out, hook);
       else if constexpr (GEO)
@@ -896,15 +919,18 @@ struct BatchProc {
       }
     } else if constexpr (!DEST) {
       // p >= 3: the row offsets are read again here rather than held in
-      // registers through the operator
-      const int32_t* r2 = a.rowoff + idx * D::NB3;
-      asm volatile("" : "+s"(r2));  // a fresh read, not the gather's values kept live
+      // registers through the operator (through a buffer resource, with an
+      // opaque offset: a fresh read, not the gather's values kept live)
+      const __amdgpu_buffer_rsrc_t r2 = buffer_rsrc(a.rowoff + idx * D::NB3, D::NB3 * 4u);
+      uint32_t tt = (uint32_t)t;
+      asm volatile("" : "+v"(tt));
       const int nc = a.items[idx].nc;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const int e2 = t + k * NT;
         if (e2 >= NV || (e2 & 7) >= nc) continue;
-        const int32_t o = r2[e2 >> 3];
+        const int32_t o = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(
+            r2, (int)(((tt + (uint32_t)(k * NT)) >> 3) << 2), 0, 0);
         if (o >= 0) unsafeAtomicAdd(a.Y + (int64_t)o + (e2 & 7), G[e2]);
       }
     } else {
@@ -1186,9 +1212,15 @@ struct RegWave {
     sweep_c<n, 2, false, kTabS>(u, Sm);
     R w[n3];
     if constexpr (OP == 0) {
-      const double* __restrict__ cv = a.cV + ((int64_t)rank * 8 + e) * n3;
+      // JxW V through a buffer resource over the batch's cells, the offset
+      // opaque: the loads are issued here, not hoisted to the start and held
+      // in registers through the sweeps
+      const __amdgpu_buffer_rsrc_t rcv =
+          buffer_rsrc(a.cV + (int64_t)__builtin_amdgcn_readfirstlane(rank) * 8 * n3, 8u * n3 * 8u);
+      uint32_t cvo = (uint32_t)(e * n3) * 8u;
+      asm volatile("" : "+v"(cvo));
 #pragma unroll
-      for (int q = 0; q < n3; ++q) w[q] = (R)(cv[q] * (double)u[q]);
+      for (int q = 0; q < n3; ++q) w[q] = (R)(buffer_load_f64(rcv, cvo + q * 8u, 0) * (double)u[q]);
       const R* __restrict__ K = tab_K<R>(a);
       stiff_line_pass<n, 0>(u, w, K, a.gline[0]);
       stiff_line_pass<n, 1>(u, w, K, a.gline[1]);
@@ -1204,7 +1236,13 @@ struct RegWave {
     face_sum<n, 1>(w, e);
     face_sum<n, 2>(w, e);
     if (c >= nc) return;
-    const int32_t* __restrict__ rd = (DEST ? a.rowoff_out : a.rowoff) + idx * NB3;
+    // the destination offsets are read here, through a buffer resource with
+    // an opaque lane offset (not hoisted to the start and held)
+    const __amdgpu_buffer_rsrc_t rd = buffer_rsrc(
+        (DEST ? a.rowoff_out : a.rowoff) + (int64_t)__builtin_amdgcn_readfirstlane((int)idx) * NB3,
+        NB3 * 4u);
+    uint32_t rdo = 0;
+    asm volatile("" : "+v"(rdo));
     const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
 #pragma unroll
     for (int k = 0; k < n; ++k)
@@ -1213,7 +1251,8 @@ struct RegWave {
 #pragma unroll
         for (int i = 0; i < n; ++i) {
           if ((ex && i == 0) || (ey && j == 0) || (ez && k == 0)) continue;
-          const int32_t r = rd[node(e, i, j, k)];
+          const int32_t r =
+              (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rd, (int)(rdo + node(e, i, j, k) * 4u), 0, 0);
           if (r >= 0) unsafeAtomicAdd(a.Y + (int64_t)r + c, (double)w[i + n * j + n2 * k]);
         }
   }
@@ -1320,15 +1359,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Raw buffer resource over `bytes` bytes at `base` (gfx9 descriptor word 3):
-// loads at offsets past the end return 0.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
-}
-
-__device__ __forceinline__ double buffer_load_f64(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
-}
 
 // Blocks at most 8 wide on both sides, on the fp64 matrix cores.  In
 // v_mfma_f64_16x16x4f64 lane l supplies A(l % 16, l / 16) and B(l / 16,
@@ -1824,8 +1854,8 @@ void apply_fused_kernel(ApplyParams a, int spw) {
 // destination row offsets, JxW V of the cells) and already holds the row
 // offsets of item k + 2, so the compute waves never wait on global memory.
 // The loader passes the same barriers as the compute waves: the operator's
-// own (4 for H, 2 for M: one before each read of the other layout), the one
-// before the flush and the one that ends the item.
+// own (4 for H, 2 for M: one before each read of the other layout) and the
+// one before the flush, ahead of which it stages the next item.
 template <int P>
 struct Stage {
   using D = Dims<P>;
@@ -2035,8 +2065,14 @@ void apply_ws_kernel(ApplyParams a) {
         L::issue(a, seq(k + 1), l, h, s);
         if (k + 2 < nk) L::rows(a, seq(k + 2), l, h);
       }
+      // the next item is staged after the operator's barriers (item k - 1's
+      // flush, the last reader of that stage, is then done) and before the
+      // barrier ahead of item k's flush, which hands the stage over; an item
+      // with no non-zero value passes two barriers instead
       if (nz_cur)
-        for (int b = 0; b < L::kOpBarriers + 1; ++b) __syncthreads();
+        for (int b = 0; b < L::kOpBarriers; ++b) __syncthreads();
+      else
+        __syncthreads();
       if (more) nz_cur = L::store(sm.st[(k + 1) & 1], l, s);
       __syncthreads();
     }
@@ -2065,10 +2101,16 @@ void apply_ws_kernel(ApplyParams a) {
     const int nk = n_own + min(__builtin_amdgcn_readfirstlane(sm.nlist), L::kListMax);
     if (nk == 0) return;
     if (n_own == 0) __syncthreads();
+    // no barrier at the end of an item: its flush runs on into the next
+    // item's first phase, whose stage was handed over before the flush
     for (int k = 0; k < nk; ++k) {
       Stage<P>& cur = sm.st[k & 1];
-      if (__builtin_amdgcn_readfirstlane(cur.nz)) L::compute(a, cur, sm.T, sm.wg, t, wv);
-      __syncthreads();
+      if (__builtin_amdgcn_readfirstlane(cur.nz)) {
+        L::compute(a, cur, sm.T, sm.wg, t, wv);
+      } else {
+        __syncthreads();
+        __syncthreads();
+      }
     }
   }
 }
@@ -2471,8 +2513,13 @@ hipError_t launch_pipe1(const ApplyParams& p, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Below this many own items per CU the p = 2 Hamiltonian runs on the fused
+// grid rather than the loader pipeline.
+constexpr int kFusedItemsPerCu = 64;
+
+// pick: the default apply (may take the fused grid); false: kernel 7 itself.
 template <typename R, int P, bool MF, int OP>
-hipError_t launch_ws(const ApplyParams& p, int grid, hipStream_t st) {
+hipError_t launch_ws(const ApplyParams& p, int grid, hipStream_t st, bool pick = true) {
   if constexpr (P != 2) {
     // p >= 3 on box cells with X's own pattern as the destination: the
     // shared-stage loader pipeline; otherwise the fused grid
@@ -2483,6 +2530,14 @@ hipError_t launch_ws(const ApplyParams& p, int grid, hipStream_t st) {
     if (p.cG) return launch_fused<R, P, MF, OP>(p, 0, st);  // curved cells: the fused grid
     if (p.nitems + p.nshell == 0) return hipSuccess;
     const bool dest = p.rowoff_out != p.rowoff;
+    // few items per CU (the fp64 Hamiltonian onto X's own pattern): the fused
+    // grid, whose one-item workgroups fill the CUs more densely, is faster
+    // there (61.6 against 63.5 us for apply_H at 31 own items per CU); with
+    // many items per CU the pipeline's overlap of gather and compute wins
+    // (758 against 889 us at 575)
+    if constexpr (OP == 0 && !MF && std::is_same<R, double>::value)
+      if (pick && !dest && p.nitems < int64_t(kFusedItemsPerCu) * device_cu_count())
+        return launch_fused<R, P, MF, OP>(p, 0, st);
     const void* fn = dest ? reinterpret_cast<const void*>(&apply_ws_kernel<R, P, MF, OP, true>)
                           : reinterpret_cast<const void*>(&apply_ws_kernel<R, P, MF, OP, false>);
     constexpr int NT = 64 * (P + 2);
@@ -2519,14 +2574,15 @@ hipError_t launch_reg(const ApplyParams& p, hipStream_t st) {
 
 template <typename R, int P, bool MF = false>
 hipError_t launch_apply_t(const ApplyParams& p, int kernel, hipStream_t st) {
-  // curved cells: the fused grid only (kernel 7 runs it too)
-  if (p.cG && kernel != 0 && kernel != 2 && kernel != 7) return hipErrorNotSupported;
+  // curved cells: the fused grid only (kernels 7 and -1 run it too)
+  if (p.cG && kernel != -1 && kernel != 0 && kernel != 2 && kernel != 7) return hipErrorNotSupported;
   if (kernel == 8) {
     if constexpr (P <= 2 && !MF) return launch_reg<R, P, 0, false>(p, st);
     else return hipErrorNotSupported;
   }
   if (kernel == 6) return launch_pipe<R, P, MF>(p, st);
-  if (kernel == 7) return launch_ws<R, P, MF, 0>(p, p.grid, st);
+  if (kernel == 7) return launch_ws<R, P, MF, 0>(p, p.grid, st, false);
+  if (kernel == -1) return launch_ws<R, P, MF, 0>(p, p.grid, st, true);  // the default apply
   const bool queue = (kernel & 1) != 0;
   // processor: kernels 0/1 the default for the degree, 2/3 the batch
   // processor, 4/5 the single-wave processor (RegProc for p = 2, CellProc
@@ -2795,8 +2851,8 @@ int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t
                  void* stream) {
   hipStream_t st = (hipStream_t)stream;
   // refuse before anything is enqueued, so that a refused call leaves Y as it was
-  if (degree < 1 || degree > 4 || prec < 0 || prec > 3 || kernel < 0 || kernel > 8) return -2;
-  if (p.cG && kernel != 0 && kernel != 2 && kernel != 7) return -2;
+  if (degree < 1 || degree > 4 || prec < 0 || prec > 3 || kernel < -1 || kernel > 8) return -2;
+  if (p.cG && kernel != -1 && kernel != 0 && kernel != 2 && kernel != 7) return -2;
   if (kernel == 8 && !reg_kernel_supported(degree, prec, p.cG != nullptr)) return -2;
   {
     const int64_t blocks = std::min<int64_t>(4096, std::max<int64_t>(1, (nvalues / 2 + 255) / 256));

@@ -78,8 +78,10 @@ struct TmParams {
 };
 
 // prec: 0 fp64 VALU, 1 fp64 MFMA, 2 fp32 MFMA, 3 fp32 VALU.
-// kernel: 0/1 default processor as grid/queue, 2/3 batch processor, 4/5
-// single-wave processor (register-resident for p = 2, per cell for p = 4).
+// kernel: -1 the library's choice (mfb_apply_H), 0/1 default processor as
+// grid/queue, 2/3 batch processor, 4/5 single-wave processor
+// (register-resident for p = 2, per cell for p = 4), 6 pipelined persistent,
+// 7 loader pipeline, 8 register-resident waves.
 // Returns a hipError_t value (0 on success) or -2 for an unsupported variant.
 int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t nvalues,
                  void* stream);
