@@ -155,6 +155,28 @@ def copy_bandwidth(mib: int = 1024, reps: int = 5) -> float:
     return gbs
 
 
+def fp64_fma_rate(reps: int = 5) -> float:
+    """TFLOP/s of the library's fp64 FMA probe (8 independent chains per
+    thread, 8 workgroups of 256 threads per CU): the fp64 vector-ALU rate this
+    device reaches, beside the 78.6 TF/s it is rated at."""
+    import torch
+    from paper_1907_01005_amd import api
+    cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    blocks, iters = 8 * cus, 20000
+    api.probe_fp64_fma(out, blocks, iters)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        flops = api.probe_fp64_fma(out, blocks, iters)
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b) * 1e-3)
+    return flops / float(np.median(ts)) / 1e12
+
+
 def build_problem(cfg: int, mesh_index: int = 0, radius: float = 0.0, bend: float = 0.0):
     """The seeded workload of configuration `cfg` on the GPU; radius > 0 replaces the
     support radius (same centres, potential and blocks; a different workload); bend > 0
@@ -522,7 +544,7 @@ def executed_flops_per_cell_column(p: int) -> int:
 
 
 def measure(wl, dp, prec_name: str, steps: int, warmup: int, kernel: int, copy_gbs: float,
-            cold: bool = True) -> dict:
+            cold: bool = True, fma_tfs: float = 0.0) -> dict:
     """One workload: the K steps as one hipGraph (value), the eager loop with
     events around every launch (latencies, the roofline of the apply_H launch)
     and, with cold, apply_H and tmmult after a scrub of L2 and MALL (the
@@ -566,7 +588,9 @@ def measure(wl, dp, prec_name: str, steps: int, warmup: int, kernel: int, copy_g
                  "alu_frac": tfl / peak_f,
                  # min(P, B I): the roof at this arithmetic intensity
                  "attainable_frac": tfl / min(peak_f, HBM_PEAK_GBS * alg["flops"] / alg["bytes"] / 1e3),
-                 "copy_gbs": copy_gbs, "hbm_frac_vs_copy": gbs / copy_gbs})
+                 "copy_gbs": copy_gbs, "hbm_frac_vs_copy": gbs / copy_gbs,
+                 "fp64_fma_probe_tflops": fma_tfs or None,
+                 "alu_frac_vs_probe": tfl / fma_tfs if fma_tfs else None})
     tm_bytes = 16 * alg["E"] + 8 * dp.M * dp.M
     t_t = float(np.mean(t_tm))
     rec = {
@@ -676,7 +700,8 @@ def main(argv=None):
     print(f"[bench] E={dp.nvalues} items={dp.layout.info['apply_items']}; timing {args.steps} steps",
           file=sys.stderr, flush=True)
     copy_gbs = copy_bandwidth()
-    rec = measure(wl, dp, args.prec, args.steps, args.warmup, args.kernel, copy_gbs,
+    fma_tfs = fp64_fma_rate()
+    rec = measure(wl, dp, args.prec, args.steps, args.warmup, args.kernel, copy_gbs, fma_tfs=fma_tfs,
                   cold=not args.no_forms)
     out = {
         "metric": "apply_H GDoF*cols/s (stored BCSR entries per second, apply_H + tmmult step)",
@@ -714,7 +739,8 @@ def main(argv=None):
             import torch
             torch.cuda.empty_cache()
             wl3, dp3 = build_problem(3)
-            q4 = measure(wl3, dp3, args.prec, min(args.steps, 100), args.warmup, 0, copy_gbs)
+            q4 = measure(wl3, dp3, args.prec, min(args.steps, 100), args.warmup, 0, copy_gbs,
+                         fma_tfs=fma_tfs)
             q4["workload"] = wl3.name
             q4["stored_entries"] = dp3.nvalues
             q4["forms"] = precision_forms(dp3, q4["roofline"]["eager_launch_s"], 4)

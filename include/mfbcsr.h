@@ -431,6 +431,17 @@ int mfb_tmmult_noalloc(const mfb_mv* mv, const double* d_X, const double* d_Y, d
 int mfb_mv_update(const mfb_mv* mv, double* d_X, const double* d_Y, const double* d_S,
                   const double* d_S2, double tau, void* stream);
 
+/* Measurement instrument: the fp64 vector-ALU rate this device reaches, the
+ * roof the vector forms of the apply are held against (Sec. 4.2 compares its
+ * kernels' GFlop/s with the machine's).  Launches `blocks` workgroups of 256
+ * threads; each thread runs 8 independent chains of `iters` fused
+ * multiply-adds (16 iters flops).  d_out: at least 8 bytes of device memory,
+ * written only if the chains reach a value they cannot reach (it keeps the
+ * arithmetic from being removed).  The caller times the launch on its stream
+ * (flops = blocks * 256 * 16 * iters).  Errors: EINVAL (blocks or iters < 1,
+ * null d_out), EHIP.                                                         */
+int mfb_probe_fp64_fma(double* d_out, int64_t blocks, int32_t iters, void* stream);
+
 /* Thread-local message describing the last error (empty if none).           */
 const char* mfb_last_error(void);
 

@@ -98,6 +98,7 @@ SIGNATURES = {
     "mfb_tmmult": (C.c_int, [VP, VP, VP, VP, VP, VP, VP]),
     "mfb_tmmult_noalloc": (C.c_int, [VP, VP, VP, VP, VP, VP]),
     "mfb_mv_update": (C.c_int, [VP, VP, VP, VP, VP, C.c_double, VP]),
+    "mfb_probe_fp64_fma": (C.c_int, [VP, C.c_int64, C.c_int32, VP]),
     "mfb_create_closure": (C.c_int, [VP, C.POINTER(VP)]),
     "mfb_apply_op": (C.c_int, [VP, VP, VP, C.c_int, VP, VP, C.c_int, VP]),
     "mfb_energy": (C.c_int, [C.c_int32, VP, VP, VP, VP, VP]),

@@ -867,4 +867,14 @@ int mfb_mv_update(const mfb_mv* mv, double* d_X, const double* d_Y, const double
   MFB_CATCH
 }
 
+int mfb_probe_fp64_fma(double* d_out, int64_t blocks, int32_t iters, void* stream) {
+  MFB_TRY
+  if (!d_out) fail(MFB_EINVAL, "null output");
+  if (blocks < 1 || blocks > (int64_t(1) << 31) - 1 || iters < 1) fail(MFB_EINVAL, "blocks and iters must be positive");
+  const int rc = mfb::gpu::launch_probe_fma(d_out, blocks, iters, stream);
+  if (rc != 0) fail(MFB_EHIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)rc));
+  return MFB_OK;
+  MFB_CATCH
+}
+
 }  // extern "C"

@@ -2839,6 +2839,30 @@ int launch_update(const UpdateParams& p, void* stream) {
   return (int)hipGetLastError();
 }
 
+// Eight independent chains per thread keep the fp64 pipes busy without a
+// dependency stall; the chains converge to c / (1 - m) = -1e-3 and never
+// reach the sentinel, so the store never happens but the arithmetic stays.
+__global__ __launch_bounds__(256) void probe_fma_kernel(double* out, int32_t iters) {
+  double a[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) a[k] = 1e-3 * (double)(threadIdx.x + 1) + 1e-6 * k;
+  const double m = 0.999999, c = -1e-9;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = __builtin_fma(a[k], m, c);
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s += a[k];
+  if (s == 12345.678) out[0] = s;
+}
+
+int launch_probe_fma(double* out, int64_t blocks, int32_t iters, void* stream) {
+  hipLaunchKernelGGL(probe_fma_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                     out, iters);
+  return (int)hipGetLastError();
+}
+
 int device_cu_count() {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;

@@ -142,6 +142,9 @@ int launch_scale_columns(const BlockView& v, const double* scale, double* X, voi
 constexpr int kDotPartials = 1024;
 int launch_dot(int64_t n, const double* X, const double* Y, double* out, double* work, void* stream);
 int device_cu_count();
+// fp64 fused multiply-add rate probe: blocks x 256 threads, 8 chains of
+// iters FMAs each; out written only on an impossible value.
+int launch_probe_fma(double* out, int64_t blocks, int32_t iters, void* stream);
 
 }  // namespace gpu
 }  // namespace mfb

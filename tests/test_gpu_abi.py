@@ -110,3 +110,30 @@ def test_refused_calls_leave_buffers_untouched():
         apply_H(dp.mesh, dp.layout, dp.X, dp.Y, FP64)
         torch.cuda.synchronize()
         assert not torch.equal(dp.Y, sentinel)
+
+
+def test_fp64_fma_probe():
+    """The measurement probe runs, leaves its output untouched (the chains
+    never reach the sentinel) and reports a rate between a tenth of the
+    rated fp64 peak and the peak itself; bad arguments are refused."""
+    import torch
+    from paper_1907_01005_amd import _native as N
+    from paper_1907_01005_amd import MfbError
+    from paper_1907_01005_amd.api import probe_fp64_fma
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    probe_fp64_fma(out, 8 * cus, 2000)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    flops = probe_fp64_fma(out, 8 * cus, 20000)
+    b.record()
+    torch.cuda.synchronize()
+    tfs = flops / (a.elapsed_time(b) * 1e-3) / 1e12
+    say(f"fp64 FMA probe: {tfs:.1f} TFLOP/s on {cus} CUs")
+    assert out.item() == 0.0
+    assert 0.1 * 78.6 * cus / 256 < tfs <= 1.02 * 78.6 * cus / 256
+    for blocks, iters in ((0, 10), (4, 0)):
+        with pytest.raises(MfbError) as e:
+            probe_fp64_fma(out, blocks, iters)
+        assert e.value.code == N.MFB_EINVAL
