@@ -156,7 +156,7 @@ def copy_bandwidth(mib: int = 1024, reps: int = 5) -> float:
 
 
 def fp64_fma_rate(reps: int = 5) -> float:
-    """TFLOP/s of the library's fp64 FMA probe (8 independent chains per
+    """TFLOP/s of the library's fp64 FMA probe (16 independent chains per
     thread, 8 workgroups of 256 threads per CU): the fp64 vector-ALU rate this
     device reaches, beside the 78.6 TF/s it is rated at."""
     import torch

@@ -101,7 +101,10 @@ typedef enum {
 
 /* Box [0,Lx]x[0,Ly]x[0,Lz] split into nx x ny x nz equal Q_p cells.
  * nx, ny, nz must be even (cells are grouped in 2x2x2 batches, the coarse
- * level of Alg. 1).  degree p in 1..4 (else MFB_EUNSUPPORTED).
+ * level of Alg. 1).  degree p in 1..6 (else MFB_EUNSUPPORTED); at p = 5, 6 the
+ * applies run the fp64 and fp32 vector forms on box cells (one workgroup
+ * per cell), and the matrix-core forms, curved cells and the tuned kernel
+ * variants other than 0 give MFB_EUNSUPPORTED.
  * dirichlet_faces: bit 2d = face x_d = 0, bit 2d+1 = face x_d = L_d.
  * order: 0 = batches along the Hilbert curve (Alg. 1 step 2), 1 = batches
  * in lexicographic order (x fastest).                                      */
@@ -434,11 +437,11 @@ int mfb_mv_update(const mfb_mv* mv, double* d_X, const double* d_Y, const double
 /* Measurement instrument: the fp64 vector-ALU rate this device reaches, the
  * roof the vector forms of the apply are held against (Sec. 4.2 compares its
  * kernels' GFlop/s with the machine's).  Launches `blocks` workgroups of 256
- * threads; each thread runs 8 independent chains of `iters` fused
- * multiply-adds (16 iters flops).  d_out: at least 8 bytes of device memory,
+ * threads; each thread runs 16 independent chains of `iters` fused
+ * multiply-adds (32 iters flops).  d_out: at least 8 bytes of device memory,
  * written only if the chains reach a value they cannot reach (it keeps the
  * arithmetic from being removed).  The caller times the launch on its stream
- * (flops = blocks * 256 * 16 * iters).  Errors: EINVAL (blocks or iters < 1,
+ * (flops = blocks * 256 * 32 * iters).  Errors: EINVAL (blocks or iters < 1,
  * null d_out), EHIP.                                                         */
 int mfb_probe_fp64_fma(double* d_out, int64_t blocks, int32_t iters, void* stream);
 

@@ -320,10 +320,10 @@ def mv_update(layout: Layout, X, Y, S, S2, tau: float, stream=None) -> None:
 
 
 def probe_fp64_fma(out, blocks: int, iters: int, stream=None) -> int:
-    """mfb_probe_fp64_fma: blocks x 256 threads of 8 x iters fp64 FMAs; returns
+    """mfb_probe_fp64_fma: blocks x 256 threads of 16 x iters fp64 FMAs; returns
     the flop count of the launch (the caller times it)."""
     check(lib().mfb_probe_fp64_fma(_f64(out, "out", 1), int(blocks), int(iters), _stream(stream)))
-    return int(blocks) * 256 * 16 * int(iters)
+    return int(blocks) * 256 * 32 * int(iters)
 
 
 def apply_op(mesh: Mesh, x: Layout, y: Layout, op: int, X, Y, prec: int = FP64,

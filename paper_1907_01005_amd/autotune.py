@@ -69,6 +69,8 @@ def candidates(cu_count: int, curved: bool = False, degree: int = 2,
                prec: int = api.FP64) -> List[tuple]:
     # kernel 0: own and shell items in one grid, grid = shell items checked
     # per wave; 4: one wave per unit; 6, 7 and odd: persistent (grid = workgroups)
+    if degree >= 5:
+        return [(0, 0)]  # one kernel (a workgroup per cell) at p = 5, 6
     if curved:
         out = [(0, spw) for spw in (0, 1, 4, 8)] + [(2, 0), (7, 0)]
         assert all(k in CURVED_KERNELS for k, _ in out)

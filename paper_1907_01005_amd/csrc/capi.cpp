@@ -559,12 +559,17 @@ static void fill_apply_params(const mfb_mesh* mesh, const mfb_mv* mv, const doub
   const int n = m.n;
   for (int i = 0; i < n * n; ++i) {
     a.S[i] = b.S[i];
-    a.Dco[i] = b.Dco[i];
     a.Sf[i] = (float)b.S[i];
-    a.Df[i] = (float)b.Dco[i];
-    a.Dw[i] = b.wq[i / n] * b.Dco[i];
-    a.Dwf[i] = (float)a.Dw[i];
   }
+  if (n <= 5) {
+    for (int i = 0; i < n * n; ++i) {
+      a.Dco[i] = b.Dco[i];
+      a.Df[i] = (float)b.Dco[i];
+      a.Dw[i] = b.wq[i / n] * b.Dco[i];
+      a.Dwf[i] = (float)a.Dw[i];
+    }
+  }
+  for (int i = 0; i < n; ++i) a.wq[i] = b.wq[i];
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) {
       double k1 = 0.0;
@@ -573,9 +578,11 @@ static void fill_apply_params(const mfb_mesh* mesh, const mfb_mv* mv, const doub
       a.K1f[i * n + j] = (float)k1;
     }
   const double det = m.h[0] * m.h[1] * m.h[2];
-  for (int d = 0; d < 3; ++d)
-    for (int q = 0; q < n * n; ++q)
-      a.gline[d][q] = 0.5 * det / (m.h[d] * m.h[d]) * b.wq[q % n] * b.wq[q / n];
+  for (int d = 0; d < 3; ++d) {
+    a.gfac[d] = 0.5 * det / (m.h[d] * m.h[d]);
+    if (n <= 5)
+      for (int q = 0; q < n * n; ++q) a.gline[d][q] = a.gfac[d] * b.wq[q % n] * b.wq[q / n];
+  }
 }
 
 // The same BCSR pattern: one handle, or layouts created like one another.

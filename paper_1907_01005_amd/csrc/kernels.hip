@@ -2609,6 +2609,151 @@ hipError_t launch_apply_t(const ApplyParams& p, int kernel, hipStream_t st) {
   return hipGetLastError();
 }
 
+// -------------------------------------------------------------- high degree
+// p = 5 and 6, where a batch's transpose tile alone (64 cell-columns of
+// (p+1)^3 values) passes the LDS of a CU and a thread's plane of (p+1)^2
+// values passes its registers.  One workgroup per (item, cell): the cell's
+// 8 columns of (p+1)^3 values sit in LDS, and thread (column c, line l)
+// contracts one line of its column per pass (in place: within a pass every
+// line belongs to one thread), a barrier between passes.  The operator is
+// the one of the box kernels (eq. fe_matrices, Sec. 3.2): interpolate to the
+// Gauss points along x, y, z; W = JxW V (.) U (the mass operator: JxW); the
+// gradient term along each direction through the 1D stiffness
+// K1 = D^T diag(w) D scaled per line (R22); integrate back along z, y, x.  The
+// cell's results are added into Y node by node with fp64 atomics (nodes
+// shared with neighbour cells take one atomic per cell).
+template <int P>
+struct LineDims {
+  static constexpr int n = P + 1, n2 = n * n, n3 = n2 * n;
+  static constexpr int NB = 2 * P + 1, NB3 = NB * NB * NB;
+  static constexpr int NL = 8 * n2;                 // (column, line) threads
+  static constexpr int NT = ((NL + 63) / 64) * 64;
+};
+
+// One pass along AXIS over line l of column block A (n^3 values): the line's
+// values v_m become sum_m M(o, m) v_m (M(m, o) when TR), scaled by sc.
+template <typename R, int n, int AXIS, bool TR>
+__device__ __forceinline__ void line_pass(R* __restrict__ A, const R* __restrict__ M, int l,
+                                          R* __restrict__ Wacc, double sc) {
+  constexpr int n2 = n * n;
+  const int base = AXIS == 0 ? l * n : (AXIS == 1 ? (l % n) + (l / n) * n2 : l);
+  constexpr int stride = AXIS == 0 ? 1 : (AXIS == 1 ? n : n2);
+  R v[n];
+#pragma unroll
+  for (int m = 0; m < n; ++m) v[m] = A[base + m * stride];
+#pragma unroll
+  for (int o = 0; o < n; ++o) {
+    R acc = 0;
+#pragma unroll
+    for (int m = 0; m < n; ++m) acc = fma_r(TR ? M[m * n + o] : M[o * n + m], v[m], acc);
+    if (Wacc)  // gradient term: added, scaled, into the other block
+      Wacc[base + o * stride] = (R)((double)Wacc[base + o * stride] + (double)acc * sc);
+    else
+      A[base + o * stride] = acc;
+  }
+}
+
+template <typename R, int P, int OP, bool DEST>
+__global__ __launch_bounds__(LineDims<P>::NT) void apply_line_kernel(ApplyParams a) {
+  using D = LineDims<P>;
+  constexpr int n = D::n, n2 = D::n2, n3 = D::n3, NB = D::NB, NB3 = D::NB3;
+  __shared__ R U[8 * n3];
+  __shared__ R W[8 * n3];
+  __shared__ double cvs[n3];
+  __shared__ int32_t ros[n3];
+  const int t = threadIdx.x;
+  const int64_t idx = (int64_t)(blockIdx.x >> 3);  // own items, then shell items
+  const int e = (int)(blockIdx.x & 7);
+  const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
+  const int nc = a.items[idx].nc, rank = a.items[idx].rank;
+  const int32_t* __restrict__ ro = a.rowoff + idx * NB3;
+  auto node = [&](int q) {
+    const int i = q % n, j = (q / n) % n, k = q / n2;
+    return (ex * P + i) + NB * ((ey * P + j) + NB * (ez * P + k));
+  };
+  for (int q = t; q < n3; q += D::NT) {
+    ros[q] = ro[node(q)];
+    cvs[q] = OP == 0 ? a.cV[((int64_t)rank * 8 + e) * n3 + q] : a.jxw[q];
+  }
+  __syncthreads();
+  // gather: consecutive threads take consecutive columns of one node
+  bool any = false;
+  for (int z = t; z < 8 * n3; z += D::NT) {
+    const int c = z & 7, q = z >> 3;
+    const int32_t r = ros[q];
+    const double x = (r >= 0 && c < nc) ? a.X[(int64_t)r + c] : 0.0;
+    U[c * n3 + q] = (R)x;
+    any |= x != 0.0;
+  }
+  if (!__syncthreads_or(any)) return;
+  const bool act = t < D::NL;
+  const int c = act ? t / n2 : 0, l = act ? t % n2 : 0;
+  R* __restrict__ Uc = U + c * n3;
+  R* __restrict__ Wc = W + c * n3;
+  const R* __restrict__ Sm = tab_S<R>(a);
+  const R* __restrict__ K = tab_K<R>(a);
+  if (act) line_pass<R, n, 0, false>(Uc, Sm, l, nullptr, 0.0);
+  __syncthreads();
+  if (act) line_pass<R, n, 1, false>(Uc, Sm, l, nullptr, 0.0);
+  __syncthreads();
+  if (act) line_pass<R, n, 2, false>(Uc, Sm, l, nullptr, 0.0);
+  __syncthreads();
+  for (int z = t; z < 8 * n3; z += D::NT) {
+    const int q = z % n3;
+    W[z] = (R)(cvs[q] * (double)U[z]);
+  }
+  if constexpr (OP == 0) {
+    __syncthreads();
+    const double wa = a.wq[l % n], wb = a.wq[l / n];
+    if (act) line_pass<R, n, 0, false>(Uc, K, l, Wc, a.gfac[0] * wa * wb);
+    __syncthreads();
+    if (act) line_pass<R, n, 1, false>(Uc, K, l, Wc, a.gfac[1] * wa * wb);
+    __syncthreads();
+    if (act) line_pass<R, n, 2, false>(Uc, K, l, Wc, a.gfac[2] * wa * wb);
+  }
+  __syncthreads();
+  if (act) line_pass<R, n, 2, true>(Wc, Sm, l, nullptr, 0.0);
+  __syncthreads();
+  if (act) line_pass<R, n, 1, true>(Wc, Sm, l, nullptr, 0.0);
+  __syncthreads();
+  if (act) line_pass<R, n, 0, true>(Wc, Sm, l, nullptr, 0.0);
+  __syncthreads();
+  const int32_t* __restrict__ rd = DEST ? a.rowoff_out + idx * NB3 : nullptr;
+  for (int z = t; z < 8 * n3; z += D::NT) {
+    const int cc = z & 7, q = z >> 3;
+    if (cc >= nc) continue;
+    const int32_t r = DEST ? rd[node(q)] : ros[q];
+    if (r >= 0) unsafeAtomicAdd(a.Y + (int64_t)r + cc, (double)W[cc * n3 + q]);
+  }
+}
+
+template <typename R, int P>
+hipError_t launch_line(const ApplyParams& p, int op, hipStream_t st) {
+  const int64_t n = (p.nitems + p.nshell) * 8;
+  if (n == 0) return hipSuccess;
+  if (n > int64_t(0x7fffffff)) return hipErrorInvalidValue;
+  const bool dest = p.rowoff_out != p.rowoff;
+  const dim3 g((unsigned)n), b(LineDims<P>::NT);
+  if (op == 0 && !dest) hipLaunchKernelGGL((apply_line_kernel<R, P, 0, false>), g, b, 0, st, p);
+  else if (op == 0) hipLaunchKernelGGL((apply_line_kernel<R, P, 0, true>), g, b, 0, st, p);
+  else if (!dest) hipLaunchKernelGGL((apply_line_kernel<R, P, 1, false>), g, b, 0, st, p);
+  else hipLaunchKernelGGL((apply_line_kernel<R, P, 1, true>), g, b, 0, st, p);
+  return hipGetLastError();
+}
+
+// p = 5, 6: the vector forms (fp64 and fp32) on box cells only.
+int launch_high_degree(const ApplyParams& p, int degree, int prec, int op, hipStream_t st) {
+  if (p.cG || (prec != 0 && prec != 3)) return -2;
+  hipError_t e;
+  if (degree == 5)
+    e = prec == 0 ? launch_line<double, 5>(p, op, st) : launch_line<float, 5>(p, op, st);
+  else if (degree == 6)
+    e = prec == 0 ? launch_line<double, 6>(p, op, st) : launch_line<float, 6>(p, op, st);
+  else
+    return -2;
+  return (int)e;
+}
+
 // -------------------------------------------------------------- energy
 // E = tr((2 I - Mbar) Hbar) = 2 tr Hbar - sum_ab Mbar_ab Hbar_ba (eq. energy).
 // Stage 1: one workgroup per 32x32 tile (a, b) sums Mbar_ab Hbar_ba, the tile
@@ -2839,21 +2984,21 @@ int launch_update(const UpdateParams& p, void* stream) {
   return (int)hipGetLastError();
 }
 
-// Eight independent chains per thread keep the fp64 pipes busy without a
+// Sixteen independent chains per thread keep the fp64 pipes busy without a
 // dependency stall; the chains converge to c / (1 - m) = -1e-3 and never
 // reach the sentinel, so the store never happens but the arithmetic stays.
 __global__ __launch_bounds__(256) void probe_fma_kernel(double* out, int32_t iters) {
-  double a[8];
+  double a[16];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) a[k] = 1e-3 * (double)(threadIdx.x + 1) + 1e-6 * k;
+  for (int k = 0; k < 16; ++k) a[k] = 1e-3 * (double)(threadIdx.x + 1) + 1e-6 * k;
   const double m = 0.999999, c = -1e-9;
   for (int i = 0; i < iters; ++i) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) a[k] = __builtin_fma(a[k], m, c);
+    for (int k = 0; k < 16; ++k) a[k] = __builtin_fma(a[k], m, c);
   }
   double s = 0.0;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) s += a[k];
+  for (int k = 0; k < 16; ++k) s += a[k];
   if (s == 12345.678) out[0] = s;
 }
 
@@ -2875,16 +3020,19 @@ int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t
                  void* stream) {
   hipStream_t st = (hipStream_t)stream;
   // refuse before anything is enqueued, so that a refused call leaves Y as it was
-  if (degree < 1 || degree > 4 || prec < 0 || prec > 3 || kernel < -1 || kernel > 8) return -2;
+  if (degree < 1 || degree > 6 || prec < 0 || prec > 3 || kernel < -1 || kernel > 8) return -2;
+  // p = 5, 6: one kernel (the library's choice or kernel 0), vector forms, box cells
+  if (degree >= 5 && (kernel > 0 || p.cG || (prec != 0 && prec != 3))) return -2;
   if (p.cG && kernel != -1 && kernel != 0 && kernel != 2 && kernel != 7) return -2;
   if (kernel == 8 && !reg_kernel_supported(degree, prec, p.cG != nullptr)) return -2;
   {
     const int64_t blocks = std::min<int64_t>(4096, std::max<int64_t>(1, (nvalues / 2 + 255) / 256));
     hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p.Y, nvalues,
-                       (kernel & 1) ? p.counters : nullptr);
+                       (kernel > 0 && (kernel & 1)) ? p.counters : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
   }
+  if (degree >= 5) return launch_high_degree(p, degree, prec, 0, st);
   // one instantiation per degree and precision form
   auto by_degree = [&](auto form) -> hipError_t {
     switch (degree) {
@@ -2912,7 +3060,8 @@ int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t
 int launch_apply_op(const ApplyParams& p, int degree, int prec, int op, int64_t nvalues,
                     void* stream) {
   hipStream_t st = (hipStream_t)stream;
-  if (degree < 1 || degree > 4 || prec < 0 || prec > 3 || op < 0 || op > 1) return -2;
+  if (degree < 1 || degree > 6 || prec < 0 || prec > 3 || op < 0 || op > 1) return -2;
+  if (degree >= 5 && (p.cG || (prec != 0 && prec != 3))) return -2;
   {
     const int64_t blocks = std::min<int64_t>(4096, std::max<int64_t>(1, (nvalues / 2 + 255) / 256));
     hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p.Y, nvalues,
@@ -2920,6 +3069,7 @@ int launch_apply_op(const ApplyParams& p, int degree, int prec, int op, int64_t 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
   }
+  if (degree >= 5) return launch_high_degree(p, degree, prec, op, st);
   // p = 2: the loader-wave pipeline (about 5% faster on closure destinations;
   // launch_ws runs the fused grid at other degrees); the fp32 VALU form: the
   // fused grid

@@ -25,9 +25,10 @@ struct ApplyParams {
   int32_t* counters;     // 8 queue counters (persistent kernel only)
   int32_t grid;          // persistent workgroups, or shell items per wave (fused grid)
   int32_t pad;
-  double S[25];          // S[q*n + k] = phi_k(xq_q)
-  double Dco[25];        // collocation derivative on the Gauss points
-  float Sf[25];          // float copies of S and Dco for the float contractions
+  // 1D tables, n = p + 1 <= 7 (the kernels of p <= 4 read the first n^2)
+  double S[49];          // S[q*n + k] = phi_k(xq_q)
+  double Dco[25];        // collocation derivative on the Gauss points (p <= 4)
+  float Sf[49];          // float copies of S and Dco for the float contractions
   float Df[25];
   const double* Wg;      // [3][ (p+1)^3 ]: 1/2 JxW_q / h_d^2 per direction d
   const double* jxw;     // [ (p+1)^3 ]: JxW_q (mass operator)
@@ -46,8 +47,11 @@ struct ApplyParams {
   double gline[3][25];
   // the 1D stiffness K1 = D^T diag(w) D on the Gauss points (symmetric, and
   // unchanged under (o, k) -> (n-1-o, n-1-k))
-  double K1[25];
-  float K1f[25];
+  double K1[49];
+  float K1f[49];
+  // the line scales as factors (p >= 5): gline[d][a + n b] = gfac[d] wq[a] wq[b]
+  double wq[8];
+  double gfac[3];        // 1/2 hx hy hz / h_d^2
   int64_t nvalues_x;     // stored values of X (the extent of d_X)
 };
 
@@ -142,7 +146,7 @@ int launch_scale_columns(const BlockView& v, const double* scale, double* X, voi
 constexpr int kDotPartials = 1024;
 int launch_dot(int64_t n, const double* X, const double* Y, double* out, double* work, void* stream);
 int device_cu_count();
-// fp64 fused multiply-add rate probe: blocks x 256 threads, 8 chains of
+// fp64 fused multiply-add rate probe: blocks x 256 threads, 16 chains of
 // iters FMAs each; out written only on an impossible value.
 int launch_probe_fma(double* out, int64_t blocks, int32_t iters, void* stream);
 

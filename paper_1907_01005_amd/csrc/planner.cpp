@@ -156,7 +156,7 @@ void plan_mesh(MeshPlan& m, const int nc[3], const double L[3], int degree, unsi
       throw Error(-1, "cell counts must be positive and even (2x2x2 batches)");
     if (!(L[d] > 0.0) || !std::isfinite(L[d])) throw Error(-1, "box lengths must be positive");
   }
-  if (degree < 1 || degree > kMaxDeg) throw Error(-2, "only degrees 1 to 4 are implemented");
+  if (degree < 1 || degree > kMaxDeg) throw Error(-2, "only degrees 1 to 6 are implemented");
   if (order != 0 && order != 1) throw Error(-1, "order must be 0 (Hilbert) or 1 (lexicographic)");
   if (dirichlet > 0x3F) throw Error(-1, "dirichlet_faces has bits beyond the 6 faces");
   m.p = degree;

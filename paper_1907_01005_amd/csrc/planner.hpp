@@ -36,7 +36,7 @@ uint64_t hilbert3(uint32_t x, uint32_t y, uint32_t z, int bits);
 int bits_for(int extent);
 
 // ---------------------------------------------------------------- mesh
-constexpr int kMaxDeg = 4;
+constexpr int kMaxDeg = 6;
 
 struct MeshPlan {
   int nc[3] = {0, 0, 0};   // cells per axis

@@ -34,7 +34,7 @@ def test_mesh_errors():
         Mesh(3, 4, 4, (1, 1, 1), 2)
     assert e.value.code == N.MFB_EINVAL
     with pytest.raises(MfbError) as e:
-        Mesh(4, 4, 4, (1, 1, 1), 5)
+        Mesh(4, 4, 4, (1, 1, 1), 7)
     assert e.value.code == N.MFB_EUNSUPPORTED
     with pytest.raises(MfbError) as e:
         Mesh(4, 4, 4, (1, 1, 1), 0)

@@ -183,3 +183,36 @@ def test_dense_closure_energy():
     dp.enable_closure()
     assert dp.closure.info["tm_tasks"] > 0
     _check(wl, op, dp, 0, TOL64)
+
+
+@pytest.mark.parametrize("degree", [5, 6])
+def test_high_degree_closure_and_mass(degree):
+    """p = 5, 6: H X and M X onto the closure, Hbar, Mbar and E, and M X, H X
+    on X's own pattern, in the fp64 and fp32 vector forms against the oracle."""
+    import torch
+    from paper_1907_01005_amd import OP_H, OP_M, apply_op
+    ms = synth.MeshSpec(4, 4, 2, (4.0, 3.5, 2.0), degree, 0b100101)
+    wl = synth.custom_workload(ms, 21, 1.6, 40 + degree, potential="wells",
+                               name=f"4x4x2-Q{degree}-M21")
+    wl.colblock_sizes = np.asarray([8, 5, 4, 4], dtype=np.int32)
+    say(f"closure Q{degree}")
+    op = OracleProblem(wl, values="generic", value_seed=9)
+    dp = device_problem(wl)
+    dp.set_X_coo(op.node, op.orb, op.val)
+    _check(wl, op, dp, 0, TOL64)
+    _check(wl, op, dp, 3, TOL32)
+    node, orb = dp.layout.entry_coords()
+    for which, code in (("M", OP_M), ("H", OP_H)):
+        apply_op(dp.mesh, dp.layout, dp.layout, code, dp.X, dp.Y, 0)
+        torch.cuda.synchronize()
+        Yg = dp.Y.cpu().numpy()[:dp.nvalues]
+        Yo = np.zeros(len(node))
+        for C in range(op.pattern.ncb):
+            orbs = op.block_orbitals(C)
+            Y = op.Y_columns(orbs, which, "x")
+            col = {int(a): j for j, a in enumerate(orbs)}
+            sel = np.isin(orb, orbs)
+            Yo[sel] = Y[node[sel], [col[int(a)] for a in orb[sel]]]
+        e = rel_fro(Yg, Yo)
+        say(f"{which}X on x pattern Q{degree}: rel {e:.2e}")
+        assert e <= TOL64

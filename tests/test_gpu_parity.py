@@ -336,3 +336,33 @@ def test_dense_runs_of_row_blocks():
     eS = rel_fro(dp.S_original_order(), So)
     say(f"dense runs: X^T Z rel {eS:.2e}")
     assert eS <= TOL64
+
+
+@pytest.mark.parametrize("degree", [5, 6])
+def test_high_degree(degree):
+    """p = 5, 6 (one workgroup per cell, a thread per line): generic values at
+    every stored entry with ragged column blocks, and orbital values with
+    shell items, in the fp64 and fp32 vector forms against the oracle: all of
+    Y, S and the trace.  The matrix-core forms, the other kernels and curved
+    cells are refused at these degrees."""
+    from paper_1907_01005_amd import MfbError
+    import paper_1907_01005_amd._native as N
+    wl = _small((4, 4, 2), degree, 21, 1.6, 40 + degree, sizes=[8, 5, 4, 4], dirichlet=0b100101)
+    say(f"high degree Q{degree}")
+    for values in ("generic", "orbitals"):
+        op = OracleProblem(wl, values=values, value_seed=7) if values == "generic" else OracleProblem(wl)
+        dp = device_problem(wl)
+        dp.set_X_coo(op.node, op.orb, op.val)
+        node, orb = dp.layout.entry_coords()
+        ref = oracle_full(op, node, orb)
+        _check_full(wl, op, dp, 0, TOL64, ref=ref)
+        _check_full(wl, op, dp, 3, TOL32, ref=ref)
+        _check_full(wl, op, dp, 0, TOL64, tuned=0, ref=ref)
+    for prec in (1, 2):
+        with pytest.raises(MfbError) as e:
+            dp.apply(prec)
+        assert e.value.code == N.MFB_EUNSUPPORTED
+    for kernel in (1, 2, 7, 8):
+        with pytest.raises(MfbError) as e:
+            dp.apply_tuned(0, kernel=kernel)
+        assert e.value.code == N.MFB_EUNSUPPORTED

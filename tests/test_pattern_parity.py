@@ -246,3 +246,16 @@ def test_statistics_at_the_paper_density():
     st = Layout(m, wl.centres, wl.radius, wl.colblock_sizes).stats()
     assert 15.0 < st["rows_std"] < 21.0
     assert 9.5 <= st["colblocks_per_cell_mean"] <= 12.0
+
+
+@pytest.mark.parametrize("degree", [5, 6])
+def test_high_degree_patterns_and_nodes(degree):
+    """p = 5, 6: the library's pattern equals the oracle's bit for bit, and
+    the node positions (GLL points inside each cell) agree."""
+    ms = synth.MeshSpec(4, 4, 2, (4.0, 3.5, 2.0), degree, 0b100101)
+    wl = synth.custom_workload(ms, 21, 1.6, 40 + degree, B=5, uneven=True)
+    m, lay, op = _both(wl)
+    _assert_same(lay, op)
+    om = BoxMesh(ms.nx, ms.ny, ms.nz, tuple(ms.L), ms.degree, ms.dirichlet)
+    assert np.abs(m.node_points() - om.node_points()).max() <= 1e-14 * max(ms.L)
+    assert lay.info["apply_items"] > 0
