@@ -457,6 +457,24 @@ def time_graph(dp, prec: int, steps: int, kernel: int = 0) -> float:
     return time.perf_counter() - t0
 
 
+def time_overlapped(dp, prec: int, steps: int) -> float:
+    """Wall seconds of `steps` steps as one hipGraph in the double-buffered
+    form (autotune.OverlappedLoop: the zero fill of the next destination on a
+    second stream while the current step's apply and overlap run), replayed
+    once after one warm replay."""
+    import torch
+    from paper_1907_01005_amd.autotune import OverlappedLoop
+    loop = OverlappedLoop(dp, prec, n=steps)
+    loop.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loop.replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    del loop
+    return wall
+
+
 def time_in_graph(one, n: int = 100, reps: int = 3) -> float:
     """Mean duration of one call of `one` (an apply_H launch: zero fill + apply
     kernel; or a tmmult: its stage kernels) when n calls run back to back in
@@ -554,6 +572,7 @@ def measure(wl, dp, prec_name: str, steps: int, warmup: int, kernel: int, copy_g
     alg = algorithmic(dp, degree)
     wall, t_apply, t_tm = time_path(dp, prec, steps, warmup, kernel)
     wall_g = time_graph(dp, prec, steps, kernel)
+    wall_o = time_overlapped(dp, prec, steps) if kernel == 0 else None
     t_eager = float(np.mean(t_apply))
     if kernel == 0:
         t_ap = time_in_graph(lambda: dp.apply(prec), min(steps, 100))
@@ -597,6 +616,10 @@ def measure(wl, dp, prec_name: str, steps: int, warmup: int, kernel: int, copy_g
         "value": alg["E"] * steps / wall_g / 1e9,
         "ms_per_step": wall_g / steps * 1e3,
         "eager": {"value": alg["E"] * steps / wall / 1e9, "ms_per_step": wall / steps * 1e3},
+        "overlapped_fill": None if wall_o is None else {
+            "value": alg["E"] * steps / wall_o / 1e9, "ms_per_step": wall_o / steps * 1e3,
+            "form": "the same K steps as one hipGraph with two destinations: each step's zero fill "
+                    "runs on a second stream one step ahead (mfb_mv_zero, then mfb_apply_H_acc)"},
         "apply_ms_p50": float(np.percentile(t_apply, 50) * 1e3),
         "apply_ms_p99": float(np.percentile(t_apply, 99) * 1e3),
         "apply_gdofcols_s": alg["E"] / t_ap / 1e9,

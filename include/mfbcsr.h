@@ -303,6 +303,19 @@ void mfb_destroy_mv(mfb_mv* mv);
 int mfb_apply_H(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X, double* d_Y,
                 int prec, void* stream);
 
+/* Y += mask_P(H X): Alg. 6 without its first step (the zero fill), the same
+ * kernels otherwise.  With Y zeroed beforehand (mfb_mv_zero) the result is
+ * that of mfb_apply_H; the split lets a caller zero the next destination
+ * while the current one is in use (two destinations, two streams), so the
+ * fill leaves the apply's critical path.  Same arguments and errors as
+ * mfb_apply_H; every check happens before anything is enqueued.             */
+int mfb_apply_H_acc(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X, double* d_Y,
+                    int prec, void* stream);
+
+/* Y <- 0 on the info.nvalues stored entries of mv's layout (the first step
+ * of Alg. 6, as mfb_apply_H runs it).  Errors: EINVAL (null), EHIP.          */
+int mfb_mv_zero(const mfb_mv* mv, double* d_Y, void* stream);
+
 /* Same result through an explicitly configured kernel (used by the
  * autotuner).  kernel: even values launch one work unit per workgroup, odd
  * values launch persistent workgroups that pull units from a queue; kernel/2
@@ -314,9 +327,13 @@ int mfb_apply_H(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X, doubl
  * of C is not stored) in a second kernel.  kernel 6: persistent workgroups
  * of the batch mapping walking a static strided list, with the loads of the
  * next items issued before the current item is computed (no workspace).
- * kernel 7 (p = 2; at p = 4 the same as kernel 0): persistent workgroups of
- * p + 1 compute waves and one loader wave that gathers the next item into a
- * second LDS stage while the current one is computed (no workspace).
+ * kernel 7: at p = 2 persistent workgroups of p + 1 compute waves and one
+ * loader wave that gathers the next item into a second LDS stage while the
+ * current one is computed; at p = 3, 4 on box cells the shared-stage form
+ * (one stage, refilled chunk by chunk during the operator), else the fused
+ * grid (no workspace).  kernel 8 (p <= 2, vector forms, box cells): one wave
+ * per item with each lane's cell tensor in registers.  At p = 5, 6 only
+ * kernel 0 (a workgroup per cell) is available.
  * grid: for kernels 0 and 2, the shell items checked per wave (a power of
  * two up to 64; 0 = 2); for the persistent kernels, the
  * number of workgroups (0 = as many as fit on the device); else unused.  d_work: the workspace (info.work_bytes);

@@ -16,6 +16,7 @@ from .api import (  # noqa: F401
     Layout,
     Mesh,
     apply_H,
+    apply_H_acc,
     apply_H_tuned,
     apply_op,
     energy,
@@ -24,6 +25,7 @@ from .api import (  # noqa: F401
     mv_dot,
     mv_scale_columns,
     mv_update,
+    mv_zero,
     tmmult,
 )
 from ._native import MfbError, lib  # noqa: F401

@@ -94,6 +94,8 @@ SIGNATURES = {
     "mfb_mv_bind": (C.c_int, [VP, VP, VP]),
     "mfb_destroy_mv": (None, [VP]),
     "mfb_apply_H": (C.c_int, [VP, VP, VP, VP, C.c_int, VP]),
+    "mfb_apply_H_acc": (C.c_int, [VP, VP, VP, VP, C.c_int, VP]),
+    "mfb_mv_zero": (C.c_int, [VP, VP, VP]),
     "mfb_apply_H_tuned": (C.c_int, [VP, VP, VP, VP, C.POINTER(Tune), VP, VP]),
     "mfb_tmmult": (C.c_int, [VP, VP, VP, VP, VP, VP, VP]),
     "mfb_tmmult_noalloc": (C.c_int, [VP, VP, VP, VP, VP, VP]),

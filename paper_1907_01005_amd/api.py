@@ -292,6 +292,18 @@ def apply_H(mesh: Mesh, layout: Layout, X, Y, prec: int = FP64, stream=None) -> 
                             int(prec), _stream(stream)))
 
 
+def apply_H_acc(mesh: Mesh, layout: Layout, X, Y, prec: int = FP64, stream=None) -> None:
+    """mfb_apply_H_acc: Y += mask(H X) (no zero fill) on the caller's stream."""
+    n = layout.nvalues
+    check(lib().mfb_apply_H_acc(mesh.handle, layout.handle, _f64(X, "X", n), _f64(Y, "Y", n),
+                                int(prec), _stream(stream)))
+
+
+def mv_zero(layout: Layout, Y, stream=None) -> None:
+    """mfb_mv_zero: Y <- 0 on the layout's stored entries."""
+    check(lib().mfb_mv_zero(layout.handle, _f64(Y, "Y", layout.nvalues), _stream(stream)))
+
+
 def apply_H_tuned(mesh: Mesh, layout: Layout, X, Y, work, prec: int = FP64, kernel: int = 0,
                   grid: int = 0, stream=None) -> None:
     """mfb_apply_H_tuned: the same result through an explicit kernel configuration."""

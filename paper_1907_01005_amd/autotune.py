@@ -186,3 +186,63 @@ class GraphLoop:
 
     def replay(self):
         self.graph.replay()
+
+
+class OverlappedLoop:
+    """`n` steps of apply_H + tmmult captured in one hipGraph with two
+    destinations: step k computes Y[k % 2] = mask(H X) (mfb_apply_H_acc on a
+    destination zeroed beforehand) and S = X^T Y[k % 2] on the capture
+    stream, while a second stream zeroes Y[(k + 1) % 2] for the next step as
+    soon as step k - 1's overlap, the last reader of that buffer, is done.
+    Every step does the work of the plain step (zero fill, apply, overlap);
+    the fill leaves the apply's critical path.  After a replay S, the trace
+    and Y[(n - 1) % 2] (`last_Y`) hold the last step's results.
+    """
+
+    def __init__(self, dp, prec: int, n: int = 20):
+        import torch
+        from .api import apply_H_acc, mv_zero, tmmult
+        self.dp, self.n, self.prec = dp, n, prec
+        self.Ys = [dp.Y, torch.zeros_like(dp.Y)]
+        side = torch.cuda.Stream()
+        cap = torch.cuda.Stream()
+
+        def steps(s0, s1):
+            z = [torch.cuda.Event() for _ in range(n)]
+            done = [torch.cuda.Event() for _ in range(n)]
+            with torch.cuda.stream(s1):
+                mv_zero(dp.layout, self.Ys[0], s1)
+                z[0].record(s1)
+            for k in range(n):
+                cur = self.Ys[k % 2]
+                s0.wait_event(z[k])
+                with torch.cuda.stream(s0):
+                    apply_H_acc(dp.mesh, dp.layout, dp.X, cur, prec, s0)
+                    tmmult(dp.layout, dp.X, cur, dp.S, dp.trace, dp.work, s0)
+                    done[k].record(s0)
+                if k + 1 < n:
+                    if k >= 1:
+                        s1.wait_event(done[k - 1])
+                    with torch.cuda.stream(s1):
+                        mv_zero(dp.layout, self.Ys[(k + 1) % 2], s1)
+                        z[k + 1].record(s1)
+            s0.wait_stream(s1)
+
+        # warm up outside the capture, then capture on `cap` with `side` forked
+        cap.wait_stream(torch.cuda.current_stream())
+        side.wait_stream(cap)
+        steps(cap, side)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph, stream=cap):
+            side.wait_stream(cap)
+            steps(cap, side)
+        torch.cuda.current_stream().wait_stream(cap)
+        torch.cuda.synchronize()
+
+    @property
+    def last_Y(self):
+        return self.Ys[(self.n - 1) % 2]
+
+    def replay(self):
+        self.graph.replay()

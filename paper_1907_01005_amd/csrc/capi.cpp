@@ -599,9 +599,9 @@ static void check_apply_args(const mfb_mesh* mesh, const mfb_mv* mv, const doubl
   if (X == Y) fail(MFB_EINVAL, "X and Y must not alias");
 }
 
-int mfb_apply_H(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X, double* d_Y, int prec,
-                void* stream) {
-  MFB_TRY
+// Alg. 6 with (fill) or without its zero fill.
+static void apply_H_impl(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X, double* d_Y,
+                         int prec, void* stream, bool fill) {
   check_apply_args(mesh, mv, d_X, d_Y);
   if (prec < 0 || prec > 3) fail(MFB_EINVAL, "unknown precision");
   mfb::gpu::ApplyParams a;
@@ -611,9 +611,32 @@ int mfb_apply_H(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X, doubl
   // at p = 3, 4 the shared-stage pipeline on box cells; the fused grid on
   // curved cells.  The fused grid (0) for the fp64-MFMA and fp32 VALU forms.
   const int kernel = (prec == MFB_FP64 || prec == MFB_FP32_MFMA) ? -1 : 0;
-  const int rc =
-      mfb::gpu::launch_apply(a, mesh->plan.p, prec, kernel, mv->plan.block_offset.back(), stream);
+  const int rc = mfb::gpu::launch_apply(a, mesh->plan.p, prec, kernel, mv->plan.block_offset.back(),
+                                        stream, fill);
   if (rc == -2) fail(MFB_EUNSUPPORTED, "precision not implemented by the library");
+  if (rc != 0) fail(MFB_EHIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)rc));
+}
+
+int mfb_apply_H(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X, double* d_Y, int prec,
+                void* stream) {
+  MFB_TRY
+  apply_H_impl(mesh, mv, d_X, d_Y, prec, stream, true);
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_apply_H_acc(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X, double* d_Y,
+                    int prec, void* stream) {
+  MFB_TRY
+  apply_H_impl(mesh, mv, d_X, d_Y, prec, stream, false);
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_mv_zero(const mfb_mv* mv, double* d_Y, void* stream) {
+  MFB_TRY
+  if (!mv || !d_Y) fail(MFB_EINVAL, "null argument");
+  const int rc = mfb::gpu::launch_zero(d_Y, mv->plan.block_offset.back(), stream);
   if (rc != 0) fail(MFB_EHIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)rc));
   return MFB_OK;
   MFB_CATCH

@@ -3016,8 +3016,16 @@ int device_cu_count() {
   return cus;
 }
 
+int launch_zero(double* Y, int64_t n, void* stream) {
+  if (n <= 0) return 0;
+  const int64_t blocks = std::min<int64_t>(4096, std::max<int64_t>(1, (n / 2 + 255) / 256));
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, Y, n,
+                     nullptr);
+  return (int)hipGetLastError();
+}
+
 int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t nvalues,
-                 void* stream) {
+                 void* stream, bool fill) {
   hipStream_t st = (hipStream_t)stream;
   // refuse before anything is enqueued, so that a refused call leaves Y as it was
   if (degree < 1 || degree > 6 || prec < 0 || prec > 3 || kernel < -1 || kernel > 8) return -2;
@@ -3025,10 +3033,11 @@ int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t
   if (degree >= 5 && (kernel > 0 || p.cG || (prec != 0 && prec != 3))) return -2;
   if (p.cG && kernel != -1 && kernel != 0 && kernel != 2 && kernel != 7) return -2;
   if (kernel == 8 && !reg_kernel_supported(degree, prec, p.cG != nullptr)) return -2;
-  {
-    const int64_t blocks = std::min<int64_t>(4096, std::max<int64_t>(1, (nvalues / 2 + 255) / 256));
-    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p.Y, nvalues,
-                       (kernel > 0 && (kernel & 1)) ? p.counters : nullptr);
+  if (fill || (kernel > 0 && (kernel & 1))) {
+    // the queue kernels' counters are reset by the fill's first workgroup
+    const int64_t blocks = fill ? std::min<int64_t>(4096, std::max<int64_t>(1, (nvalues / 2 + 255) / 256)) : 1;
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p.Y,
+                       fill ? nvalues : int64_t(0), (kernel > 0 && (kernel & 1)) ? p.counters : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
   }

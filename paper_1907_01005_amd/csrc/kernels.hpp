@@ -88,7 +88,9 @@ struct TmParams {
 // 7 loader pipeline, 8 register-resident waves.
 // Returns a hipError_t value (0 on success) or -2 for an unsupported variant.
 int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t nvalues,
-                 void* stream);
+                 void* stream, bool fill = true);
+// Y[0 .. n) = 0 with the apply's fill kernel.
+int launch_zero(double* Y, int64_t n, void* stream);
 int launch_tmmult(const TmParams& p, void* stream);
 // Fixed device scratch of the allocation-free overlap: kScratchBytes per GPU;
 // scratch_address gives this device's address (a hipError_t value on failure).

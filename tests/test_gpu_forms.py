@@ -256,3 +256,41 @@ def test_graph_replays_with_overlap_tasks():
         dp.apply(FP64)
         dp.overlap()
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("degree", [2, 4])
+def test_overlapped_loop_matches_oracle(degree):
+    """The double-buffered step loop (zero fill of the next destination on a
+    second stream, mfb_apply_H_acc on the current one) gives the oracle's Y,
+    S and trace on every replay, with eager work in between; and
+    mfb_apply_H_acc on a zeroed Y equals mfb_apply_H."""
+    import torch
+    from paper_1907_01005_amd import FP64, apply_H_acc, mv_zero
+    from paper_1907_01005_amd.autotune import OverlappedLoop
+    wl = _small(degree=degree)
+    say(f"overlapped loop Q{degree}")
+    op = OracleProblem(wl)
+    dp = device_problem(wl)
+    dp.set_X_coo(op.node, op.orb, op.val)
+    node, orb = dp.layout.entry_coords()
+    Yo, So, tro = oracle_full(op, node, orb)
+    dp.apply(FP64)
+    torch.cuda.synchronize()
+    Y_plain = dp.Y.clone()
+    Yacc = torch.full_like(dp.Y, 7.0)
+    mv_zero(dp.layout, Yacc)
+    apply_H_acc(dp.mesh, dp.layout, dp.X, Yacc, FP64)
+    torch.cuda.synchronize()
+    assert (Yacc - Y_plain).abs().max().item() <= 1e-14 * Y_plain.abs().max().item()
+    loop = OverlappedLoop(dp, FP64, n=5)
+    for rep in range(3):
+        loop.replay()
+        torch.cuda.synchronize()
+        Yg = loop.last_Y.cpu().numpy()[:dp.nvalues]
+        gate(Yg, Yo, 1e-12, f"overlapped replay {rep} Y")
+        gate(dp.S_original_order(), So, 1e-12, f"overlapped replay {rep} S")
+        assert abs(float(dp.trace.cpu()[0]) - tro) <= 1e-12 * abs(tro)
+        # eager work between replays (the buffers are shared with it)
+        dp.apply(FP64)
+        dp.overlap()
+        torch.cuda.synchronize()
