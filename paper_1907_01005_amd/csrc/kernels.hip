@@ -162,27 +162,29 @@ struct ValuCtr {
 // contributes A = M(a, k).  Every lane therefore gets M times its own pencil
 // (rows 0..3; a second row group covers rows 4..7 when n = 5), accumulated in
 // fp32 over the n steps k.
-template <int n>
+// K: the lean operator's set [S, S^T, K1] (MAT 0 = S, MAT 2 = the symmetric
+// 1D stiffness K1), else [S, S^T, D, D^T] (MAT 0 = S, MAT 1 = D).
+template <int n, bool K = false>
 struct MfmaCtr {
-  static constexpr int G = (n + 3) / 4;
-  float m[4][G][n];  // [S, S^T, D, D^T][row group][k] = M(4 g + lane % 4, k)
+  static constexpr int G = (n + 3) / 4, NM = K ? 3 : 4;
+  float m[NM][G][n];  // [matrix][row group][k] = M(4 g + lane % 4, k)
   __device__ __forceinline__ void init(const float* __restrict__ S, const float* __restrict__ D) {
     const int r = threadIdx.x & 3;
 #pragma unroll
-    for (int mat = 0; mat < 4; ++mat)
+    for (int mat = 0; mat < NM; ++mat)
 #pragma unroll
       for (int g = 0; g < G; ++g)
 #pragma unroll
         for (int k = 0; k < n; ++k) {
           const float* M = mat < 2 ? S : D;
-          const bool tr = mat & 1;
+          const bool tr = mat == 1 || mat == 3;
           const int row = 4 * g + r;
           m[mat][g][k] = row < n ? (tr ? M[k * n + row] : M[row * n + k]) : 0.f;
         }
   }
   template <int AX, bool TR, int MAT, bool ADD>
   __device__ __forceinline__ void run(const float (&in)[n][n], float (&out)[n][n]) const {
-    constexpr int mi = 2 * MAT + (TR ? 1 : 0);
+    constexpr int mi = MAT == 0 ? (TR ? 1 : 0) : (K ? 2 : 2 + (TR ? 1 : 0));
 #pragma unroll
     for (int line = 0; line < n; ++line)
 #pragma unroll
@@ -230,28 +232,28 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // 4..7 when n = 5).  Only a quarter of each product is used, so this form
 // costs several times the vector form's issue time; it exists to measure
 // the fp64 matrix cores on the same operator.
-template <int n>
+template <int n, bool K = false>
 struct MfmaCtr64 {
-  static constexpr int G = (n + 3) / 4;
-  double m[4][G][n];  // [S, S^T, D, D^T][row group][k]: this lane's entry of A
+  static constexpr int G = (n + 3) / 4, NM = K ? 3 : 4;
+  double m[NM][G][n];  // [matrix][row group][k]: this lane's entry of A
   __device__ __forceinline__ void init(const double* __restrict__ S, const double* __restrict__ D) {
     const int i = threadIdx.x & 15, kk = (threadIdx.x >> 4) & 3;
     const bool on = (i & 3) == kk;
 #pragma unroll
-    for (int mat = 0; mat < 4; ++mat)
+    for (int mat = 0; mat < NM; ++mat)
 #pragma unroll
       for (int g = 0; g < G; ++g)
 #pragma unroll
         for (int k = 0; k < n; ++k) {
           const double* M = mat < 2 ? S : D;
-          const bool tr = mat & 1;
+          const bool tr = mat == 1 || mat == 3;
           const int row = 4 * g + (i >> 2);
           m[mat][g][k] = (on && row < n) ? (tr ? M[k * n + row] : M[row * n + k]) : 0.0;
         }
   }
   template <int AX, bool TR, int MAT, bool ADD>
   __device__ __forceinline__ void run(const double (&in)[n][n], double (&out)[n][n]) const {
-    constexpr int mi = 2 * MAT + (TR ? 1 : 0);
+    constexpr int mi = MAT == 0 ? (TR ? 1 : 0) : (K ? 2 : 2 + (TR ? 1 : 0));
 #pragma unroll
     for (int line = 0; line < n; ++line)
 #pragma unroll
@@ -799,6 +801,101 @@ __device__ __forceinline__ Contractor<R, P, MF> make_ctr(const ApplyParams& a) {
   return c;
 }
 
+// Whether the matrix-core forms take the lean operator: measured faster for
+// fp64 at p = 2 and 4 and for fp32 at p = 4, slower for fp32 at p = 2 (73.7
+// against 65.2 us at box-64x40x40-Q2), where plane_operator stays.
+template <typename R, int P>
+constexpr bool kLeanMfma = !(std::is_same<R, float>::value && P <= 2);
+
+// The matrix-core contractor holding [S, S^T, K1], for the lean operator.
+template <typename R, int P>
+using LeanMfmaCtr = typename std::conditional<std::is_same<R, float>::value, MfmaCtr<P + 1, true>,
+                                              MfmaCtr64<P + 1, true>>::type;
+
+template <typename R, int P>
+__device__ __forceinline__ LeanMfmaCtr<R, P> make_lean_ctr(const ApplyParams& a) {
+  LeanMfmaCtr<R, P> c;
+  if constexpr (std::is_same<R, float>::value)
+    c.init(a.Sf, a.K1f);
+  else
+    c.init(a.S, a.K1);
+  return c;
+}
+
+// plane_operator_lean with the contractions on the matrix cores: the same
+// layouts, barriers and calling convention (u is overwritten), nine 1D
+// contractions (three S, three K1, three S^T) instead of plane_operator's
+// twelve, each gradient term's per-line scale applied in float64.  The
+// contractor cannot work in place, so each step writes the other plane.
+template <typename R, int P, class Ctr, class Hook>
+__device__ __forceinline__ void plane_operator_lean_mf(const Ctr& ctr, const ApplyParams& a,
+                                                       R* __restrict__ Tc, int pl,
+                                                       const double* __restrict__ cv,
+                                                       R (&u)[P + 1][P + 1], R (&out)[P + 1][P + 1],
+                                                       Hook after_first_barrier) {
+  constexpr int n = P + 1, n2 = n * n;
+  R A[n][n], B[n][n];
+  // layout A (z = pl): interpolate along x and y
+  ctr.template c<0, false, 0>(u, A);
+  ctr.template c<1, false, 0>(A, B);
+#pragma unroll
+  for (int j = 0; j < n; ++j)
+#pragma unroll
+    for (int i = 0; i < n; ++i) Tc[i + n * j + n2 * pl] = B[i][j];
+  __syncthreads();
+  after_first_barrier();
+  // layout B (y = pl): along z, then the x and z gradient terms and V
+#pragma unroll
+  for (int k = 0; k < n; ++k)
+#pragma unroll
+    for (int i = 0; i < n; ++i) A[i][k] = Tc[i + n * pl + n2 * k];
+  R uq[n][n], w[n][n];
+  ctr.template c<1, false, 0>(A, uq);
+  ctr.template c<0, false, 2>(uq, A);  // K1 along x: line (pl, k)
+  ctr.template c<1, false, 2>(uq, B);  // K1 along z: line (i, pl)
+#pragma unroll
+  for (int i = 0; i < n; ++i)
+#pragma unroll
+    for (int k = 0; k < n; ++k)
+      w[i][k] = (R)((double)A[i][k] * a.gline[0][pl + n * k] + (double)B[i][k] * a.gline[2][i + n * pl] +
+                    cv[i + n * pl + n2 * k] * (double)uq[i][k]);
+  // written back to the positions this thread read: no barrier before it
+#pragma unroll
+  for (int k = 0; k < n; ++k)
+#pragma unroll
+    for (int i = 0; i < n; ++i) Tc[i + n * pl + n2 * k] = uq[i][k];
+  __syncthreads();
+  // layout A: the y gradient term (line (i, pl))
+#pragma unroll
+  for (int j = 0; j < n; ++j)
+#pragma unroll
+    for (int i = 0; i < n; ++i) A[i][j] = Tc[i + n * j + n2 * pl];
+  ctr.template c<1, false, 2>(A, B);
+#pragma unroll
+  for (int j = 0; j < n; ++j)
+#pragma unroll
+    for (int i = 0; i < n; ++i) Tc[i + n * j + n2 * pl] = (R)((double)B[i][j] * a.gline[1][i + n * pl]);
+  __syncthreads();
+  // layout B: add the y part, integrate back along z
+#pragma unroll
+  for (int k = 0; k < n; ++k)
+#pragma unroll
+    for (int i = 0; i < n; ++i) w[i][k] += Tc[i + n * pl + n2 * k];
+  ctr.template c<1, true, 0>(w, A);
+#pragma unroll
+  for (int k = 0; k < n; ++k)
+#pragma unroll
+    for (int i = 0; i < n; ++i) Tc[i + n * pl + n2 * k] = A[i][k];
+  __syncthreads();
+  // layout A: integrate back along y and x
+#pragma unroll
+  for (int j = 0; j < n; ++j)
+#pragma unroll
+    for (int i = 0; i < n; ++i) A[i][j] = Tc[i + n * j + n2 * pl];
+  ctr.template c<1, true, 0>(A, B);
+  ctr.template c<0, true, 0>(B, out);
+}
+
 template <typename R, int P, bool MF = false, int OP = 0, bool DEST = false, bool GEO = false>
 struct BatchProc {
   using D = Dims<P>;
@@ -889,6 +986,8 @@ struct BatchProc {
       else if constexpr (OP == 0 && !MF)
         plane_operator_lean<R, P>(a, Tc, pl, a.cV + (int64_t)__builtin_amdgcn_readfirstlane(rank) * 8 * D::n3,
                                   u, out, hook, e * D::n3);
+      else if constexpr (OP == 0 && kLeanMfma<R, P>)
+        plane_operator_lean_mf<R, P>(make_lean_ctr<R, P>(a), a, Tc, pl, cv, u, out, hook);
       else if constexpr (OP == 0)
         plane_operator<R, P>(make_ctr<R, P, MF>(a), Tc, pl, cv, wg, true, u, out, hook);
       else if constexpr (GEO)
@@ -1978,6 +2077,9 @@ struct LoaderPipe {
       // previous item's atomics)
       plane_operator_lean<R, P, decltype(zero_sums), false>(a, T + (t & 63) * n3, pl, cur.cv + e * n3,
                                                             u, out, zero_sums);
+    else if constexpr (OP == 0 && kLeanMfma<R, P>)
+      plane_operator_lean_mf<R, P>(make_lean_ctr<R, P>(a), a, T + (t & 63) * n3, pl, cur.cv + e * n3,
+                                   u, out, zero_sums);
     else if constexpr (OP == 0)
       plane_operator<R, P>(make_ctr<R, P, MF>(a), T + (t & 63) * n3, pl, cur.cv + e * n3, wg,
                            true, u, out, zero_sums);
@@ -2229,6 +2331,9 @@ struct SharedPipe {
     if constexpr (!MF) {
       auto none = []() {};
       plane_operator_lean<R, P, decltype(none), false>(a, Tc, pl, sm.cv[slot] + e * n3, u, out, none);
+    } else if constexpr (kLeanMfma<R, P>) {
+      auto none = []() {};
+      plane_operator_lean_mf<R, P>(make_lean_ctr<R, P>(a), a, Tc, pl, sm.cv[slot] + e * n3, u, out, none);
     } else {
       plane_operator<R, P>(make_ctr<R, P, MF>(a), Tc, pl, sm.cv[slot] + e * n3, sm.wg, true, u, out,
                            []() {});
