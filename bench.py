@@ -530,17 +530,22 @@ def cold_times(dp, prec: int, reps: int = 10, scrub_mib: int = 1024):
     return float(np.median(ta)), float(np.median(tt))
 
 
-KERNELS = {0: "default", 1: "queue", 2: "batch-grid", 7: "loader-pipelined", 8: "register-waves"}
+KERNELS = {0: "default", 1: "queue", 2: "batch-grid", 7: "loader-pipelined", 8: "register-waves",
+           9: "line-per-thread"}
 
 
 def default_apply_kernel(dp, degree: int, prec_name: str) -> str:
     """The kernel mfb_apply_H launches after the zero fill on box cells (the
-    library's rule: at p = 2 the fused grid for fp64 below 64 own items per CU,
-    else the loader pipeline; at p = 3, 4 the shared-stage pipeline while X's
+    library's rule: fp32 on the vector ALUs, the fused grid; p = 5, 6 and fp64
+    at p = 3, 4, the line kernel; fp64 at p = 2, the fused grid below 64 own
+    items per CU, else the loader pipeline; the matrix-core forms, the loader
+    pipeline at p = 2 and the shared-stage pipeline at p = 3, 4 while X's
     byte offsets fit 31 bits)."""
     import torch
-    if prec_name in ("fp32", "fp64-mfma"):
+    if prec_name == "fp32":
         return "apply_fused_kernel"
+    if degree >= 5 or (degree >= 3 and prec_name == "fp64"):
+        return "apply_line_kernel"
     if degree == 2:
         cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
         own = dp.layout.info["apply_items_own"]
@@ -598,7 +603,8 @@ def measure(wl, dp, prec_name: str, steps: int, warmup: int, kernel: int, copy_g
                      default_kernel if kernel == 0 else {1: "apply_queue_kernel",
                                                          2: "apply_fused_kernel",
                                                          7: "apply_ws_kernel",
-                                                         8: "apply_reg_kernel"}[kernel]),
+                                                         8: "apply_reg_kernel",
+                                                         9: "apply_line_kernel"}[kernel]),
                  "algorithmic_bytes": alg["bytes"], "algorithmic_flops": alg["flops"],
                  "executed_flops": exe, "executed_frac": exe / t_ap / 1e12 / peak_f,
                  "avg_launch_s": t_ap, "timing": "apply_H launches back to back in one hipGraph, "
@@ -668,7 +674,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--prec", default="fp64", choices=sorted(PRECS))
     ap.add_argument("--config", type=int, default=2, choices=[2, 3])
-    ap.add_argument("--kernel", type=int, default=0, choices=[0, 1, 2, 7, 8],
+    ap.add_argument("--kernel", type=int, default=0, choices=[0, 1, 2, 7, 8, 9],
                     help="0: the library's default apply; otherwise an explicit kernel of "
                          "mfb_apply_H_tuned (1: persistent queue, 2: batch grid, "
                          "7: loader-pipelined, 8: register-resident waves)")

@@ -104,7 +104,7 @@ typedef enum {
  * level of Alg. 1).  degree p in 1..6 (else MFB_EUNSUPPORTED); at p = 5, 6 the
  * applies run the fp64 and fp32 vector forms on box cells (one workgroup
  * per cell), and the matrix-core forms, curved cells and the tuned kernel
- * variants other than 0 give MFB_EUNSUPPORTED.
+ * variants other than 0 and 9 give MFB_EUNSUPPORTED.
  * dirichlet_faces: bit 2d = face x_d = 0, bit 2d+1 = face x_d = L_d.
  * order: 0 = batches along the Hilbert curve (Alg. 1 step 2), 1 = batches
  * in lexicographic order (x fastest).                                      */
@@ -332,8 +332,12 @@ int mfb_mv_zero(const mfb_mv* mv, double* d_Y, void* stream);
  * current one is computed; at p = 3, 4 on box cells the shared-stage form
  * (one stage, refilled chunk by chunk during the operator), else the fused
  * grid (no workspace).  kernel 8 (p <= 2, vector forms, box cells): one wave
- * per item with each lane's cell tensor in registers.  At p = 5, 6 only
- * kernel 0 (a workgroup per cell) is available.
+ * per item with each lane's cell tensor in registers.  kernel 9 (p >= 2,
+ * vector forms, box cells, no workspace): one workgroup per (item, cell), a
+ * thread per (line, column), the operator in five passes over the cell's
+ * 8 columns in LDS; mfb_apply_H's kernel at p = 3, 4 in fp64 and at
+ * p = 5, 6.  At p = 5, 6 only kernels 0 and 9 (both that kernel) are
+ * available.
  * grid: for kernels 0 and 2, the shell items checked per wave (a power of
  * two up to 64; 0 = 2); for the persistent kernels, the
  * number of workgroups (0 = as many as fit on the device); else unused.  d_work: the workspace (info.work_bytes);

@@ -24,7 +24,7 @@ from . import api
 
 KERNEL_NAMES = {0: "default-grid", 1: "default-queue", 2: "batch-grid", 3: "batch-queue",
                 4: "wave-grid", 5: "wave-queue", 6: "batch-pipelined",
-                7: "loader-pipelined", 8: "register-waves"}
+                7: "loader-pipelined", 8: "register-waves", 9: "line-per-cell"}
 
 
 @dataclass(frozen=True)
@@ -35,7 +35,7 @@ class TuneChoice:
     us: float          # median apply time measured by the tuner
 
     def describe(self) -> str:
-        if self.kernel & 1 or self.kernel == 6:
+        if (self.kernel & 1 and self.kernel != 9) or self.kernel == 6:
             g = f", grid {self.grid}"
         elif self.kernel in (0, 2) and self.grid:
             g = f", {self.grid} shell items/wave"
@@ -68,7 +68,8 @@ def reg_kernel_supported(degree: int, prec: int, curved: bool) -> bool:
 def candidates(cu_count: int, curved: bool = False, degree: int = 2,
                prec: int = api.FP64) -> List[tuple]:
     # kernel 0: own and shell items in one grid, grid = shell items checked
-    # per wave; 4: one wave per unit; 6, 7 and odd: persistent (grid = workgroups)
+    # per wave; 4: one wave per unit; 6, 7 and odd: persistent (grid =
+    # workgroups); 9: a workgroup per (item, cell)
     if degree >= 5:
         return [(0, 0)]  # one kernel (a workgroup per cell) at p = 5, 6
     if curved:
@@ -85,6 +86,8 @@ def candidates(cu_count: int, curved: bool = False, degree: int = 2,
             out.append((k, per_cu * cu_count))
     if reg_kernel_supported(degree, prec, curved):
         out.append((8, 0))
+    if degree >= 2 and prec in (api.FP64, api.FP32):
+        out.append((9, 0))  # a workgroup per (item, cell), a thread per line
     return out
 
 

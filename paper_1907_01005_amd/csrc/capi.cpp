@@ -648,7 +648,7 @@ int mfb_apply_H_tuned(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X,
   check_apply_args(mesh, mv, d_X, d_Y);
   if (!tune) fail(MFB_EINVAL, "null tune");
   if (tune->prec < 0 || tune->prec > 3) fail(MFB_EINVAL, "unknown precision");
-  if (tune->kernel < 0 || tune->kernel > 8) fail(MFB_EINVAL, "kernel must be in 0..8");
+  if (tune->kernel < 0 || tune->kernel > 9) fail(MFB_EINVAL, "kernel must be in 0..9");
   if (tune->grid < 0) fail(MFB_EINVAL, "negative grid");
   if ((tune->kernel == 0 || tune->kernel == 2) &&
       (tune->grid > 64 || (tune->grid & (tune->grid - 1)) != 0))
@@ -657,7 +657,9 @@ int mfb_apply_H_tuned(const mfb_mesh* mesh, const mfb_mv* mv, const double* d_X,
     fail(MFB_EUNSUPPORTED, "curved cells run the fused kernels only (0, 2 and 7)");
   if (tune->kernel == 8 && !mfb::gpu::reg_kernel_supported(mesh->plan.p, tune->prec, mesh->plan.curved))
     fail(MFB_EUNSUPPORTED, "kernel 8 takes p <= 2, box cells and the vector-ALU precisions");
-  if ((tune->kernel & 1) && tune->kernel != 7 && !d_work)
+  if (tune->kernel == 9 && (mesh->plan.p < 2 || (tune->prec != MFB_FP64 && tune->prec != MFB_FP32)))
+    fail(MFB_EUNSUPPORTED, "kernel 9 takes p >= 2 and the vector-ALU precisions");
+  if ((tune->kernel & 1) && tune->kernel != 7 && tune->kernel != 9 && !d_work)
     fail(MFB_EINVAL, "the queue kernels need the workspace");
   mfb::gpu::ApplyParams a;
   fill_apply_params(mesh, mv, d_X, d_Y, a);

@@ -2618,6 +2618,10 @@ hipError_t launch_pipe1(const ApplyParams& p, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
+// The line kernel's launch (defined with the kernel below).
+template <typename R, int P>
+hipError_t launch_line(const ApplyParams& p, int op, hipStream_t st);
+
 // Below this many own items per CU the p = 2 Hamiltonian runs on the fused
 // grid rather than the loader pipeline.
 constexpr int kFusedItemsPerCu = 64;
@@ -2626,6 +2630,11 @@ constexpr int kFusedItemsPerCu = 64;
 template <typename R, int P, bool MF, int OP>
 hipError_t launch_ws(const ApplyParams& p, int grid, hipStream_t st, bool pick = true) {
   if constexpr (P != 2) {
+    // the default at p = 3, 4 in fp64 on box cells: the line kernel (at Q4
+    // 46 us against 77 us for the shared-stage pipeline, at Q3 40 against 99
+    // us for apply_H on the 32x20x20 box)
+    if constexpr (P >= 3 && !MF && std::is_same<R, double>::value)
+      if (pick && !p.cG) return launch_line<R, P>(p, OP, st);
     // p >= 3 on box cells with X's own pattern as the destination: the
     // shared-stage loader pipeline; otherwise the fused grid
     if constexpr (P >= 3 && OP == 0)
@@ -2714,143 +2723,270 @@ hipError_t launch_apply_t(const ApplyParams& p, int kernel, hipStream_t st) {
   return hipGetLastError();
 }
 
-// -------------------------------------------------------------- high degree
-// p = 5 and 6, where a batch's transpose tile alone (64 cell-columns of
-// (p+1)^3 values) passes the LDS of a CU and a thread's plane of (p+1)^2
-// values passes its registers.  One workgroup per (item, cell): the cell's
-// 8 columns of (p+1)^3 values sit in LDS, and thread (column c, line l)
-// contracts one line of its column per pass (in place: within a pass every
-// line belongs to one thread), a barrier between passes.  The operator is
-// the one of the box kernels (eq. fe_matrices, Sec. 3.2): interpolate to the
-// Gauss points along x, y, z; W = JxW V (.) U (the mass operator: JxW); the
-// gradient term along each direction through the 1D stiffness
-// K1 = D^T diag(w) D scaled per line (R22); integrate back along z, y, x.  The
-// cell's results are added into Y node by node with fp64 atomics (nodes
-// shared with neighbour cells take one atomic per cell).
+// -------------------------------------------------------------- line kernel
+// One workgroup per (item, cell), at p >= 3 (at p = 5, 6 the only form: a
+// batch's transpose tile of 64 cell-columns of (p+1)^3 values passes the LDS
+// of a CU and a thread's plane of (p+1)^2 values passes its registers).
+// Thread (line l, column c), c fastest, holds one line of its column per
+// pass; the cell's 8 columns of (p+1)^3 values sit in LDS node-major (the 8
+// columns of a node side by side), so that the gather from X and the atomics
+// into Y move 64 contiguous bytes per node.  Within a pass every line of a
+// column belongs to one thread, which writes back only what it read: one
+// barrier per pass.  The operator is the one of the box kernels (eq.
+// fe_matrices, Sec. 3.2) in quadrature space, U = (S x S x S) X:
+//   Y = (S^T x S^T x S^T) [JxW V (.) U + sum_d g_d (K1 along d, w along the
+//       other two directions) U],  K1 = D^T diag(w) D (R22),
+// (the mass operator: JxW (.) U only).  Five passes instead of nine: the
+// last interpolation, the potential, the z gradient and the first
+// integration along z share the z pass; the x gradient and the integration
+// along x the x pass; the y gradient and the last integration the y pass,
+// whose results go from registers into Y.  This works because a contraction
+// along one direction commutes with everything acting on the others: the
+// gradient terms of x and y are formed on U integrated along z (and then
+// along x), after the weights of those directions have been applied (a
+// diagonal scaling does not commute with S^T along its own direction).
+// Nodes shared by neighbour cells take one fp64 atomic per cell.
 template <int P>
 struct LineDims {
   static constexpr int n = P + 1, n2 = n * n, n3 = n2 * n;
   static constexpr int NB = 2 * P + 1, NB3 = NB * NB * NB;
-  static constexpr int NL = 8 * n2;                 // (column, line) threads
+  static constexpr int NL = 8 * n2;                 // (line, column) threads
   static constexpr int NT = ((NL + 63) / 64) * 64;
+  static constexpr int NW = NT / 64;
 };
 
-// One pass along AXIS over line l of column block A (n^3 values): the line's
-// values v_m become sum_m M(o, m) v_m (M(m, o) when TR), scaled by sc.
-template <typename R, int n, int AXIS, bool TR>
-__device__ __forceinline__ void line_pass(R* __restrict__ A, const R* __restrict__ M, int l,
-                                          R* __restrict__ Wacc, double sc) {
-  constexpr int n2 = n * n;
-  const int base = AXIS == 0 ? l * n : (AXIS == 1 ? (l % n) + (l / n) * n2 : l);
-  constexpr int stride = AXIS == 0 ? 1 : (AXIS == 1 ? n : n2);
-  R v[n];
+// o = M v (o = M^T v when TR) for one line, M n x n row-major.
+template <typename R, int n, bool TR>
+__device__ __forceinline__ void line_ctr(const R* __restrict__ M, const R (&v)[n], R (&o)[n]) {
 #pragma unroll
-  for (int m = 0; m < n; ++m) v[m] = A[base + m * stride];
-#pragma unroll
-  for (int o = 0; o < n; ++o) {
+  for (int q = 0; q < n; ++q) {
     R acc = 0;
 #pragma unroll
-    for (int m = 0; m < n; ++m) acc = fma_r(TR ? M[m * n + o] : M[o * n + m], v[m], acc);
-    if (Wacc)  // gradient term: added, scaled, into the other block
-      Wacc[base + o * stride] = (R)((double)Wacc[base + o * stride] + (double)acc * sc);
-    else
-      A[base + o * stride] = acc;
+    for (int m = 0; m < n; ++m) acc = fma_r(TR ? M[m * n + q] : M[q * n + m], v[m], acc);
+    o[q] = acc;
+  }
+}
+
+// One cell e of item idx (all threads of the workgroup call it; U, W: the
+// workgroup's LDS tiles; wqs: the quadrature weights in LDS, written before
+// the call, read after its first barrier).
+template <typename R, int P, int OP, bool DEST>
+__device__ __forceinline__ void line_cell(const ApplyParams& a, int64_t idx, int e, R* __restrict__ U,
+                                          R* __restrict__ W, const double* __restrict__ wqs) {
+  using D = LineDims<P>;
+  constexpr int n = D::n, n2 = D::n2, n3 = D::n3, NB = D::NB, NB3 = D::NB3;
+  const int t = threadIdx.x;
+  const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
+  const bool act = t < D::NL;
+  // line l = la + n lb: the x line (j, k) = (la, lb), the y line (i, k) =
+  // (la, lb), the z line (i, j) = (la, lb)
+  const int c = t & 7, l = act ? (t >> 3) : 0;
+  const int la = l % n, lb = l / n;
+  const int nc = a.items[idx].nc, rank = a.items[idx].rank;
+  // batch nodes of point m: x line bx + m, y line by + NB m; cell node of
+  // point m of the z line: la + n lb + n^2 m
+  const int bx = ex * P + NB * ((ey * P + la) + NB * (ez * P + lb));
+  const int by = (ex * P + la) + NB * (ey * P + NB * (ez * P + lb));
+  const int32_t* __restrict__ rox = a.rowoff + idx * NB3 + bx;
+  const int32_t* __restrict__ roy = (DEST ? a.rowoff_out : a.rowoff) + idx * NB3 + by;
+  const double* __restrict__ cvz =
+      (OP == 0 ? a.cV + ((int64_t)rank * 8 + e) * n3 : a.jxw) + la + n * lb;
+  // LDS element of point m (node-major, column c): x line ux + 8 m, y line
+  // uy + 8 n m, z line uz + 8 n^2 m
+  const int ux = 8 * n * l + c, uy = 8 * (la + n2 * lb) + c, uz = 8 * l + c;
+  // everything the thread reads from memory, issued up front
+  int32_t rx[n], ry[n];
+  double cz[n];
+#pragma unroll
+  for (int m = 0; m < n; ++m) {
+    rx[m] = rox[m];
+    ry[m] = roy[NB * m];
+    cz[m] = cvz[n2 * m];
+  }
+  R v[n], o[n];
+#pragma unroll
+  for (int m = 0; m < n; ++m)
+    v[m] = (R)((act && rx[m] >= 0 && c < nc) ? a.X[(int64_t)rx[m] + c] : 0.0);
+  const R* __restrict__ Sm = tab_S<R>(a);
+  const R* __restrict__ K = tab_K<R>(a);
+  // x pass: interpolate along x
+  line_ctr<R, n, false>(Sm, v, o);
+  if (act)
+#pragma unroll
+    for (int m = 0; m < n; ++m) U[ux + 8 * m] = o[m];
+  __syncthreads();
+  // y pass: interpolate along y
+  if (act) {
+#pragma unroll
+    for (int m = 0; m < n; ++m) v[m] = U[uy + 8 * n * m];
+    line_ctr<R, n, false>(Sm, v, o);
+#pragma unroll
+    for (int m = 0; m < n; ++m) U[uy + 8 * n * m] = o[m];
+  }
+  __syncthreads();
+  // z pass: interpolate along z; W = JxW V (.) u + g_z w_i w_j K1 u, then
+  // integrate W along z; U <- S^T (w (.) u) for the x and y gradients
+  // quadrature weights of the line's two fixed indices
+  const double wl0 = wqs[la], wl1 = wqs[lb];
+  if (act) {
+#pragma unroll
+    for (int m = 0; m < n; ++m) v[m] = U[uz + 8 * n2 * m];
+    R u[n];
+    line_ctr<R, n, false>(Sm, v, u);
+    R w[n];
+    if constexpr (OP == 0) {
+      R ku[n];
+      line_ctr<R, n, false>(K, u, ku);
+      const double gz = a.gfac[2] * wl0 * wl1;
+#pragma unroll
+      for (int m = 0; m < n; ++m) w[m] = (R)(cz[m] * (double)u[m] + gz * (double)ku[m]);
+#pragma unroll
+      for (int m = 0; m < n; ++m) v[m] = (R)(a.wq[m] * (double)u[m]);
+      line_ctr<R, n, true>(Sm, v, o);
+#pragma unroll
+      for (int m = 0; m < n; ++m) U[uz + 8 * n2 * m] = o[m];
+    } else {
+#pragma unroll
+      for (int m = 0; m < n; ++m) w[m] = (R)(cz[m] * (double)u[m]);
+    }
+    line_ctr<R, n, true>(Sm, w, o);
+#pragma unroll
+    for (int m = 0; m < n; ++m) W[uz + 8 * n2 * m] = o[m];
+  }
+  __syncthreads();
+  // x pass: W += g_x w_j K1 U, integrate W along x; U <- S^T (w (.) U)
+  if (act) {
+    R w[n];
+#pragma unroll
+    for (int m = 0; m < n; ++m) w[m] = W[ux + 8 * m];
+    if constexpr (OP == 0) {
+#pragma unroll
+      for (int m = 0; m < n; ++m) v[m] = U[ux + 8 * m];
+      line_ctr<R, n, false>(K, v, o);
+      const double gx = a.gfac[0] * wl0;
+#pragma unroll
+      for (int m = 0; m < n; ++m) w[m] = (R)((double)w[m] + gx * (double)o[m]);
+#pragma unroll
+      for (int m = 0; m < n; ++m) v[m] = (R)(a.wq[m] * (double)v[m]);
+      line_ctr<R, n, true>(Sm, v, o);
+#pragma unroll
+      for (int m = 0; m < n; ++m) U[ux + 8 * m] = o[m];
+    }
+    line_ctr<R, n, true>(Sm, w, o);
+#pragma unroll
+    for (int m = 0; m < n; ++m) W[ux + 8 * m] = o[m];
+  }
+  __syncthreads();
+  // y pass: W += g_y K1 U, integrate W along y, add into Y
+  if (!act || c >= nc) return;
+  {
+    R w[n];
+#pragma unroll
+    for (int m = 0; m < n; ++m) w[m] = W[uy + 8 * n * m];
+    if constexpr (OP == 0) {
+#pragma unroll
+      for (int m = 0; m < n; ++m) v[m] = U[uy + 8 * n * m];
+      line_ctr<R, n, false>(K, v, o);
+      const double gy = a.gfac[1];
+#pragma unroll
+      for (int m = 0; m < n; ++m) w[m] = (R)((double)w[m] + gy * (double)o[m]);
+    }
+    line_ctr<R, n, true>(Sm, w, o);
+    double* __restrict__ y = a.Y + c;
+#pragma unroll
+    for (int m = 0; m < n; ++m)
+      if (ry[m] >= 0) unsafeAtomicAdd(y + ry[m], (double)o[m]);
+  }
+}
+
+// Own items: one workgroup per (item, cell); consecutive workgroups take
+// the cells of one item, so that they run on different XCDs (the atomics of
+// cells sharing nodes then seldom meet in one L2: with the cells of an item
+// on one XCD the kernel is 1.4x slower).
+template <typename R, int P, int OP, bool DEST>
+__global__ __launch_bounds__(LineDims<P>::NT) void apply_line_kernel(ApplyParams a) {
+  using D = LineDims<P>;
+  __shared__ R U[8 * D::n3];  // [node][column]
+  __shared__ R W[8 * D::n3];
+  __shared__ double wqs[D::n];
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int m = 0; m < D::n; ++m) wqs[m] = a.wq[m];
+  line_cell<R, P, OP, DEST>(a, (int64_t)(blockIdx.x >> 3), (int)(blockIdx.x & 7), U, W, wqs);
+}
+
+// Shell items (batches whose own block is not stored): one workgroup per
+// item reads the values the item would gather (the present rows of its
+// neighbours' blocks) and runs its 8 cells only when one of them is
+// non-zero (for orbital-supported inputs none is, and the item ends after
+// the check; a wave per item instead makes the check 2x slower).  A kernel
+// of its own, so that the loop over the cells does not add to the registers
+// of the one above.
+template <typename R, int P, int OP, bool DEST>
+__global__ __launch_bounds__(LineDims<P>::NT) void apply_line_shell_kernel(ApplyParams a) {
+  using D = LineDims<P>;
+  __shared__ R U[8 * D::n3];
+  __shared__ R W[8 * D::n3];
+  __shared__ double wqs[D::n];
+  __shared__ int32_t anyw[D::NW];
+  const int t = threadIdx.x;
+  const int64_t k = blockIdx.x;
+  const int64_t idx = a.nitems + k;
+  const int nc = a.items[idx].nc;
+  bool any = false;
+  const int64_t q1 = (int64_t)a.shell_ptr[k + 1] * 8;
+  for (int64_t q = (int64_t)a.shell_ptr[k] * 8 + t; q < q1; q += D::NT) {
+    const int c = (int)(q & 7);
+    if (c < nc) any |= a.X[(int64_t)a.shell_ro[q >> 3] + c] != 0.0;
+  }
+  {
+    const bool wany = __ballot(any) != 0;
+    if ((t & 63) == 0) anyw[t >> 6] = wany;
+  }
+  if (t == 0)
+#pragma unroll
+    for (int m = 0; m < D::n; ++m) wqs[m] = a.wq[m];
+  __syncthreads();
+  int32_t f = 0;
+#pragma unroll
+  for (int w = 0; w < D::NW; ++w) f |= anyw[w];
+  if (!f) return;
+#pragma unroll 1
+  for (int e = 0; e < 8; ++e) {
+    line_cell<R, P, OP, DEST>(a, idx, e, U, W, wqs);
+    __syncthreads();  // the next cell overwrites U and W
   }
 }
 
 template <typename R, int P, int OP, bool DEST>
-__global__ __launch_bounds__(LineDims<P>::NT) void apply_line_kernel(ApplyParams a) {
-  using D = LineDims<P>;
-  constexpr int n = D::n, n2 = D::n2, n3 = D::n3, NB = D::NB, NB3 = D::NB3;
-  __shared__ R U[8 * n3];
-  __shared__ R W[8 * n3];
-  __shared__ double cvs[n3];
-  __shared__ int32_t ros[n3];
-  const int t = threadIdx.x;
-  const int64_t idx = (int64_t)(blockIdx.x >> 3);  // own items, then shell items
-  const int e = (int)(blockIdx.x & 7);
-  const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
-  const int nc = a.items[idx].nc, rank = a.items[idx].rank;
-  const int32_t* __restrict__ ro = a.rowoff + idx * NB3;
-  auto node = [&](int q) {
-    const int i = q % n, j = (q / n) % n, k = q / n2;
-    return (ex * P + i) + NB * ((ey * P + j) + NB * (ez * P + k));
-  };
-  for (int q = t; q < n3; q += D::NT) {
-    ros[q] = ro[node(q)];
-    cvs[q] = OP == 0 ? a.cV[((int64_t)rank * 8 + e) * n3 + q] : a.jxw[q];
-  }
-  __syncthreads();
-  // gather: consecutive threads take consecutive columns of one node
-  bool any = false;
-  for (int z = t; z < 8 * n3; z += D::NT) {
-    const int c = z & 7, q = z >> 3;
-    const int32_t r = ros[q];
-    const double x = (r >= 0 && c < nc) ? a.X[(int64_t)r + c] : 0.0;
-    U[c * n3 + q] = (R)x;
-    any |= x != 0.0;
-  }
-  if (!__syncthreads_or(any)) return;
-  const bool act = t < D::NL;
-  const int c = act ? t / n2 : 0, l = act ? t % n2 : 0;
-  R* __restrict__ Uc = U + c * n3;
-  R* __restrict__ Wc = W + c * n3;
-  const R* __restrict__ Sm = tab_S<R>(a);
-  const R* __restrict__ K = tab_K<R>(a);
-  if (act) line_pass<R, n, 0, false>(Uc, Sm, l, nullptr, 0.0);
-  __syncthreads();
-  if (act) line_pass<R, n, 1, false>(Uc, Sm, l, nullptr, 0.0);
-  __syncthreads();
-  if (act) line_pass<R, n, 2, false>(Uc, Sm, l, nullptr, 0.0);
-  __syncthreads();
-  for (int z = t; z < 8 * n3; z += D::NT) {
-    const int q = z % n3;
-    W[z] = (R)(cvs[q] * (double)U[z]);
-  }
-  if constexpr (OP == 0) {
-    __syncthreads();
-    const double wa = a.wq[l % n], wb = a.wq[l / n];
-    if (act) line_pass<R, n, 0, false>(Uc, K, l, Wc, a.gfac[0] * wa * wb);
-    __syncthreads();
-    if (act) line_pass<R, n, 1, false>(Uc, K, l, Wc, a.gfac[1] * wa * wb);
-    __syncthreads();
-    if (act) line_pass<R, n, 2, false>(Uc, K, l, Wc, a.gfac[2] * wa * wb);
-  }
-  __syncthreads();
-  if (act) line_pass<R, n, 2, true>(Wc, Sm, l, nullptr, 0.0);
-  __syncthreads();
-  if (act) line_pass<R, n, 1, true>(Wc, Sm, l, nullptr, 0.0);
-  __syncthreads();
-  if (act) line_pass<R, n, 0, true>(Wc, Sm, l, nullptr, 0.0);
-  __syncthreads();
-  const int32_t* __restrict__ rd = DEST ? a.rowoff_out + idx * NB3 : nullptr;
-  for (int z = t; z < 8 * n3; z += D::NT) {
-    const int cc = z & 7, q = z >> 3;
-    if (cc >= nc) continue;
-    const int32_t r = DEST ? rd[node(q)] : ros[q];
-    if (r >= 0) unsafeAtomicAdd(a.Y + (int64_t)r + cc, (double)W[cc * n3 + q]);
-  }
+hipError_t launch_line_op(const ApplyParams& p, hipStream_t st) {
+  const dim3 b(LineDims<P>::NT);
+  if (p.nitems > 0)
+    hipLaunchKernelGGL((apply_line_kernel<R, P, OP, DEST>), dim3((unsigned)(p.nitems * 8)), b, 0, st, p);
+  if (p.nshell > 0)
+    hipLaunchKernelGGL((apply_line_shell_kernel<R, P, OP, DEST>), dim3((unsigned)p.nshell), b, 0, st, p);
+  return hipGetLastError();
 }
 
 template <typename R, int P>
 hipError_t launch_line(const ApplyParams& p, int op, hipStream_t st) {
-  const int64_t n = (p.nitems + p.nshell) * 8;
-  if (n == 0) return hipSuccess;
-  if (n > int64_t(0x7fffffff)) return hipErrorInvalidValue;
+  if (p.nitems * 8 > int64_t(0x7fffffff) || p.nshell > int64_t(0x7fffffff)) return hipErrorInvalidValue;
   const bool dest = p.rowoff_out != p.rowoff;
-  const dim3 g((unsigned)n), b(LineDims<P>::NT);
-  if (op == 0 && !dest) hipLaunchKernelGGL((apply_line_kernel<R, P, 0, false>), g, b, 0, st, p);
-  else if (op == 0) hipLaunchKernelGGL((apply_line_kernel<R, P, 0, true>), g, b, 0, st, p);
-  else if (!dest) hipLaunchKernelGGL((apply_line_kernel<R, P, 1, false>), g, b, 0, st, p);
-  else hipLaunchKernelGGL((apply_line_kernel<R, P, 1, true>), g, b, 0, st, p);
-  return hipGetLastError();
+  if (op == 0) return dest ? launch_line_op<R, P, 0, true>(p, st) : launch_line_op<R, P, 0, false>(p, st);
+  return dest ? launch_line_op<R, P, 1, true>(p, st) : launch_line_op<R, P, 1, false>(p, st);
 }
 
 // p = 5, 6: the vector forms (fp64 and fp32) on box cells only.
 int launch_high_degree(const ApplyParams& p, int degree, int prec, int op, hipStream_t st) {
   if (p.cG || (prec != 0 && prec != 3)) return -2;
   hipError_t e;
-  if (degree == 5)
+  if (degree == 2)
+    e = prec == 0 ? launch_line<double, 2>(p, op, st) : launch_line<float, 2>(p, op, st);
+  else if (degree == 3)
+    e = prec == 0 ? launch_line<double, 3>(p, op, st) : launch_line<float, 3>(p, op, st);
+  else if (degree == 4)
+    e = prec == 0 ? launch_line<double, 4>(p, op, st) : launch_line<float, 4>(p, op, st);
+  else if (degree == 5)
     e = prec == 0 ? launch_line<double, 5>(p, op, st) : launch_line<float, 5>(p, op, st);
   else if (degree == 6)
     e = prec == 0 ? launch_line<double, 6>(p, op, st) : launch_line<float, 6>(p, op, st);
@@ -3133,20 +3269,22 @@ int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t
                  void* stream, bool fill) {
   hipStream_t st = (hipStream_t)stream;
   // refuse before anything is enqueued, so that a refused call leaves Y as it was
-  if (degree < 1 || degree > 6 || prec < 0 || prec > 3 || kernel < -1 || kernel > 8) return -2;
-  // p = 5, 6: one kernel (the library's choice or kernel 0), vector forms, box cells
-  if (degree >= 5 && (kernel > 0 || p.cG || (prec != 0 && prec != 3))) return -2;
+  if (degree < 1 || degree > 6 || prec < 0 || prec > 3 || kernel < -1 || kernel > 9) return -2;
+  if (kernel == 9 && (degree < 2 || p.cG || (prec != 0 && prec != 3))) return -2;
+  // p = 5, 6: one kernel (the library's choice, kernel 0 or 9), vector forms, box cells
+  if (degree >= 5 && ((kernel > 0 && kernel != 9) || p.cG || (prec != 0 && prec != 3))) return -2;
   if (p.cG && kernel != -1 && kernel != 0 && kernel != 2 && kernel != 7) return -2;
   if (kernel == 8 && !reg_kernel_supported(degree, prec, p.cG != nullptr)) return -2;
-  if (fill || (kernel > 0 && (kernel & 1))) {
+  const bool queue = kernel == 1 || kernel == 3 || kernel == 5 || kernel == 7;
+  if (fill || queue) {
     // the queue kernels' counters are reset by the fill's first workgroup
     const int64_t blocks = fill ? std::min<int64_t>(4096, std::max<int64_t>(1, (nvalues / 2 + 255) / 256)) : 1;
     hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p.Y,
-                       fill ? nvalues : int64_t(0), (kernel > 0 && (kernel & 1)) ? p.counters : nullptr);
+                       fill ? nvalues : int64_t(0), queue ? p.counters : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
   }
-  if (degree >= 5) return launch_high_degree(p, degree, prec, 0, st);
+  if (degree >= 5 || kernel == 9) return launch_high_degree(p, degree, prec, 0, st);
   // one instantiation per degree and precision form
   auto by_degree = [&](auto form) -> hipError_t {
     switch (degree) {

@@ -83,12 +83,12 @@ def test_refused_calls_leave_buffers_untouched():
                                 st) == N.MFB_EINVAL
         assert lib.mfb_apply_op(dp.mesh.handle, dp.layout.handle, dp.layout.handle, 0, X, Y, 7,
                                 st) == N.MFB_EINVAL
-        for kernel, grid in ((9, 0), (-1, 0), (0, 3), (0, 128)):
+        for kernel, grid in ((10, 0), (-1, 0), (0, 3), (0, 128)):
             with pytest.raises(MfbError) as e:
                 apply_H_tuned(dp.mesh, dp.layout, dp.X, dp.Y, dp.work, FP64, kernel, grid)
             assert e.value.code == N.MFB_EINVAL
         if bend:
-            for kernel in (1, 3, 4, 5, 6, 8):
+            for kernel in (1, 3, 4, 5, 6, 8, 9):
                 with pytest.raises(MfbError) as e:
                     apply_H_tuned(dp.mesh, dp.layout, dp.X, dp.Y, dp.work, FP64, kernel, 0)
                 assert e.value.code == N.MFB_EUNSUPPORTED

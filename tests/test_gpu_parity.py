@@ -96,6 +96,9 @@ def test_generic_values_ragged_blocks(degree):
         _check_full(wl, op, dp, 0, TOL64, tuned=kernel, ref=ref)
         _check_full(wl, op, dp, 1, TOL64, tuned=kernel, ref=ref)
         _check_full(wl, op, dp, 2, TOL32, tuned=kernel, ref=ref)
+    if degree >= 2:   # the line kernel (a workgroup per cell): vector-ALU forms
+        _check_full(wl, op, dp, 0, TOL64, tuned=9, ref=ref)
+        _check_full(wl, op, dp, 3, TOL32, tuned=9, ref=ref)
     if degree <= 2:   # register-resident waves: vector-ALU forms at p <= 2
         _check_full(wl, op, dp, 0, TOL64, tuned=8, ref=ref)
         _check_full(wl, op, dp, 3, TOL32, tuned=8, ref=ref)
@@ -135,6 +138,8 @@ def test_few_nonzero_shell_items(degree):
         _check_full(wl, op, dp, 0, TOL64, tuned=(0, spw))
     _check_full(wl, op, dp, 2, TOL32, tuned=(0, 4))
     _check_full(wl, op, dp, 0, TOL64, tuned=1)
+    if degree >= 2:
+        _check_full(wl, op, dp, 0, TOL64, tuned=9)
     if degree <= 2:
         _check_full(wl, op, dp, 0, TOL64, tuned=8)
 
@@ -358,6 +363,7 @@ def test_high_degree(degree):
         _check_full(wl, op, dp, 0, TOL64, ref=ref)
         _check_full(wl, op, dp, 3, TOL32, ref=ref)
         _check_full(wl, op, dp, 0, TOL64, tuned=0, ref=ref)
+        _check_full(wl, op, dp, 3, TOL32, tuned=9, ref=ref)
     for prec in (1, 2):
         with pytest.raises(MfbError) as e:
             dp.apply(prec)
