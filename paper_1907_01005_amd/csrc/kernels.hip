@@ -2899,37 +2899,32 @@ __device__ __forceinline__ void line_cell(const ApplyParams& a, int64_t idx, int
   }
 }
 
-// Own items: one workgroup per (item, cell); consecutive workgroups take
-// the cells of one item, so that they run on different XCDs (the atomics of
-// cells sharing nodes then seldom meet in one L2: with the cells of an item
-// on one XCD the kernel is 1.4x slower).
+// One grid: first the shell items (batches whose own block is not stored),
+// one workgroup per item, which reads the values the item would gather (the
+// present rows of its neighbours' blocks) and runs its 8 cells only when one
+// of them is non-zero (for orbital-supported inputs none is, and the item
+// ends after the check; a wave per item instead makes the check 2x slower);
+// they come first so that their loads overlap the own items' arithmetic.
+// Then the own items, one workgroup per (item, cell); consecutive workgroups
+// take the cells of one item, so that they run on different XCDs (the
+// atomics of cells sharing nodes then seldom meet in one L2: with the cells
+// of an item on one XCD the kernel is 1.4x slower).
 template <typename R, int P, int OP, bool DEST>
 __global__ __launch_bounds__(LineDims<P>::NT) void apply_line_kernel(ApplyParams a) {
   using D = LineDims<P>;
   __shared__ R U[8 * D::n3];  // [node][column]
   __shared__ R W[8 * D::n3];
   __shared__ double wqs[D::n];
-  if (threadIdx.x == 0)
-#pragma unroll
-    for (int m = 0; m < D::n; ++m) wqs[m] = a.wq[m];
-  line_cell<R, P, OP, DEST>(a, (int64_t)(blockIdx.x >> 3), (int)(blockIdx.x & 7), U, W, wqs);
-}
-
-// Shell items (batches whose own block is not stored): one workgroup per
-// item reads the values the item would gather (the present rows of its
-// neighbours' blocks) and runs its 8 cells only when one of them is
-// non-zero (for orbital-supported inputs none is, and the item ends after
-// the check; a wave per item instead makes the check 2x slower).  A kernel
-// of its own, so that the loop over the cells does not add to the registers
-// of the one above.
-template <typename R, int P, int OP, bool DEST>
-__global__ __launch_bounds__(LineDims<P>::NT) void apply_line_shell_kernel(ApplyParams a) {
-  using D = LineDims<P>;
-  __shared__ R U[8 * D::n3];
-  __shared__ R W[8 * D::n3];
-  __shared__ double wqs[D::n];
   __shared__ int32_t anyw[D::NW];
   const int t = threadIdx.x;
+  if (t == 0)
+#pragma unroll
+    for (int m = 0; m < D::n; ++m) wqs[m] = a.wq[m];
+  if ((int64_t)blockIdx.x >= a.nshell) {
+    const int64_t b = (int64_t)blockIdx.x - a.nshell;
+    line_cell<R, P, OP, DEST>(a, b >> 3, (int)(b & 7), U, W, wqs);
+    return;
+  }
   const int64_t k = blockIdx.x;
   const int64_t idx = a.nitems + k;
   const int nc = a.items[idx].nc;
@@ -2943,9 +2938,6 @@ __global__ __launch_bounds__(LineDims<P>::NT) void apply_line_shell_kernel(Apply
     const bool wany = __ballot(any) != 0;
     if ((t & 63) == 0) anyw[t >> 6] = wany;
   }
-  if (t == 0)
-#pragma unroll
-    for (int m = 0; m < D::n; ++m) wqs[m] = a.wq[m];
   __syncthreads();
   int32_t f = 0;
 #pragma unroll
@@ -2960,17 +2952,15 @@ __global__ __launch_bounds__(LineDims<P>::NT) void apply_line_shell_kernel(Apply
 
 template <typename R, int P, int OP, bool DEST>
 hipError_t launch_line_op(const ApplyParams& p, hipStream_t st) {
-  const dim3 b(LineDims<P>::NT);
-  if (p.nitems > 0)
-    hipLaunchKernelGGL((apply_line_kernel<R, P, OP, DEST>), dim3((unsigned)(p.nitems * 8)), b, 0, st, p);
-  if (p.nshell > 0)
-    hipLaunchKernelGGL((apply_line_shell_kernel<R, P, OP, DEST>), dim3((unsigned)p.nshell), b, 0, st, p);
+  const int64_t n = p.nshell + p.nitems * 8;
+  if (n == 0) return hipSuccess;
+  if (n > int64_t(0x7fffffff)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((apply_line_kernel<R, P, OP, DEST>), dim3((unsigned)n), dim3(LineDims<P>::NT), 0, st, p);
   return hipGetLastError();
 }
 
 template <typename R, int P>
 hipError_t launch_line(const ApplyParams& p, int op, hipStream_t st) {
-  if (p.nitems * 8 > int64_t(0x7fffffff) || p.nshell > int64_t(0x7fffffff)) return hipErrorInvalidValue;
   const bool dest = p.rowoff_out != p.rowoff;
   if (op == 0) return dest ? launch_line_op<R, P, 0, true>(p, st) : launch_line_op<R, P, 0, false>(p, st);
   return dest ? launch_line_op<R, P, 1, true>(p, st) : launch_line_op<R, P, 1, false>(p, st);
