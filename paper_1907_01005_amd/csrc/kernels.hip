@@ -2908,9 +2908,12 @@ __device__ __forceinline__ void line_cell(const ApplyParams& a, int64_t idx, int
 // Then the own items, one workgroup per (item, cell); consecutive workgroups
 // take the cells of one item, so that they run on different XCDs (the
 // atomics of cells sharing nodes then seldom meet in one L2: with the cells
-// of an item on one XCD the kernel is 1.4x slower).
+// of an item on one XCD the kernel is 1.4x slower).  At p <= 4 the compiler is
+// held to 8 waves per SIMD (2048 threads per CU): the shell path's registers
+// would otherwise leave 7, and the spilled scalar registers cost less than the
+// lost wave (Q4: 52.6 against 55.3 us for apply_H).
 template <typename R, int P, int OP, bool DEST>
-__global__ __launch_bounds__(LineDims<P>::NT) void apply_line_kernel(ApplyParams a) {
+__global__ __launch_bounds__(LineDims<P>::NT, P <= 4 ? 2048 / LineDims<P>::NT : 1) void apply_line_kernel(ApplyParams a) {
   using D = LineDims<P>;
   __shared__ R U[8 * D::n3];  // [node][column]
   __shared__ R W[8 * D::n3];
