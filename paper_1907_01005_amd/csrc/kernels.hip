@@ -3420,7 +3420,10 @@ int launch_tmmult(const TmParams& p, void* stream) {
     const int64_t nwg = (((n + 3) / 4 + 7) / 8) * 8;
     hipLaunchKernelGGL(kernel, dim3((unsigned)nwg), dim3(256), 0, st, p, lo, n);
   };
-  launch4(tm_unit8_kernel<16, true, 1>, 0);
+  // 8x8 blocks: 8 steps of 8 rows in flight per wave (a p = 2 row block has at
+  // most 64 rows; longer blocks loop), so that a wave issues no loads past the
+  // end of its blocks (16 steps: 22.8 against 21.4 us for tmmult at Q2)
+  launch4(tm_unit8_kernel<8, true, 1>, 0);
   {  // longer products: four waves each
     const int64_t lo = ce[0], n = ce[1] - ce[0];
     if (n > 0)
