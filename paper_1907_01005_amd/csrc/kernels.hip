@@ -3424,10 +3424,11 @@ int launch_tmmult(const TmParams& p, void* stream) {
   // most 64 rows; longer blocks loop), so that a wave issues no loads past the
   // end of its blocks (16 steps: 22.8 against 21.4 us for tmmult at Q2)
   launch4(tm_unit8_kernel<8, true, 1>, 0);
-  {  // longer products: four waves each
+  {  // longer products: four waves each, 4 row steps in flight per wave (8 and
+     // 16 steps: 19.7 and 22.8 against 19.2 us for tmmult at Q4)
     const int64_t lo = ce[0], n = ce[1] - ce[0];
     if (n > 0)
-      hipLaunchKernelGGL((tm_unit8_kernel<8, false, 4>), dim3((unsigned)(((n + 7) / 8) * 8)), dim3(256),
+      hipLaunchKernelGGL((tm_unit8_kernel<4, false, 4>), dim3((unsigned)(((n + 7) / 8) * 8)), dim3(256),
                          0, st, p, lo, n);
   }
   launch(tm_stage1_mfma_kernel<1, 2>, 2, 64);
