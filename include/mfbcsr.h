@@ -335,8 +335,8 @@ int mfb_mv_zero(const mfb_mv* mv, double* d_Y, void* stream);
  * per item with each lane's cell tensor in registers.  kernel 9 (p >= 2,
  * vector forms, box cells, no workspace): one workgroup per (item, cell), a
  * thread per (line, column), the operator in five passes over the cell's
- * 8 columns in LDS; mfb_apply_H's kernel at p = 3, 4 in fp64 and at
- * p = 5, 6.  At p = 5, 6 only kernels 0 and 9 (both that kernel) are
+ * 8 columns in LDS; mfb_apply_H's kernel at p = 3, 4 in the vector forms
+ * (fp64 and fp32) and at p = 5, 6.  At p = 5, 6 only kernels 0 and 9 (both that kernel) are
  * available.
  * grid: for kernels 0 and 2, the shell items checked per wave (a power of
  * two up to 64; 0 = 2); for the persistent kernels, the
