@@ -428,6 +428,22 @@ int mfb_mv_dot(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d
 int mfb_tmmult(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d_S,
                double* d_trace, void* d_work, void* stream);
 
+/* mfb_tmmult with an explicit shape of its block-product kernels (used by the
+ * autotuner, a search over the same computation, Alg. 8): unit_steps and
+ * long_steps are the row steps of 8 rows each wave keeps in flight in the
+ * products of two 8-wide blocks and in the other products at most 8 wide
+ * (4, 8 or 16; 0 = the library's choice, 8 and 4).  The result equals
+ * mfb_tmmult's to rounding (the rows are dealt to the waves of a product
+ * differently) and is bitwise reproducible for a given shape.  Errors: EINVAL
+ * (another step count, null argument, misaligned d_work), ESTATE, EHIP.      */
+typedef struct {
+  int32_t unit_steps;
+  int32_t long_steps;
+  int32_t reserved[2];
+} mfb_tm_tune;
+int mfb_tmmult_tuned(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d_S,
+                     double* d_trace, void* d_work, const mfb_tm_tune* tune, void* stream);
+
 /* mfb_tmmult without a workspace argument and without any allocation, for
  * callers that cannot allocate device memory: code under HIP graph capture,
  * serving loops that must not call hipMalloc, harnesses that forbid it.  The

@@ -27,5 +27,6 @@ from .api import (  # noqa: F401
     mv_update,
     mv_zero,
     tmmult,
+    tmmult_tuned,
 )
 from ._native import MfbError, lib  # noqa: F401

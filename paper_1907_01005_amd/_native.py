@@ -65,6 +65,11 @@ class Tune(C.Structure):
                 ("reserved", C.c_int32)]
 
 
+class TmTune(C.Structure):
+    _fields_ = [("unit_steps", C.c_int32), ("long_steps", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
+
+
 VP = C.c_void_p
 PI64 = C.POINTER(C.c_int64)
 PI32 = C.POINTER(C.c_int32)
@@ -98,6 +103,7 @@ SIGNATURES = {
     "mfb_mv_zero": (C.c_int, [VP, VP, VP]),
     "mfb_apply_H_tuned": (C.c_int, [VP, VP, VP, VP, C.POINTER(Tune), VP, VP]),
     "mfb_tmmult": (C.c_int, [VP, VP, VP, VP, VP, VP, VP]),
+    "mfb_tmmult_tuned": (C.c_int, [VP, VP, VP, VP, VP, VP, C.POINTER(TmTune), VP]),
     "mfb_tmmult_noalloc": (C.c_int, [VP, VP, VP, VP, VP, VP]),
     "mfb_mv_update": (C.c_int, [VP, VP, VP, VP, VP, C.c_double, VP]),
     "mfb_probe_fp64_fma": (C.c_int, [VP, C.c_int64, C.c_int32, VP]),

@@ -323,6 +323,17 @@ def tmmult(layout: Layout, X, Y, S, trace, work, stream=None) -> None:
                            _dev(work, "work", layout.work_bytes), _stream(stream)))
 
 
+def tmmult_tuned(layout: Layout, X, Y, S, trace, work, unit_steps: int = 0, long_steps: int = 0,
+                 stream=None) -> None:
+    """mfb_tmmult_tuned: the same S and trace with chosen row steps per wave."""
+    nx = layout.source.nvalues if layout.source is not None else layout.nvalues
+    M = layout.M
+    t = N.TmTune(int(unit_steps), int(long_steps))
+    check(lib().mfb_tmmult_tuned(layout.handle, _f64(X, "X", nx), _f64(Y, "Y", layout.nvalues),
+                                 _f64(S, "S", M * M), _f64(trace, "trace", 1),
+                                 _dev(work, "work", layout.work_bytes), C.byref(t), _stream(stream)))
+
+
 def mv_update(layout: Layout, X, Y, S, S2, tau: float, stream=None) -> None:
     """mfb_mv_update: X <- X - tau (Y - X diag(S)/diag(S2)) on the stored entries."""
     n, M = layout.nvalues, layout.M

@@ -33,6 +33,9 @@ class TuneChoice:
     kernel: int
     grid: int          # persistent workgroups (0 = device-filling default)
     us: float          # median apply time measured by the tuner
+    tm_unit_steps: int = 0   # overlap: row steps per wave of the 8x8 block products (0 = default)
+    tm_long_steps: int = 0   # overlap: row steps per wave of the other products (0 = default)
+    tm_us: float = 0.0       # median overlap time measured by the tuner
 
     def describe(self) -> str:
         if (self.kernel & 1 and self.kernel != 9) or self.kernel == 6:
@@ -41,7 +44,11 @@ class TuneChoice:
             g = f", {self.grid} shell items/wave"
         else:
             g = ""
-        return f"{KERNEL_NAMES[self.kernel]}{g} ({api.PREC_NAMES[self.prec]}): {self.us:.1f} us"
+        out = f"{KERNEL_NAMES[self.kernel]}{g} ({api.PREC_NAMES[self.prec]}): {self.us:.1f} us"
+        if self.tm_us:
+            out += (f"; overlap {self.tm_unit_steps or 'default'}/{self.tm_long_steps or 'default'}"
+                    f" row steps: {self.tm_us:.1f} us")
+        return out
 
 
 _CACHE: Dict[str, TuneChoice] = {}
@@ -106,6 +113,49 @@ def _time_apply(dp, prec: int, kernel: int, grid: int, iters: int, warmup: int) 
     return statistics.median(a.elapsed_time(b) for a, b in evs) * 1e3
 
 
+# Overlap shapes: row steps of 8 rows in flight per wave for the 8x8 block
+# products and for the other products up to 8 wide (0 = the library's choice).
+TM_STEPS = (4, 8, 16)
+
+
+def _time_overlap(dp, unit_steps: int, long_steps: int, iters: int, warmup: int) -> float:
+    import torch
+    for _ in range(warmup):
+        dp.overlap_tuned(unit_steps, long_steps)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(iters)]
+    for a, b in evs:
+        a.record()
+        dp.overlap_tuned(unit_steps, long_steps)
+        b.record()
+    torch.cuda.synchronize()
+    return statistics.median(a.elapsed_time(b) for a, b in evs) * 1e3
+
+
+def tune_overlap(dp, iters: int = 20, warmup: int = 3, verbose: bool = False):
+    """Time the overlap's block-product shapes on this layout (Y as it stands)
+    and return (unit_steps, long_steps, us) of the fastest whose S agrees with
+    the default overlap's to 1e-12 relative."""
+    import torch
+    dp.overlap()
+    torch.cuda.synchronize()
+    ref = dp.S.clone()
+    scale = max(ref.abs().max().item(), 1e-300)
+    best = None
+    for u in TM_STEPS:
+        for lng in TM_STEPS:
+            us = _time_overlap(dp, u, lng, iters, warmup)
+            dev = (dp.S - ref).abs().max().item() / scale
+            if verbose:
+                print(f"[tune] overlap steps {u}/{lng}: {us:.1f} us, max dev {dev:.1e}", flush=True)
+            if dev <= 1e-12 and (best is None or us < best[2]):
+                best = (u, lng, us)
+    dp.overlap()
+    assert best is not None
+    return best
+
+
 def tune(dp, prec: int, iters: int = 20, warmup: int = 3, cache_file: Optional[str] = None,
          verbose: bool = False) -> TuneChoice:
     """Time every kernel variant that takes this mesh on this layout and return
@@ -142,8 +192,12 @@ def tune(dp, prec: int, iters: int = 20, warmup: int = 3, cache_file: Optional[s
             continue
         if best is None or us < best.us:
             best = TuneChoice(prec, kernel, grid, us)
-    dp.Y.copy_(Y_saved)
     assert best is not None
+    # the overlap's shape, on the Y of the chosen apply
+    dp.apply_tuned(prec, kernel=best.kernel, grid=best.grid)
+    u, lng, tm_us = tune_overlap(dp, iters, warmup, verbose)
+    best = TuneChoice(prec, best.kernel, best.grid, best.us, u, lng, tm_us)
+    dp.Y.copy_(Y_saved)
     _CACHE[key] = best
     if cache_file:
         try:
@@ -185,7 +239,7 @@ class GraphLoop:
     def _body(self):
         c = self.choice
         self.dp.apply_tuned(c.prec, kernel=c.kernel, grid=c.grid)
-        self.dp.overlap()
+        self.dp.overlap_tuned(c.tm_unit_steps, c.tm_long_steps)
 
     def replay(self):
         self.graph.replay()

@@ -814,7 +814,8 @@ int mfb_mv_dot(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d
 }
 
 static void tmmult_enqueue(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d_S,
-                           double* d_trace, void* d_work, void* stream) {
+                           double* d_trace, void* d_work, void* stream, int unit_steps = 0,
+                           int long_steps = 0) {
   const auto& p = mv->plan;
   const char* mb = (const char*)mv->d_meta;
   mfb::gpu::TmParams t;
@@ -845,7 +846,7 @@ static void tmmult_enqueue(const mfb_mv* mv, const double* d_X, const double* d_
 
   t.S = d_S;
   t.trace = d_trace;
-  const int rc = mfb::gpu::launch_tmmult(t, stream);
+  const int rc = mfb::gpu::launch_tmmult(t, stream, unit_steps, long_steps);
   if (rc != 0) fail(MFB_EHIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)rc));
 }
 
@@ -856,6 +857,20 @@ int mfb_tmmult(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d
   if (!mv->bound) fail(MFB_ESTATE, "layout metadata not bound");
   if (((uintptr_t)d_work & 255) != 0) fail(MFB_EINVAL, "d_work must be 256-byte aligned");
   tmmult_enqueue(mv, d_X, d_Y, d_S, d_trace, d_work, stream);
+  return MFB_OK;
+  MFB_CATCH
+}
+
+int mfb_tmmult_tuned(const mfb_mv* mv, const double* d_X, const double* d_Y, double* d_S,
+                     double* d_trace, void* d_work, const mfb_tm_tune* tune, void* stream) {
+  MFB_TRY
+  if (!mv || !d_X || !d_Y || !d_S || !d_trace || !d_work || !tune) fail(MFB_EINVAL, "null argument");
+  auto steps_ok = [](int32_t s) { return s == 0 || s == 4 || s == 8 || s == 16; };
+  if (!steps_ok(tune->unit_steps) || !steps_ok(tune->long_steps))
+    fail(MFB_EINVAL, "row steps must be 0, 4, 8 or 16");
+  if (!mv->bound) fail(MFB_ESTATE, "layout metadata not bound");
+  if (((uintptr_t)d_work & 255) != 0) fail(MFB_EINVAL, "d_work must be 256-byte aligned");
+  tmmult_enqueue(mv, d_X, d_Y, d_S, d_trace, d_work, stream, tune->unit_steps, tune->long_steps);
   return MFB_OK;
   MFB_CATCH
 }

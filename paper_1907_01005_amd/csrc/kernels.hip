@@ -3403,7 +3403,7 @@ int launch_energy(int M, const double* Mbar, const double* Hbar, double* E, doub
   return (int)hipGetLastError();
 }
 
-int launch_tmmult(const TmParams& p, void* stream) {
+int launch_tmmult(const TmParams& p, void* stream, int unit_steps, int long_steps) {
   hipStream_t st = (hipStream_t)stream;
   // units in XCD-contiguous ranges (xcd_item): the products of one row block
   // run on one XCD, close in time, and share its L2 for the X and Y blocks
@@ -3420,16 +3420,22 @@ int launch_tmmult(const TmParams& p, void* stream) {
     const int64_t nwg = (((n + 3) / 4 + 7) / 8) * 8;
     hipLaunchKernelGGL(kernel, dim3((unsigned)nwg), dim3(256), 0, st, p, lo, n);
   };
-  // 8x8 blocks: 8 steps of 8 rows in flight per wave (a p = 2 row block has at
-  // most 64 rows; longer blocks loop), so that a wave issues no loads past the
-  // end of its blocks (16 steps: 22.8 against 21.4 us for tmmult at Q2)
-  launch4(tm_unit8_kernel<8, true, 1>, 0);
-  {  // longer products: four waves each, 4 row steps in flight per wave (8 and
-     // 16 steps: 19.7 and 22.8 against 19.2 us for tmmult at Q4)
+  // 8x8 blocks: by default 8 steps of 8 rows in flight per wave (a p = 2 row
+  // block has at most 64 rows; longer blocks loop), so that a wave issues no
+  // loads past the end of its blocks (16 steps: 22.8 against 21.4 us for
+  // tmmult at Q2)
+  if (unit_steps == 4) launch4(tm_unit8_kernel<4, true, 1>, 0);
+  else if (unit_steps == 16) launch4(tm_unit8_kernel<16, true, 1>, 0);
+  else launch4(tm_unit8_kernel<8, true, 1>, 0);
+  {  // longer products: four waves each, by default 4 row steps in flight per
+     // wave (8 and 16 steps: 19.7 and 22.8 against 19.2 us for tmmult at Q4)
     const int64_t lo = ce[0], n = ce[1] - ce[0];
-    if (n > 0)
-      hipLaunchKernelGGL((tm_unit8_kernel<4, false, 4>), dim3((unsigned)(((n + 7) / 8) * 8)), dim3(256),
-                         0, st, p, lo, n);
+    const dim3 g((unsigned)(((n + 7) / 8) * 8)), b(256);
+    if (n > 0) {
+      if (long_steps == 8) hipLaunchKernelGGL((tm_unit8_kernel<8, false, 4>), g, b, 0, st, p, lo, n);
+      else if (long_steps == 16) hipLaunchKernelGGL((tm_unit8_kernel<16, false, 4>), g, b, 0, st, p, lo, n);
+      else hipLaunchKernelGGL((tm_unit8_kernel<4, false, 4>), g, b, 0, st, p, lo, n);
+    }
   }
   launch(tm_stage1_mfma_kernel<1, 2>, 2, 64);
   launch(tm_stage1_mfma_kernel<4, 2>, 3, 256);

@@ -91,7 +91,9 @@ int launch_apply(const ApplyParams& p, int degree, int prec, int kernel, int64_t
                  void* stream, bool fill = true);
 // Y[0 .. n) = 0 with the apply's fill kernel.
 int launch_zero(double* Y, int64_t n, void* stream);
-int launch_tmmult(const TmParams& p, void* stream);
+// unit_steps, long_steps: row steps of 8 rows in flight per wave in the two
+// block-product classes (4, 8 or 16; 0 = the defaults, 8 and 4).
+int launch_tmmult(const TmParams& p, void* stream, int unit_steps = 0, int long_steps = 0);
 // Fixed device scratch of the allocation-free overlap: kScratchBytes per GPU;
 // scratch_address gives this device's address (a hipError_t value on failure).
 constexpr size_t kScratchBytes = size_t(64) << 20;

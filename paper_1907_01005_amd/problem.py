@@ -12,7 +12,8 @@ from typing import Callable, Optional, Sequence
 import numpy as np
 
 from .api import (DOT_WORK_DOUBLES, FP64, OP_H, OP_M, Layout, Mesh, apply_H, apply_H_tuned,
-                  apply_op, energy, energy_work_bytes, mmult, mv_axpy, mv_dot, mv_update, tmmult)
+                  apply_op, energy, energy_work_bytes, mmult, mv_axpy, mv_dot, mv_update, tmmult,
+                  tmmult_tuned)
 
 
 class DeviceProblem:
@@ -60,6 +61,10 @@ class DeviceProblem:
     def overlap(self, stream=None, X=None, Y=None) -> None:
         tmmult(self.layout, self.X if X is None else X, self.Y if Y is None else Y, self.S,
                self.trace, self.work, stream)
+
+    def overlap_tuned(self, unit_steps: int = 0, long_steps: int = 0, stream=None) -> None:
+        tmmult_tuned(self.layout, self.X, self.Y, self.S, self.trace, self.work, unit_steps,
+                     long_steps, stream)
 
     def overlap_into(self, S, trace, X=None, Y=None, stream=None) -> None:
         tmmult(self.layout, self.X if X is None else X, self.Y if Y is None else Y, S, trace,

@@ -372,3 +372,38 @@ def test_high_degree(degree):
         with pytest.raises(MfbError) as e:
             dp.apply_tuned(0, kernel=kernel)
         assert e.value.code == N.MFB_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("degree", [2, 4])
+def test_overlap_shapes(degree):
+    """mfb_tmmult_tuned: every row-step shape of the two block-product classes
+    gives the oracle's S and trace (generic values and ragged column blocks, so
+    that 8x8 products, narrower ones and wider ones all occur), and a shape the
+    library does not have is refused."""
+    import torch
+    import paper_1907_01005_amd._native as N
+    from paper_1907_01005_amd import MfbError
+    wl = _small((8, 6, 4), degree, 29, 2.2, 11, sizes=[8, 5, 12, 4])
+    say(f"overlap shapes Q{degree}")
+    op = OracleProblem(wl, values="generic", value_seed=3)
+    dp = device_problem(wl)
+    dp.set_X_coo(op.node, op.orb, op.val)
+    node, orb = dp.layout.entry_coords()
+    _, So, tro = oracle_full(op, node, orb)
+    dp.apply(0)
+    for u in (4, 8, 16):
+        for lng in (4, 8, 16):
+            dp.S.fill_(7.25)
+            dp.trace.fill_(7.25)
+            dp.overlap_tuned(u, lng)
+            torch.cuda.synchronize()
+            tag = f"{wl.name} overlap steps {u}/{lng}"
+            gate(dp.S_original_order(), So, TOL64, tag + " S")
+            tr = float(dp.trace.cpu()[0])
+            et = abs(tr - tro) / max(abs(tro), 1e-300)
+            say(f"{tag} trace rel {et:.2e}")
+            assert et <= TOL64
+    for bad in ((5, 4), (4, 32)):
+        with pytest.raises(MfbError) as e:
+            dp.overlap_tuned(*bad)
+        assert e.value.code == N.MFB_EINVAL
