@@ -339,7 +339,7 @@ int mfb_mv_zero(const mfb_mv* mv, double* d_Y, void* stream);
  * (fp64 and fp32) and at p = 5, 6.  At p = 5, 6 only kernels 0 and 9 (both that kernel) are
  * available.
  * grid: for kernels 0 and 2, the shell items checked per wave (a power of
- * two up to 64; 0 = 2); for the persistent kernels, the
+ * two up to 64; 0 = 4 at p <= 2, else 2); for the persistent kernels, the
  * number of workgroups (0 = as many as fit on the device); else unused.  d_work: the workspace (info.work_bytes);
  * it holds the queue counters, so two tuned applies sharing a workspace must
  * not overlap in time.                                                      */

@@ -80,10 +80,10 @@ def candidates(cu_count: int, curved: bool = False, degree: int = 2,
     if degree >= 5:
         return [(0, 0)]  # one kernel (a workgroup per cell) at p = 5, 6
     if curved:
-        out = [(0, spw) for spw in (0, 1, 4, 8)] + [(2, 0), (7, 0)]
+        out = [(0, spw) for spw in (1, 2, 4, 8)] + [(2, 0), (7, 0)]
         assert all(k in CURVED_KERNELS for k, _ in out)
         return out
-    out = [(0, spw) for spw in (0, 1, 4, 8)] + [(4, 0)]
+    out = [(0, spw) for spw in (1, 2, 4, 8)] + [(4, 0)]
     for per_cu in (0, 1, 2, 3):
         out.append((6, per_cu * cu_count))
     for per_cu in (0, 2, 3):
