@@ -539,13 +539,12 @@ def default_apply_kernel(dp, degree: int, prec_name: str) -> str:
     library's rule: at p >= 3 the line kernel in fp64 and fp32 on the vector
     ALUs (the only kernel at p = 5, 6); fp32 at p = 2, the fused grid; fp64 at
     p = 2, the fused grid below 64 own items per CU, else the loader pipeline;
-    the fp32 matrix-core form, the loader pipeline at p = 2 and the
-    shared-stage pipeline at p = 3, 4 while X's byte offsets fit 31 bits; the
-    fp64 matrix-core form, the fused grid)."""
+    the matrix-core forms, the loader pipeline at p = 2 and the shared-stage
+    pipeline at p = 3, 4 while X's byte offsets fit 31 bits)."""
     import torch
     if degree >= 5 or (degree >= 3 and prec_name in ("fp64", "fp32")):
         return "apply_line_kernel"
-    if prec_name in ("fp32", "fp64-mfma"):
+    if prec_name == "fp32":
         return "apply_fused_kernel"
     if degree == 2:
         cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count

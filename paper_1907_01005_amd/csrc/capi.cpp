@@ -606,14 +606,15 @@ static void apply_H_impl(const mfb_mesh* mesh, const mfb_mv* mv, const double* d
   if (prec < 0 || prec > 3) fail(MFB_EINVAL, "unknown precision");
   mfb::gpu::ApplyParams a;
   fill_apply_params(mesh, mv, d_X, d_Y, a);
-  // the library's choice (-1) for the fp64 and fp32-MFMA forms: at p = 2 the
+  // the library's choice (-1) for the fp64 and matrix-core forms: at p = 2 the
   // loader pipeline, or the fused grid when there are few items per CU (fp64);
   // at p >= 3 on box cells the line kernel (fp64) or the shared-stage pipeline
-  // (fp32-MFMA); the fused grid on curved cells.  The fp32 VALU form: the
-  // line kernel (9) at p >= 3 on box cells (60 against 73 us for the fused
-  // grid on the 32x20x20 box at p = 4), else the fused grid (0), which the
-  // fp64-MFMA form always takes.
-  int kernel = (prec == MFB_FP64 || prec == MFB_FP32_MFMA) ? -1 : 0;
+  // (matrix cores: 97.6 against 109.0 us for fp64-MFMA with the fused grid on
+  // the 64x40x40 box at p = 2, 159 against 186 on the 32x20x20 box at p = 4);
+  // the fused grid on curved cells.  The fp32 VALU form: the line kernel (9)
+  // at p >= 3 on box cells (60 against 73 us for the fused grid at p = 4),
+  // else the fused grid (0).
+  int kernel = prec == MFB_FP32 ? 0 : -1;
   if (prec == MFB_FP32 && mesh->plan.p >= 3 && !mesh->plan.curved) kernel = 9;
   const int rc = mfb::gpu::launch_apply(a, mesh->plan.p, prec, kernel, mv->plan.block_offset.back(),
                                         stream, fill);
